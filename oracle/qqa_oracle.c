@@ -1,0 +1,387 @@
+/*
+ * qqa_oracle.c -- plain FP64 CPU reference for the Parallel Quasi-Quantum Annealing
+ * (PQQA) replica update.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg load this library; the solver library never links, calls or
+ * includes anything from here, and this file includes nothing from the solver.
+ *
+ * Single-threaded, double precision, no blocking, fusion or reordering: each function
+ * spells out one definition of the paper in the paper's order and notation.
+ *
+ *   S replicas of N relaxed variables, P[i*S + s] = p_i^(s) in [0, 1], row-major with
+ *   the replica index contiguous.  Graph: symmetric CSR (row_ptr[n+1] int64,
+ *   col[nnz] int32, optional weight[nnz]) or a dense symmetric n x n matrix.
+ *
+ * Noise and initial values come from a counter-based generator, Philox4x32-10
+ * (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11),
+ * implemented here from that publication.  Stream layout (shared by contract, not by
+ * code, with the device implementation):
+ *     key     = (seed mod 2^32, seed div 2^32)
+ *     counter = (row i, replica quad q, step k, stream)    stream 0 = init, 1 = noise
+ *     uniform = ((r >> 8) | 1) * 2^-24                     odd multiples of 2^-24 in (0,1)
+ *     normals = Box-Muller (1958) on (u0,u1) and (u2,u3): 4 normals per call
+ *
+ * Parity status (tests/test_oracle_*.py pin each function against something other
+ * than itself):
+ *   orc_eval        exact: brute force over every x of small graphs, textbook optima
+ *   orc_energy      exact at binary points (equals the discrete objective), closed
+ *                   forms at P = 1/2 and for the STD maximiser (appendix proposition)
+ *   orc_grad        central finite differences of orc_energy, row sums of the STD term
+ *   orc_step        AdamW first-step closed form, projected-gradient fixed point of a
+ *                   regular graph (closed-form root), Langevin noise moments
+ *   orc_philox*     parity unpinned against the published known-answer vectors (not
+ *                   available here); pinned by bijectivity and by uniform/normal
+ *                   goodness-of-fit statistics only
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- problem / step-rule codes ----------------------------------------------------- */
+enum { ORC_MIS = 0, ORC_MAXCUT = 1 };
+enum { ORC_ADAMW = 0, ORC_LANGEVIN = 1 };
+enum { ORC_STREAM_INIT = 0, ORC_STREAM_NOISE = 1 };
+
+typedef struct {
+    double gamma_min, gamma_max; /* entropy coefficient, linear schedule (Implementation; App. Annealing Schedule) */
+    double lr;                   /* eta, step size (Eq. 11; App. Configuration of Optimizer) */
+    double weight_decay;         /* AdamW decoupled decay */
+    double temperature;          /* T in sqrt(2 eta T) xi (Eq. 11) */
+    double comm_alpha;           /* alpha of the STD communication term (Eq. 10) */
+    int32_t entropy_alpha;       /* alpha of the alpha-entropy (Eq. 7), even */
+    int32_t rule;                /* ORC_ADAMW or ORC_LANGEVIN */
+    double beta1, beta2, adam_eps;
+    double lambda;               /* MIS penalty coefficient */
+    int32_t problem;             /* ORC_MIS or ORC_MAXCUT */
+    int32_t pad_;
+} orc_params;
+
+typedef struct {
+    int32_t n;
+    int32_t dense;          /* 1: W is n*n row-major, CSR fields unused */
+    const int64_t *row_ptr; /* n+1 */
+    const int32_t *col;     /* nnz */
+    const double *weight;   /* nnz or NULL (all ones) */
+    const double *W;        /* n*n when dense */
+} orc_graph;
+
+/* ---- Philox4x32-10 ------------------------------------------------------------------ */
+static const uint32_t PHILOX_M0 = 0xD2511F53u, PHILOX_M1 = 0xCD9E8D57u; /* round multipliers */
+static const uint32_t PHILOX_W0 = 0x9E3779B9u, PHILOX_W1 = 0xBB67AE85u; /* key schedule increments */
+
+/* One Philox4x32 round: two 32x32->64 multiplies act as S-boxes, the key is xor-ed
+   into the high halves and the words are permuted. */
+static void philox_round(uint32_t c[4], const uint32_t k[2]) {
+    uint64_t p0 = (uint64_t)PHILOX_M0 * c[0];
+    uint64_t p1 = (uint64_t)PHILOX_M1 * c[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t o0 = hi1 ^ c[1] ^ k[0];
+    uint32_t o2 = hi0 ^ c[3] ^ k[1];
+    c[0] = o0; c[1] = lo1; c[2] = o2; c[3] = lo0;
+}
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k[0] += PHILOX_W0; k[1] += PHILOX_W1; }
+        philox_round(c, k);
+    }
+    memcpy(out, c, sizeof c);
+}
+
+/* Inverse of the 10-round map, used by the tests to show the map is a bijection. */
+void orc_philox4x32_10_inverse(const uint32_t out[4], const uint32_t key[2], uint32_t ctr[4]) {
+    uint32_t ks[10][2];
+    ks[0][0] = key[0]; ks[0][1] = key[1];
+    for (int r = 1; r < 10; ++r) { ks[r][0] = ks[r-1][0] + PHILOX_W0; ks[r][1] = ks[r-1][1] + PHILOX_W1; }
+    uint32_t c[4] = {out[0], out[1], out[2], out[3]};
+    for (int r = 9; r >= 0; --r) {
+        /* forward: c' = (hi1^c1^k0, lo1, hi0^c3^k1, lo0) with (hi0,lo0)=M0*c0, (hi1,lo1)=M1*c2.
+           lo0 and lo1 determine c0 and c2 because the multipliers are odd. */
+        uint32_t lo1 = c[1], lo0 = c[3];
+        /* modular inverse of an odd 32-bit multiplier by Newton iteration */
+        uint32_t inv0 = PHILOX_M0, inv1 = PHILOX_M1;
+        for (int it = 0; it < 5; ++it) { inv0 *= 2u - PHILOX_M0 * inv0; inv1 *= 2u - PHILOX_M1 * inv1; }
+        uint32_t c0 = lo0 * inv0, c2 = lo1 * inv1;
+        uint32_t hi0 = (uint32_t)(((uint64_t)PHILOX_M0 * c0) >> 32);
+        uint32_t hi1 = (uint32_t)(((uint64_t)PHILOX_M1 * c2) >> 32);
+        uint32_t c1 = c[0] ^ hi1 ^ ks[r][0];
+        uint32_t c3 = c[2] ^ hi0 ^ ks[r][1];
+        c[0] = c0; c[1] = c1; c[2] = c2; c[3] = c3;
+    }
+    memcpy(ctr, c, sizeof c);
+}
+
+static void philox_seeded(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t out[4]) {
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* 24-bit uniform on (0,1): odd multiples of 2^-24, exactly representable in binary32. */
+double orc_u01(uint32_t r) { return (double)((r >> 8) | 1u) * (1.0 / 16777216.0); }
+
+/* Box-Muller: (u0,u1) -> (R cos t, R sin t), R = sqrt(-2 ln u0), t = 2 pi u1; same for (u2,u3). */
+void orc_normals4(const uint32_t r[4], double xi[4]) {
+    const double two_pi = 6.283185307179586476925286766559;
+    double ua = orc_u01(r[0]), ub = orc_u01(r[1]), uc = orc_u01(r[2]), ud = orc_u01(r[3]);
+    double R1 = sqrt(-2.0 * log(ua)), R2 = sqrt(-2.0 * log(uc));
+    xi[0] = R1 * cos(two_pi * ub);
+    xi[1] = R1 * sin(two_pi * ub);
+    xi[2] = R2 * cos(two_pi * ud);
+    xi[3] = R2 * sin(two_pi * ud);
+}
+
+/* Raw integers of the stream for rows [0,n), quads [0,nquads): out[(i*nquads + q)*4 + j]. */
+void orc_philox_grid(uint64_t seed, int32_t n, int32_t nquads, uint32_t k, uint32_t stream, uint32_t *out) {
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t q = 0; q < nquads; ++q)
+            philox_seeded(seed, (uint32_t)i, (uint32_t)q, k, stream, out + ((size_t)i * nquads + q) * 4);
+}
+
+/* Gaussian noise xi (n x S) of step k: replica s takes normal (s mod 4) of quad s/4. */
+void orc_noise(uint64_t seed, int32_t n, int32_t S, uint32_t k, double *xi) {
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t q = 0; 4 * q < S; ++q) {
+            uint32_t r[4]; double z[4];
+            philox_seeded(seed, (uint32_t)i, (uint32_t)q, k, ORC_STREAM_NOISE, r);
+            orc_normals4(r, z);
+            for (int j = 0; j < 4 && 4 * q + j < S; ++j) xi[(size_t)i * S + 4 * q + j] = z[j];
+        }
+}
+
+/* Initial relaxed variables: p ~ U(0,1) per replica (the paper does not fix the start). */
+void orc_init(uint64_t seed, int32_t n, int32_t S, double *P) {
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t q = 0; 4 * q < S; ++q) {
+            uint32_t r[4];
+            philox_seeded(seed, (uint32_t)i, (uint32_t)q, 0u, ORC_STREAM_INIT, r);
+            for (int j = 0; j < 4 && 4 * q + j < S; ++j) P[(size_t)i * S + 4 * q + j] = orc_u01(r[j]);
+        }
+}
+
+/* ---- schedule ------------------------------------------------------------------------ */
+/* gamma increases linearly from gamma_min (first update) to gamma_max (last update). */
+double orc_gamma(const orc_params *pr, int32_t t, int32_t K) {
+    if (K <= 1) return pr->gamma_min;
+    return pr->gamma_min + (pr->gamma_max - pr->gamma_min) * (double)t / (double)(K - 1);
+}
+
+static double ipow(double x, int e) {
+    double r = 1.0;
+    for (int i = 0; i < e; ++i) r *= x;
+    return r;
+}
+
+static double edge_weight(const orc_graph *g, int64_t e) { return g->weight ? g->weight[e] : 1.0; }
+
+/* ---- energy (for finite differences and closed-form pins) ----------------------------- */
+/* Relaxed objective l^(p) of one replica (continuous relaxation of the penalised loss,
+   energies of the appendix "Energy Function of Benchmark Problems"):
+     MIS:    -sum_i p_i + lambda * p^T A p / 2          (c = 1)
+     MaxCut: -sum_{(i,j) in E} A_ij (1 - (2p_i - 1)(2p_j - 1)) / 2                    */
+static double relaxed_objective(const orc_params *pr, const orc_graph *g, int32_t S, const double *P, int32_t s) {
+    const int32_t n = g->n;
+    double l = 0.0;
+    if (pr->problem == ORC_MIS) {
+        double quad = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            double pi = P[(size_t)i * S + s];
+            l -= pi;
+            if (g->dense) {
+                for (int32_t j = 0; j < n; ++j) quad += pi * g->W[(size_t)i * n + j] * P[(size_t)j * S + s];
+            } else {
+                for (int64_t e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e)
+                    quad += pi * edge_weight(g, e) * P[(size_t)g->col[e] * S + s];
+            }
+        }
+        l += pr->lambda * quad / 2.0;
+    } else {
+        for (int32_t i = 0; i < n; ++i) {
+            double zi = 2.0 * P[(size_t)i * S + s] - 1.0;
+            if (g->dense) {
+                for (int32_t j = i + 1; j < n; ++j) {
+                    double zj = 2.0 * P[(size_t)j * S + s] - 1.0;
+                    l -= g->W[(size_t)i * n + j] * (1.0 - zi * zj) / 2.0;
+                }
+            } else {
+                for (int64_t e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e) {
+                    int32_t j = g->col[e];
+                    if (j <= i) continue; /* each undirected edge once */
+                    double zj = 2.0 * P[(size_t)j * S + s] - 1.0;
+                    l -= edge_weight(g, e) * (1.0 - zi * zj) / 2.0;
+                }
+            }
+        }
+    }
+    return l;
+}
+
+/* alpha-entropy s(p) = sum_i {1 - (2 p_i - 1)^alpha}   (Eq. 7) */
+static double alpha_entropy(int alpha, int32_t n, int32_t S, const double *P, int32_t s) {
+    double acc = 0.0;
+    for (int32_t i = 0; i < n; ++i) acc += 1.0 - ipow(2.0 * P[(size_t)i * S + s] - 1.0, alpha);
+    return acc;
+}
+
+/* empirical (population) standard deviation over the S replicas of variable i (Eq. 10) */
+static double replica_std(int32_t S, const double *row) {
+    double mu = 0.0;
+    for (int32_t s = 0; s < S; ++s) mu += row[s];
+    mu /= (double)S;
+    double var = 0.0;
+    for (int32_t s = 0; s < S; ++s) var += (row[s] - mu) * (row[s] - mu);
+    return sqrt(var / (double)S);
+}
+
+/* R^ = sum_s [ l^(p^(s)) + gamma s(p^(s)) ] - S alpha_c sum_i STD_s[p_i^(s)]   (Eqs. 6, 10) */
+double orc_energy(const orc_params *pr, const orc_graph *g, int32_t S, const double *P, double gamma) {
+    double R = 0.0;
+    for (int32_t s = 0; s < S; ++s)
+        R += relaxed_objective(pr, g, S, P, s) + gamma * alpha_entropy(pr->entropy_alpha, g->n, S, P, s);
+    double stdsum = 0.0;
+    for (int32_t i = 0; i < g->n; ++i) stdsum += replica_std(S, P + (size_t)i * S);
+    return R - (double)S * pr->comm_alpha * stdsum;
+}
+
+/* ---- gradient of R^ with respect to P -------------------------------------------------- */
+/* gf: gradient of the relaxed objective
+         MIS     -1 + lambda * sum_j A_ij p_j
+         MaxCut  sum_j A_ij (2 p_j - 1)
+   ge: gradient of gamma s(p): -2 alpha gamma (2p - 1)^(alpha - 1)
+   gc: gradient of -S alpha_c STD_i: -alpha_c (p - mu_i) / sigma_i, taken as 0 when sigma_i = 0
+   sigma (optional, n): sigma_i                                                            */
+void orc_grad(const orc_params *pr, const orc_graph *g, int32_t S, const double *P, double gamma,
+              double *gf, double *ge, double *gc, double *sigma) {
+    const int32_t n = g->n;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t s = 0; s < S; ++s) {
+            double c = 0.0;
+            if (g->dense) {
+                for (int32_t j = 0; j < n; ++j) {
+                    double pj = P[(size_t)j * S + s];
+                    c += g->W[(size_t)i * n + j] * (pr->problem == ORC_MIS ? pj : 2.0 * pj - 1.0);
+                }
+            } else {
+                for (int64_t e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e) {
+                    double pj = P[(size_t)g->col[e] * S + s];
+                    c += edge_weight(g, e) * (pr->problem == ORC_MIS ? pj : 2.0 * pj - 1.0);
+                }
+            }
+            gf[(size_t)i * S + s] = pr->problem == ORC_MIS ? -1.0 + pr->lambda * c : c;
+            double z = 2.0 * P[(size_t)i * S + s] - 1.0;
+            ge[(size_t)i * S + s] = -2.0 * (double)pr->entropy_alpha * gamma * ipow(z, pr->entropy_alpha - 1);
+        }
+        const double *row = P + (size_t)i * S;
+        double mu = 0.0;
+        for (int32_t s = 0; s < S; ++s) mu += row[s];
+        mu /= (double)S;
+        double sd = replica_std(S, row);
+        if (sigma) sigma[i] = sd;
+        for (int32_t s = 0; s < S; ++s)
+            gc[(size_t)i * S + s] = sd > 0.0 ? -pr->comm_alpha * (row[s] - mu) / sd : 0.0;
+    }
+}
+
+/* ---- one update (Sensitive Transitions, Eq. 11, with AdamW in place of the plain step) ---
+   t is the 0-based update index (AdamW step count k = t + 1), K the schedule length.
+   Optional diagnostics (n*S): pre_clamp = value before the clamp, gsum = g,
+   gabs = |gf| + |ge| + |gc|;  sigma (n).                                                   */
+void orc_step(const orc_params *pr, const orc_graph *g, int32_t S, int32_t t, int32_t K, uint64_t seed,
+              const double *P_in, double *P_out, double *m, double *v,
+              double *pre_clamp, double *gsum, double *gabs, double *sigma) {
+    const int32_t n = g->n;
+    const size_t NS = (size_t)n * S;
+    const double gamma = orc_gamma(pr, t, K);
+    const uint32_t k = (uint32_t)t + 1u;
+    double *gf = (double *)malloc(NS * sizeof(double));
+    double *ge = (double *)malloc(NS * sizeof(double));
+    double *gc = (double *)malloc(NS * sizeof(double));
+    double *xi = (double *)malloc(NS * sizeof(double));
+    orc_grad(pr, g, S, P_in, gamma, gf, ge, gc, sigma);
+    orc_noise(seed, n, S, k, xi);
+    const double bc1 = 1.0 - pow(pr->beta1, (double)k);
+    const double bc2 = 1.0 - pow(pr->beta2, (double)k);
+    const double noise_scale = sqrt(2.0 * pr->lr * pr->temperature);
+    for (size_t e = 0; e < NS; ++e) {
+        double grad = gf[e] + ge[e] + gc[e];
+        double p = P_in[e];
+        if (pr->rule == ORC_ADAMW) {
+            /* AdamW (Loshchilov & Hutter): decoupled decay, moment updates, bias correction */
+            p = p - pr->lr * pr->weight_decay * p;
+            m[e] = pr->beta1 * m[e] + (1.0 - pr->beta1) * grad;
+            v[e] = pr->beta2 * v[e] + (1.0 - pr->beta2) * grad * grad;
+            double mhat = m[e] / bc1, vhat = v[e] / bc2;
+            p = p - pr->lr * mhat / (sqrt(vhat) + pr->adam_eps);
+        } else {
+            p = p - pr->lr * grad; /* plain gradient step of Eq. 11 */
+        }
+        p = p + noise_scale * xi[e]; /* sqrt(2 eta T) xi */
+        if (pre_clamp) pre_clamp[e] = p;
+        if (gsum) gsum[e] = grad;
+        if (gabs) gabs[e] = fabs(gf[e]) + fabs(ge[e]) + fabs(gc[e]);
+        P_out[e] = p < 0.0 ? 0.0 : (p > 1.0 ? 1.0 : p); /* sigma = Clamp to [0,1] */
+    }
+    free(gf); free(ge); free(gc); free(xi);
+}
+
+/* Updates t0 .. t1-1 of a K-update schedule applied in place to (P, m, v). */
+void orc_run(const orc_params *pr, const orc_graph *g, int32_t S, int32_t t0, int32_t t1, int32_t K,
+             uint64_t seed, double *P, double *m, double *v) {
+    const size_t NS = (size_t)g->n * S;
+    double *tmp = (double *)malloc(NS * sizeof(double));
+    for (int32_t t = t0; t < t1; ++t) {
+        orc_step(pr, g, S, t, K, seed, P, tmp, m, v, NULL, NULL, NULL, NULL);
+        memcpy(P, tmp, NS * sizeof(double));
+    }
+    free(tmp);
+}
+
+/* ---- rounding and exact evaluation ------------------------------------------------------
+   x_i = Theta(p_i - 1/2) with Theta(0) = 0, i.e. x = [p > 1/2].
+   MIS:    size = sum_i x_i, viol = #{(i,j) in E : x_i = x_j = 1}, l = -size + lambda*viol
+   MaxCut: cut  = sum_{(i,j) in E} w_ij [x_i != x_j] counted in units of 2^-16, l = -cut
+   Integer arithmetic throughout; weights must be integer multiples of 2^-16.
+   best = replica minimising (viol > 0, l, s) lexicographically.  Returns 0, or -1 if a
+   weight is off the 2^-16 grid.                                                          */
+int orc_eval(int32_t problem, int64_t lambda, const orc_graph *g, int32_t S, const double *P,
+             int64_t *size_or_cut, int64_t *viol, int64_t *obj, int32_t *best) {
+    const int32_t n = g->n;
+    for (int32_t s = 0; s < S; ++s) {
+        int64_t a = 0, b = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            int xi = P[(size_t)i * S + s] > 0.5;
+            if (problem == ORC_MIS) a += xi;
+            int32_t deg = g->dense ? n : (int32_t)(g->row_ptr[i + 1] - g->row_ptr[i]);
+            for (int32_t u = 0; u < deg; ++u) {
+                int32_t j; double w;
+                if (g->dense) { j = u; w = g->W[(size_t)i * n + j]; }
+                else { int64_t e = g->row_ptr[i] + u; j = g->col[e]; w = edge_weight(g, e); }
+                if (j <= i || w == 0.0) continue;
+                int xj = P[(size_t)j * S + s] > 0.5;
+                if (problem == ORC_MIS) {
+                    b += (xi && xj);
+                } else {
+                    double qd = w * 65536.0;
+                    int64_t q = (int64_t)llround(qd);
+                    if ((double)q != qd) return -1;
+                    if (xi != xj) a += q;
+                }
+            }
+        }
+        size_or_cut[s] = a;
+        viol[s] = problem == ORC_MIS ? b : 0;
+        obj[s] = problem == ORC_MIS ? -a + lambda * b : -a;
+    }
+    int32_t bi = 0;
+    for (int32_t s = 1; s < S; ++s) {
+        int fs = viol[s] > 0, fb = viol[bi] > 0;
+        if (fs < fb || (fs == fb && obj[s] < obj[bi])) bi = s;
+    }
+    *best = bi;
+    return 0;
+}

@@ -1,0 +1,84 @@
+"""Pins of the oracle's counter-based generator (Philox4x32-10) and its transforms.
+
+Conformance of the integer stream to the published known-answer vectors is parity
+unpinned (the vectors are not available here).  What is pinned: the map is a bijection
+of the counter space for each key, it diffuses single-bit changes, its uniforms and
+Box-Muller normals pass goodness-of-fit tests, and the uniforms are exact binary32."""
+
+import numpy as np
+import pytest
+from scipy import stats
+
+
+def test_bijection_roundtrip(orc):
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        c = rng.integers(0, 2 ** 32, size=4, dtype=np.uint64).astype(np.uint32)
+        k = rng.integers(0, 2 ** 32, size=2, dtype=np.uint64).astype(np.uint32)
+        out = orc.philox(c, k)
+        np.testing.assert_array_equal(orc.philox_inverse(out, k), c)
+
+
+def test_avalanche(orc):
+    rng = np.random.default_rng(1)
+    flips = []
+    for _ in range(300):
+        c = rng.integers(0, 2 ** 32, size=4, dtype=np.uint64).astype(np.uint32)
+        k = rng.integers(0, 2 ** 32, size=2, dtype=np.uint64).astype(np.uint32)
+        base = orc.philox(c, k)
+        word, bit = int(rng.integers(4)), int(rng.integers(32))
+        c2 = c.copy()
+        c2[word] ^= np.uint32(1 << bit)
+        diff = orc.philox(c2, k) ^ base
+        flips.append(sum(bin(int(x)).count("1") for x in diff))
+    assert abs(np.mean(flips) - 64) < 2.0
+
+
+def test_uniforms_exact_and_uniform(orc):
+    r = orc.philox_grid(99, 4096, 64, 3, 1).ravel()
+    u = ((r >> 8) | 1).astype(np.float64) / 2.0 ** 24
+    assert np.all(u.astype(np.float32).astype(np.float64) == u)
+    assert u.min() > 0 and u.max() < 1
+    assert orc.u01(0) == 2.0 ** -24 and orc.u01(0xFFFFFFFF) == 1 - 2.0 ** -24
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+    # counts of the top byte are flat
+    chi = stats.chisquare(np.bincount(r >> 24, minlength=256))
+    assert chi.pvalue > 1e-4
+
+
+def test_box_muller_normals(orc):
+    xi = orc.noise(5, 8192, 128, 17).ravel()
+    assert abs(xi.mean()) < 5e-3
+    assert abs(xi.var() - 1.0) < 5e-3
+    assert stats.kstest(xi, "norm").pvalue > 1e-3
+    # the four normals of one call are uncorrelated
+    q = xi.reshape(-1, 4)
+    cc = np.corrcoef(q.T)
+    assert np.max(np.abs(cc - np.eye(4))) < 0.01
+
+
+def test_streams_and_steps_are_distinct(orc):
+    a = orc.philox_grid(7, 64, 4, 0, 0)
+    b = orc.philox_grid(7, 64, 4, 0, 1)
+    c = orc.philox_grid(7, 64, 4, 1, 1)
+    d = orc.philox_grid(8, 64, 4, 1, 1)
+    for x, y in [(a, b), (b, c), (c, d)]:
+        assert np.mean(x == y) < 0.01
+
+
+def test_init_is_exact_binary32_uniform(orc):
+    P = orc.init(3, 1000, 30)
+    assert np.all(P.astype(np.float32).astype(np.float64) == P)
+    assert 0 < P.min() and P.max() < 1
+    assert stats.kstest(P.ravel(), "uniform").pvalue > 1e-3
+    # a replica count that is not a multiple of 4 takes the leading normals of the last quad
+    P2 = orc.init(3, 1000, 32)
+    np.testing.assert_array_equal(P2[:, :30], P)
+
+
+def test_noise_layout_matches_grid(orc):
+    r = orc.philox_grid(11, 5, 3, 4, 1)
+    xi = orc.noise(11, 5, 12, 4)
+    for i in range(5):
+        for q in range(3):
+            np.testing.assert_allclose(xi[i, 4 * q:4 * q + 4], orc.normals4(r[i, q]), rtol=0, atol=0)
