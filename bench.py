@@ -1,0 +1,165 @@
+"""Benchmark: replica-variable updates per second of whole PQQA solves on one MI355X.
+
+One benchmark step is one complete solve through the C ABI (U(0,1) init, every update
+of the schedule, rounding and exact evaluation) of the workload below, with the graph
+already resident in HBM.  Prints one JSON line.
+
+Default workload (the sparse single-instance configuration): maximum independent set
+on an Erdos-Renyi graph, n = 20,000, mean degree 5 (seeded G(n, p)), S = 256 replicas,
+3,000 updates, float32 state, AdamW + alpha-entropy annealing + STD communication.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "replica-var updates/s (N·S·steps/s); p50/p99 solve latency, batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (family, n, degree parameter, problem, S, updates)
+    "mis_er_n20000_d5_S256_K3000": ("er", 20000, 5.0, "mis", 256, 3000),
+    "maxcut_ba_n100000_m4_pm1_S128_K3000": ("ba", 100000, 4, "maxcut", 128, 3000),
+    "mis_rrg_n256_d3_S16_K2000": ("rrg", 256, 3, "mis", 16, 2000),
+}
+DEFAULT = "mis_er_n20000_d5_S256_K3000"
+
+
+def make_graph(family, n, d, problem, seed=0):
+    import qqa_inputs as qi
+    if family == "er":
+        g = qi.erdos_renyi(n, d, seed)
+    elif family == "ba":
+        g = qi.barabasi_albert(n, int(d), seed)
+    else:
+        g = qi.random_regular(n, int(d), seed)
+    if problem == "maxcut":
+        g = qi.pm1_weights(g, seed + 1)
+    return g
+
+
+def algorithmic_bytes_per_update_launch(n, nnz, S, stride, weighted):
+    """Bytes one update launch must move: the replica state (read P_t, write P_{t+1}, read
+    and write m and v: 24 B per replica-variable) plus one pass over the CSR (row_ptr,
+    col, weights).  Neighbour-row re-reads are not algorithmic: caches serve them."""
+    state = 24 * n * S
+    csr = 4 * (n + 1) + 4 * nnz + (4 * nnz if weighted else 0)
+    return state + csr
+
+
+def traffic_from_profiles(kernel_src_hash):
+    """Measured HBM bytes per launch of the update kernel, from the committed rocprofv3
+    counter summary, if it was taken with the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_src_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(g, problem, S, K, updates=20):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload: the first
+    `updates` updates of the schedule from the same start, one thread."""
+    import oracle
+    pr = oracle.Params(problem=0 if problem == "mis" else 1,
+                       gamma_min=-2.0 if problem == "mis" else (-20.0 if g["n"] >= 1000 else -5.0)).as_float32()
+    P = oracle.init(0, g["n"], S)
+    z = np.zeros_like(P)
+    t0 = time.perf_counter()
+    oracle.run(pr, g, 0, updates, K, 0, P, z, z)
+    dt = time.perf_counter() - t0
+    return {"value": g["n"] * S * updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{updates} of {K} updates of the same instance from the same start, single-threaded FP64 C",
+            "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is "
+              "a design in DESIGN.md, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2409_02135_amd as q
+
+    family, n, d, problem, S, K = WORKLOADS[args.workload]
+    g = make_graph(family, n, d, problem)
+    nnz = int(g["col"].size)
+    ctx = q.Context(0)
+    gid = ctx.upload(g, problem)
+    print(f"# workload {args.workload}: n={n} nnz={nnz} S={S} updates={K}", file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        ctx.poll(ctx.solve_resident(gid, n, problem, S, K, 1000 + w), want_x=False)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ids = [ctx.solve_resident(gid, n, problem, S, K, s) for s in range(args.steps)]
+    results = [ctx.poll(i, want_x=False) for i in ids]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    updates = n * S * K * args.steps
+    value = updates / elapsed
+    dev_ms = np.array([r["device_ms"] for r in results])
+    loop_ms = np.array([r["step_loop_ms"] for r in results])
+    step_us = float(np.mean(loop_ms)) * 1e3 / K  # average duration of one update launch
+    stride = q.qqa_replica_stride(S)
+    abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
+    achieved = abytes / (step_us * 1e-6) / 1e9
+    src = open(os.path.join(ROOT, "paper_2409_02135_amd", "csrc", "qqa_kernels.hip"), "rb").read()
+    traffic = traffic_from_profiles(hashlib.sha256(src).hexdigest())
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "problem": problem, "graph": family, "n": n, "nnz": nnz,
+                   "degree_param": d, "S": S, "updates_per_solve": K, "graph_seed": 0,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": float(np.percentile(dev_ms, 50)), "p99": float(np.percentile(dev_ms, 99)),
+                       "basis": "device time per solve (events on the solver stream)"},
+        "roofline": {"bound": "hbm", "kernel": "step_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes},
+        "quality": {"best_objective_mean": float(np.mean([r["best_objective"] for r in results])),
+                    "feasible_all": bool(all(r["feasible"] for r in results))},
+    }
+    ctx.release(gid)
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, problem, S, K)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

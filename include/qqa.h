@@ -1,0 +1,218 @@
+/*
+ * qqa.h -- C ABI of libqqa, an MI355X (gfx950) solver for Parallel Quasi-Quantum
+ * Annealing (PQQA, arXiv 2409.02135).
+ *
+ * The solver runs S coupled replicas of relaxed binary variables P in [0,1]^{N x S}
+ * through K updates of
+ *     g  = grad l^(P) + gamma_t grad s(P) + grad(-S alpha_c sum_i STD_s P_i)
+ *     P <- Clamp(step(P, g) + sqrt(2 eta T) xi)
+ * and finally rounds x = [P > 1/2] and evaluates each replica exactly in integers:
+ *   * relaxed objectives l^: the MIS and max-cut energies of the appendix section
+ *     "Energy Function of Benchmark Problems";
+ *   * alpha-entropy s(p) = sum_i 1 - (2 p_i - 1)^alpha: Eq. 7, annealed with gamma_t
+ *     rising linearly from gamma_min to gamma_max (Sec. 4 "Implementation", appendix
+ *     "Annealing Schedule");
+ *   * replica communication: the STD term of Eq. 10;
+ *   * update: the sensitive-transition step on p of Eq. 11 with AdamW in place of
+ *     the plain step (Sec. 3.4), or the plain step itself; Clamp to [0,1] (Sec. 4);
+ *   * rounding x_i = Theta(p_i - 1/2) (Sec. 4), with Theta(0) = 0.
+ *
+ * Conventions for every function:
+ *   * Return value: QQA_OK (0), QQA_PENDING (1) or a negative QQA_E_* code.  Nothing
+ *     aborts or throws across this ABI; qqa_last_error() describes the last failure
+ *     of a context (the qqa_dev_* functions report through qqa_dev_last_error()).
+ *   * Layout of replica state: row-major N x stride float32, replica index contiguous,
+ *     stride = qqa_replica_stride(S) = S rounded up to a multiple of 4.  Columns
+ *     S..stride-1 are padding: written as 0, never read as replicas.
+ *   * "host" pointers are ordinary CPU memory; "device" pointers are HIP device memory
+ *     (for example from torch.empty(..., device="cuda")).
+ *   * `stream` arguments are hipStream_t passed as void*; NULL is the null stream.
+ *     qqa_dev_* calls are asynchronous on that stream.
+ */
+#ifndef QQA_H
+#define QQA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QQA_OK 0
+#define QQA_PENDING 1
+#define QQA_E_ARG (-1)         /* bad argument: NULL, S <= 0, steps <= 0, odd alpha, gamma_min > gamma_max, ... */
+#define QQA_E_GRAPH (-2)       /* invalid graph: asymmetric, self-loop, duplicate, index out of range, weight off grid */
+#define QQA_E_NOMEM (-3)       /* device memory exhausted */
+#define QQA_E_ADMISSION (-4)   /* request footprint exceeds the context's HBM budget even when idle */
+#define QQA_E_DEVICE (-5)      /* HIP runtime error */
+#define QQA_E_UNKNOWN_REQ (-6) /* unknown or already collected request handle */
+#define QQA_E_CANCELLED (-7)   /* request was cancelled */
+
+typedef enum { QQA_MIS = 0, QQA_MAXCUT = 1 } qqa_problem;
+typedef enum { QQA_STEP_ADAMW = 0, QQA_STEP_LANGEVIN = 1 } qqa_step_rule;
+
+/* Hyper-parameters of one solve.  qqa_schedule_default() fills the paper's values:
+ * gamma -2 -> 0.1 (max-cut: gamma_min -20 for N >= 1000, else -5; appendix "Annealing
+ * Schedule"), alpha = 4 (Sec. 4), weight decay 0.01 and T = 0.001 (appendix
+ * "Configuration of Optimizer"), MIS lambda = 2 (appendix MIS energy), and the choices
+ * the paper leaves open: lr 0.1 (from its set {1, 0.1, 0.01}), comm_alpha 0.1,
+ * Adam betas 0.9 / 0.999, eps 1e-8. */
+typedef struct {
+    float gamma_min, gamma_max;  /* entropy coefficient schedule, linear in the update index */
+    float lr;                    /* eta */
+    float weight_decay;          /* AdamW decoupled weight decay */
+    float temperature;           /* T of the sqrt(2 eta T) xi noise */
+    float comm_alpha;            /* alpha of the STD communication term, in [0, 1] */
+    int32_t entropy_alpha;       /* alpha-entropy exponent: even, >= 2 */
+    float beta1, beta2, adam_eps;
+    int32_t penalty_lambda;      /* MIS constraint penalty (integer, so objectives stay exact) */
+    int32_t rule;                /* qqa_step_rule */
+} qqa_schedule;
+
+void qqa_schedule_default(qqa_schedule *s, qqa_problem problem, int32_t n);
+
+/* Replica-row stride (floats) used for an S-replica state: S rounded up to 4. */
+int32_t qqa_replica_stride(int32_t S);
+
+/* ---------------------------------------------------------------------------------
+ * Request-level API.  One context per device and host thread; it owns every device
+ * buffer it allocates.
+ * --------------------------------------------------------------------------------- */
+typedef struct qqa_ctx qqa_ctx;
+typedef int64_t qqa_req;
+typedef int64_t qqa_graph_id;
+
+/* Undirected graph in host memory.  Sparse: symmetric CSR (row_ptr[n+1], col_idx[nnz]),
+ * no self-loops, no duplicate entries; weight[nnz] or NULL (all ones).  Dense: `dense`
+ * is an n x n row-major symmetric matrix with zero diagonal and row_ptr/col_idx are
+ * ignored.  Max-cut weights must be integer multiples of 2^-16 with |w| < 128 (so
+ * cut values are exact integers in units of 2^-16); MIS ignores weights (A is the
+ * 0/1 adjacency).  The library copies the graph; the caller may free it on return. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    const float *weight;
+    const float *dense;
+} qqa_graph;
+
+/* Check a host graph against the rules above for `problem` without a context and without
+ * touching the device.  Returns QQA_OK or QQA_E_GRAPH; a message for the failure is
+ * written to `why` (may be NULL, else at least `why_len` bytes). */
+int qqa_graph_validate(const qqa_graph *g, qqa_problem problem, char *why, size_t why_len);
+
+/* Result of a finished request.  The caller owns the optional arrays (NULL = not
+ * wanted) and qqa_poll fills them when it returns QQA_OK.
+ * Objectives are exact integers: MIS l = -size + lambda * violations; max-cut
+ * l = -cut with cut counted in units of 2^-16.  best_replica minimises
+ * (violations > 0, l, replica index) lexicographically. */
+typedef struct {
+    int32_t best_replica;
+    int32_t feasible;            /* best replica has no violated constraint */
+    int64_t best_objective;
+    int64_t best_size_or_cut;    /* MIS set size, or cut in units of 2^-16 */
+    int64_t best_violations;     /* MIS edges with both ends selected; 0 for max-cut */
+    int64_t *replica_objective;  /* [S] or NULL */
+    int64_t *replica_size_or_cut;/* [S] or NULL */
+    int64_t *replica_violations; /* [S] or NULL */
+    uint8_t *best_x;             /* [n] or NULL: rounded solution of best_replica */
+    double queue_ms;             /* submit -> start on device (host clock) */
+    double device_ms;            /* device time from first to last kernel of the request */
+    double step_loop_ms;         /* device time of the K-update loop */
+    double latency_ms;           /* submit -> result ready (host clock) */
+} qqa_result;
+
+/* device: HIP ordinal.  hbm_budget_bytes: cap on the device memory the context may
+ * hold for requests (0 = 90% of free memory at creation).  hip_stream: stream to run
+ * on (NULL = the context creates its own). */
+int qqa_create(qqa_ctx **out, int device, size_t hbm_budget_bytes, void *hip_stream);
+void qqa_destroy(qqa_ctx *c);
+const char *qqa_last_error(const qqa_ctx *c);
+
+/* Validate a host graph and copy it into device memory once; solves that name the id
+ * read it in place.  Release with qqa_graph_release once no request uses it. */
+int qqa_graph_upload(qqa_ctx *c, const qqa_graph *g, qqa_problem problem, qqa_graph_id *out);
+int qqa_graph_release(qqa_ctx *c, qqa_graph_id id);
+
+/* Submit one solve (asynchronous): init P ~ U(0,1) from `seed`, `steps` updates,
+ * rounding and exact evaluation.  qqa_solve copies the host graph; qqa_solve_resident
+ * uses an uploaded one.  `sched` NULL = qqa_schedule_default. */
+int qqa_solve(qqa_ctx *c, const qqa_graph *g, qqa_problem problem, const qqa_schedule *sched,
+              int32_t S, int32_t steps, uint64_t seed, qqa_req *out_id);
+int qqa_solve_resident(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, const qqa_schedule *sched,
+                       int32_t S, int32_t steps, uint64_t seed, qqa_req *out_id);
+
+/* Submit `count` independent solves packed into one ragged batch: every update of the
+ * batch is a single launch covering all instances (each at its own update index), the
+ * update loop is replayed from a captured HIP graph.  Instances never interact: each
+ * result equals that of the same solve submitted alone.  Graph ids come from
+ * qqa_graph_upload.  Arrays have `count` entries; sched may be NULL (defaults). */
+int qqa_solve_batch(qqa_ctx *c, int32_t count, const qqa_graph_id *graphs, const qqa_problem *problems,
+                    const qqa_schedule *sched, const int32_t *S, const int32_t *steps,
+                    const uint64_t *seeds, qqa_req *out_ids);
+
+/* Wait up to timeout_us (0 = do not wait, < 0 = forever) for a request.  Returns QQA_OK
+ * and fills *out when done (the handle is then released), QQA_PENDING if still
+ * running, or an error. */
+int qqa_poll(qqa_ctx *c, qqa_req id, qqa_result *out, int32_t timeout_us);
+int qqa_cancel(qqa_ctx *c, qqa_req id);
+
+/* ---------------------------------------------------------------------------------
+ * Continuous-batching server.  Requests submitted with qqa_serve_submit are admitted
+ * into device-resident slots while their HBM footprint fits the budget and a slot is
+ * free; every device iteration advances all admitted slots by one update (each at its
+ * own update index) in one launch per replica-width class, so requests that arrive
+ * while others run overlap on the device.  Finished slots are rounded, evaluated and
+ * released, and waiting requests are admitted, between iterations.  Results are
+ * identical to the same solve run alone.  Collect with qqa_poll.
+ * --------------------------------------------------------------------------------- */
+int qqa_serve_start(qqa_ctx *c, int32_t max_slots);
+int qqa_serve_submit(qqa_ctx *c, const qqa_graph *g, qqa_problem problem, const qqa_schedule *sched,
+                     int32_t S, int32_t steps, uint64_t seed, qqa_req *out_id);
+int qqa_serve_stop(qqa_ctx *c);  /* drains admitted and queued requests, then stops */
+
+/* ---------------------------------------------------------------------------------
+ * Device-level entry points: one stage of the path on caller-owned device buffers,
+ * asynchronous on `stream`.  They exist so that each stage can be checked on its own.
+ * --------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *row_ptr;  /* device, n+1 (sparse) */
+    const int32_t *col_idx;  /* device, nnz (sparse) */
+    const float *weight;     /* device, nnz or NULL */
+    const float *dense;      /* device, n x n row-major, or NULL for sparse */
+} qqa_dev_graph;
+
+const char *qqa_dev_last_error(void);
+
+/* Raw Philox4x32-10 integers (SC'11 generator) for rows [0,n) and quads [0,nquads):
+ * out[(i*nquads + q)*4 + j] = word j of Philox(key = seed, counter = (i, q, k, stream_id)). */
+int qqa_dev_philox(uint64_t seed, int32_t n, int32_t nquads, uint32_t k, uint32_t stream_id,
+                   uint32_t *out, void *stream);
+
+/* Gaussian noise of update k (Box-Muller on 24-bit uniforms): xi[i*stride + s]. */
+int qqa_dev_noise(uint64_t seed, int32_t n, int32_t S, uint32_t k, float *xi, void *stream);
+
+/* Initial state: P[i*stride + s] ~ U(0,1) from `seed`; m = v = 0 (m, v may be NULL). */
+int qqa_dev_init(uint64_t seed, int32_t n, int32_t S, float *P, float *m, float *v, void *stream);
+
+/* One update t (0-based, AdamW step count t+1) of a K-update schedule:
+ * reads P_in, writes P_out (must not alias P_in: neighbours read P_in), updates m, v in
+ * place.  Sparse or dense coupling per `g`. */
+int qqa_dev_step(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule *sched, int32_t S,
+                 int32_t t, int32_t K, uint64_t seed, const float *P_in, float *P_out, float *m,
+                 float *v, void *stream);
+
+/* Round x = [P > 1/2] and evaluate every replica exactly.  Outputs are device arrays:
+ * size_or_cut[S], viol[S], obj[S] (int64) and best[1] (int32). */
+int qqa_dev_eval(const qqa_dev_graph *g, qqa_problem problem, int32_t penalty_lambda, int32_t S,
+                 const float *P, int64_t *size_or_cut, int64_t *viol, int64_t *obj, int32_t *best,
+                 void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QQA_H */

@@ -1,0 +1,324 @@
+"""Python binding of libqqa (include/qqa.h): argument marshalling only.
+
+Every stage of the solver runs in the HIP library; this module converts Python values
+and torch device tensors into the C ABI's plain pointers and sizes.  torch provides
+device memory and streams.  The library must be built (``__graft_entry__.build()``):
+importing the binding without it raises, there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # loaded first so that libqqa binds to the HIP runtime torch already uses
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqqa.so")
+
+QQA_OK, QQA_PENDING = 0, 1
+QQA_E_ARG, QQA_E_GRAPH, QQA_E_NOMEM, QQA_E_ADMISSION = -1, -2, -3, -4
+QQA_E_DEVICE, QQA_E_UNKNOWN_REQ, QQA_E_CANCELLED = -5, -6, -7
+QQA_MIS, QQA_MAXCUT = 0, 1
+QQA_STEP_ADAMW, QQA_STEP_LANGEVIN = 0, 1
+
+PROBLEMS = {"mis": QQA_MIS, "maxcut": QQA_MAXCUT, QQA_MIS: QQA_MIS, QQA_MAXCUT: QQA_MAXCUT}
+
+
+class QQAError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"qqa error {code}: {msg}")
+        self.code = code
+
+
+class qqa_schedule(C.Structure):
+    _fields_ = [("gamma_min", C.c_float), ("gamma_max", C.c_float), ("lr", C.c_float),
+                ("weight_decay", C.c_float), ("temperature", C.c_float), ("comm_alpha", C.c_float),
+                ("entropy_alpha", C.c_int32), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("adam_eps", C.c_float), ("penalty_lambda", C.c_int32), ("rule", C.c_int32)]
+
+
+class qqa_graph(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("weight", C.c_void_p), ("dense", C.c_void_p)]
+
+
+class qqa_result(C.Structure):
+    _fields_ = [("best_replica", C.c_int32), ("feasible", C.c_int32), ("best_objective", C.c_int64),
+                ("best_size_or_cut", C.c_int64), ("best_violations", C.c_int64),
+                ("replica_objective", C.c_void_p), ("replica_size_or_cut", C.c_void_p),
+                ("replica_violations", C.c_void_p), ("best_x", C.c_void_p), ("queue_ms", C.c_double),
+                ("device_ms", C.c_double), ("step_loop_ms", C.c_double), ("latency_ms", C.c_double)]
+
+
+class qqa_dev_graph(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("weight", C.c_void_p), ("dense", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libqqa.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u32, u64, i64, sz = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_int64, C.c_size_t
+        sig = {
+            "qqa_schedule_default": (None, [vp, i32, i32]),
+            "qqa_replica_stride": (i32, [i32]),
+            "qqa_create": (C.c_int, [vp, C.c_int, sz, vp]),
+            "qqa_destroy": (None, [vp]),
+            "qqa_last_error": (C.c_char_p, [vp]),
+            "qqa_graph_validate": (C.c_int, [vp, i32, vp, sz]),
+            "qqa_graph_upload": (C.c_int, [vp, vp, i32, vp]),
+            "qqa_graph_release": (C.c_int, [vp, i64]),
+            "qqa_solve": (C.c_int, [vp, vp, i32, vp, i32, i32, u64, vp]),
+            "qqa_solve_resident": (C.c_int, [vp, i64, i32, vp, i32, i32, u64, vp]),
+            "qqa_solve_batch": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp]),
+            "qqa_poll": (C.c_int, [vp, i64, vp, i32]),
+            "qqa_cancel": (C.c_int, [vp, i64]),
+            "qqa_serve_start": (C.c_int, [vp, i32]),
+            "qqa_serve_submit": (C.c_int, [vp, vp, i32, vp, i32, i32, u64, vp]),
+            "qqa_serve_stop": (C.c_int, [vp]),
+            "qqa_dev_last_error": (C.c_char_p, []),
+            "qqa_dev_philox": (C.c_int, [u64, i32, i32, u32, u32, vp, vp]),
+            "qqa_dev_noise": (C.c_int, [u64, i32, i32, u32, vp, vp]),
+            "qqa_dev_init": (C.c_int, [u64, i32, i32, vp, vp, vp, vp]),
+            "qqa_dev_step": (C.c_int, [vp, i32, vp, i32, i32, i32, u64, vp, vp, vp, vp, vp]),
+            "qqa_dev_eval": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return C.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(t)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev_check(rc: int):
+    if rc < 0:
+        raise QQAError(rc, lib().qqa_dev_last_error().decode())
+    return rc
+
+
+# ---- schedule ---------------------------------------------------------------------------
+
+def qqa_schedule_default(problem, n: int) -> qqa_schedule:
+    s = qqa_schedule()
+    lib().qqa_schedule_default(C.byref(s), PROBLEMS[problem], n)
+    return s
+
+
+def schedule(problem, n: int, **overrides) -> qqa_schedule:
+    """Default schedule with named fields replaced."""
+    s = qqa_schedule_default(problem, n)
+    for k, v in overrides.items():
+        if k == "rule" and isinstance(v, str):
+            v = {"adamw": QQA_STEP_ADAMW, "langevin": QQA_STEP_LANGEVIN}[v]
+        setattr(s, k, v)
+    return s
+
+
+def qqa_replica_stride(S: int) -> int:
+    return lib().qqa_replica_stride(S)
+
+
+# ---- device-level stages ---------------------------------------------------------------------
+
+class DevGraph:
+    """Device copy of a CSR graph dict (qqa_inputs format) as int32 CSR + float32 weights,
+    or of a dense matrix; `.struct` is the qqa_dev_graph the library reads."""
+
+    def __init__(self, g: dict | None = None, dense: np.ndarray | None = None, device="cuda"):
+        if dense is not None:
+            self.dense = torch.as_tensor(np.ascontiguousarray(dense, np.float32), device=device)
+            self.n = int(dense.shape[0])
+            self.row_ptr = self.col = self.weight = None
+            self.struct = qqa_dev_graph(self.n, 0, None, None, None, _ptr(self.dense))
+            return
+        self.n = int(g["n"])
+        self.row_ptr = torch.as_tensor(np.asarray(g["row_ptr"], np.int32), device=device)
+        self.col = torch.as_tensor(np.asarray(g["col"], np.int32), device=device)
+        w = g.get("weight")
+        self.weight = None if w is None else torch.as_tensor(np.asarray(w, np.float32), device=device)
+        self.dense = None
+        self.struct = qqa_dev_graph(self.n, int(self.col.numel()), _ptr(self.row_ptr), _ptr(self.col),
+                                    _ptr(self.weight), None)
+
+
+def qqa_dev_philox(seed, n, nquads, k, stream_id, out, stream=None):
+    return _dev_check(lib().qqa_dev_philox(seed, n, nquads, k, stream_id, _ptr(out), _stream(stream)))
+
+
+def qqa_dev_noise(seed, n, S, k, xi, stream=None):
+    return _dev_check(lib().qqa_dev_noise(seed, n, S, k, _ptr(xi), _stream(stream)))
+
+
+def qqa_dev_init(seed, n, S, P, m=None, v=None, stream=None):
+    return _dev_check(lib().qqa_dev_init(seed, n, S, _ptr(P), _ptr(m), _ptr(v), _stream(stream)))
+
+
+def qqa_dev_step(g: DevGraph, problem, sched: qqa_schedule | None, S, t, K, seed, P_in, P_out, m, v, stream=None):
+    return _dev_check(lib().qqa_dev_step(C.byref(g.struct), PROBLEMS[problem], None if sched is None else C.byref(sched),
+                                         S, t, K, seed, _ptr(P_in), _ptr(P_out), _ptr(m), _ptr(v), _stream(stream)))
+
+
+def qqa_dev_eval(g: DevGraph, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best, stream=None):
+    return _dev_check(lib().qqa_dev_eval(C.byref(g.struct), PROBLEMS[problem], penalty_lambda, S, _ptr(P),
+                                         _ptr(size_or_cut), _ptr(viol), _ptr(obj), _ptr(best), _stream(stream)))
+
+
+# ---- request-level API ------------------------------------------------------------------------
+
+def host_graph(g: dict | None = None, dense: np.ndarray | None = None):
+    """qqa_graph over host arrays; returns (struct, keepalive)."""
+    if dense is not None:
+        d = np.ascontiguousarray(dense, np.float32)
+        return qqa_graph(d.shape[0], 0, None, None, None, _ptr(d)), (d,)
+    rp = np.ascontiguousarray(g["row_ptr"], np.int64)
+    col = np.ascontiguousarray(g["col"], np.int32)
+    w = g.get("weight")
+    w = None if w is None else np.ascontiguousarray(w, np.float32)
+    return qqa_graph(int(g["n"]), int(col.size), _ptr(rp), _ptr(col), _ptr(w), None), (rp, col, w)
+
+
+def qqa_graph_validate(g: dict | None = None, problem="mis", dense: np.ndarray | None = None):
+    """(return code, message) of the library's host-side graph check."""
+    st, keep = host_graph(g, dense)
+    buf = C.create_string_buffer(256)
+    rc = lib().qqa_graph_validate(C.byref(st), PROBLEMS[problem], buf, 256)
+    return rc, buf.value.decode()
+
+
+class Result(dict):
+    pass
+
+
+class Context:
+    """One qqa_ctx (device context with its own stream unless one is given)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, stream=None):
+        self._c = C.c_void_p()
+        s = None if stream is None else _stream(stream)
+        rc = lib().qqa_create(C.byref(self._c), device, hbm_budget, s)
+        if rc != QQA_OK:
+            raise QQAError(rc, "qqa_create failed")
+        self._pending = {}
+
+    def _check(self, rc):
+        if rc < 0:
+            raise QQAError(rc, lib().qqa_last_error(self._c).decode())
+        return rc
+
+    def close(self):
+        if self._c:
+            lib().qqa_destroy(self._c)
+            self._c = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload(self, g: dict | None = None, problem="mis", dense: np.ndarray | None = None) -> int:
+        st, keep = host_graph(g, dense)
+        gid = C.c_int64()
+        self._check(lib().qqa_graph_upload(self._c, C.byref(st), PROBLEMS[problem], C.byref(gid)))
+        return gid.value
+
+    def release(self, gid: int):
+        self._check(lib().qqa_graph_release(self._c, gid))
+
+    def _track(self, rid, n, S):
+        self._pending[rid] = (n, S)
+        return rid
+
+    def solve(self, g: dict | None, problem, S, steps, seed, sched=None, dense=None) -> int:
+        st, keep = host_graph(g, dense)
+        rid = C.c_int64()
+        self._check(lib().qqa_solve(self._c, C.byref(st), PROBLEMS[problem],
+                                    None if sched is None else C.byref(sched), S, steps, seed, C.byref(rid)))
+        return self._track(rid.value, st.n, S)
+
+    def solve_resident(self, gid: int, n: int, problem, S, steps, seed, sched=None) -> int:
+        rid = C.c_int64()
+        self._check(lib().qqa_solve_resident(self._c, gid, PROBLEMS[problem], None if sched is None else C.byref(sched),
+                                             S, steps, seed, C.byref(rid)))
+        return self._track(rid.value, n, S)
+
+    def solve_batch(self, gids, ns, problems, S, steps, seeds, sched=None) -> list[int]:
+        cnt = len(gids)
+        g = np.asarray(gids, np.int64)
+        pr = np.asarray([PROBLEMS[p] for p in problems], np.int32)
+        Ss = np.asarray(S, np.int32)
+        ks = np.asarray(steps, np.int32)
+        sd = np.asarray(seeds, np.uint64)
+        out = np.zeros(cnt, np.int64)
+        sch = None
+        if sched is not None:
+            sch = (qqa_schedule * cnt)(*sched)
+        self._check(lib().qqa_solve_batch(self._c, cnt, _ptr(g), _ptr(pr), sch, _ptr(Ss), _ptr(ks), _ptr(sd),
+                                          _ptr(out)))
+        return [self._track(int(r), int(n), int(s)) for r, n, s in zip(out, ns, Ss)]
+
+    def serve_start(self, max_slots: int = 256):
+        self._check(lib().qqa_serve_start(self._c, max_slots))
+
+    def serve_submit(self, g: dict | None, problem, S, steps, seed, sched=None, dense=None) -> int:
+        st, keep = host_graph(g, dense)
+        rid = C.c_int64()
+        self._check(lib().qqa_serve_submit(self._c, C.byref(st), PROBLEMS[problem],
+                                           None if sched is None else C.byref(sched), S, steps, seed, C.byref(rid)))
+        return self._track(rid.value, st.n, S)
+
+    def serve_stop(self):
+        self._check(lib().qqa_serve_stop(self._c))
+
+    def cancel(self, rid: int):
+        self._check(lib().qqa_cancel(self._c, rid))
+
+    def poll(self, rid: int, timeout_us: int = -1, want_x: bool = True) -> Result | None:
+        """Result dict when done, None while pending; raises on errors."""
+        n, S = self._pending[rid]
+        objs = np.zeros(S, np.int64)
+        size = np.zeros(S, np.int64)
+        viol = np.zeros(S, np.int64)
+        x = np.zeros(n, np.uint8) if want_x else None
+        res = qqa_result()
+        res.replica_objective = objs.ctypes.data
+        res.replica_size_or_cut = size.ctypes.data
+        res.replica_violations = viol.ctypes.data
+        res.best_x = None if x is None else x.ctypes.data
+        rc = lib().qqa_poll(self._c, rid, C.byref(res), timeout_us)
+        if rc == QQA_PENDING:
+            return None
+        self._pending.pop(rid, None)
+        self._check(rc)
+        return Result(best_replica=res.best_replica, feasible=bool(res.feasible), best_objective=res.best_objective,
+                      best_size_or_cut=res.best_size_or_cut, best_violations=res.best_violations, obj=objs,
+                      size_or_cut=size, viol=viol, best_x=x, queue_ms=res.queue_ms, device_ms=res.device_ms,
+                      step_loop_ms=res.step_loop_ms, latency_ms=res.latency_ms)

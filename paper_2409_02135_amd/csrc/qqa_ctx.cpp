@@ -1,0 +1,419 @@
+// Request-level API of include/qqa.h: contexts, resident graphs, plain solves, polling.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "qqa.h"
+#include "qqa_ctx.h"
+#include "qqa_internal.h"
+#include "qqa_runtime.h"
+
+using namespace qqa;
+using Clock = std::chrono::steady_clock;
+
+namespace qqa {
+
+size_t request_footprint(int n, int S, int rule) {
+  const size_t stride = (size_t)replica_shape(S).stride;
+  const size_t state = (size_t)n * stride * sizeof(float) * (rule == QQA_STEP_ADAMW ? 4 : 2);
+  return state + out_bytes(n, S) + 2 * stride * sizeof(unsigned long long) + 4096;
+}
+
+size_t out_bytes(int n, int S) { return 3 * (size_t)S * sizeof(int64_t) + 8 + (size_t)n; }
+
+void out_views(char* base, int n, int S, int64_t** a, int64_t** b, int64_t** o, int32_t** best, uint8_t** x) {
+  *a = reinterpret_cast<int64_t*>(base);
+  *b = *a + S;
+  *o = *b + S;
+  *best = reinterpret_cast<int32_t*>(*o + S);
+  *x = reinterpret_cast<uint8_t*>(base + 3 * (size_t)S * sizeof(int64_t) + 8);
+  (void)n;
+}
+
+int upload_graph(qqa_ctx* c, const qqa_graph& g, int problem, DevGraph* out, std::string* why) {
+  int rc = validate_graph(g, problem, why);
+  if (rc) return rc;
+  DevGraph d;
+  d.n = g.n;
+  d.problem = problem;
+  auto dev_copy = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(dst, bytes ? bytes : 4);
+    if (e != hipSuccess) return e;
+    d.bytes += bytes;
+    return bytes ? hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, c->stream) : hipSuccess;
+  };
+  hipError_t e = hipSuccess;
+  if (g.dense) {
+    d.nnz = (int64_t)g.n * g.n;
+    e = dev_copy((void**)&d.dense, g.dense, (size_t)g.n * g.n * sizeof(float));
+  } else {
+    d.nnz = g.nnz;
+    std::vector<int32_t> rp(g.n + 1);
+    for (int i = 0; i <= g.n; ++i) rp[i] = (int32_t)g.row_ptr[i];
+    e = dev_copy((void**)&d.row_ptr, rp.data(), rp.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = dev_copy((void**)&d.col, g.col_idx, (size_t)g.nnz * sizeof(int32_t));
+    if (e == hipSuccess && problem == QQA_MAXCUT && g.weight)
+      e = dev_copy((void**)&d.w, g.weight, (size_t)g.nnz * sizeof(float));
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host arrays may go away on return
+  }
+  if (e == hipSuccess && g.dense) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    free_graph(d);
+    return fail(why, e == hipErrorOutOfMemory ? QQA_E_NOMEM : QQA_E_DEVICE,
+                std::string("graph upload: ") + hipGetErrorString(e));
+  }
+  *out = d;
+  return QQA_OK;
+}
+
+void free_graph(DevGraph& d) {
+  if (d.row_ptr) (void)hipFree(d.row_ptr);
+  if (d.col) (void)hipFree(d.col);
+  if (d.w) (void)hipFree(d.w);
+  if (d.dense) (void)hipFree(d.dense);
+  d = DevGraph{};
+}
+
+void graph_unref(qqa_ctx* c, int64_t gid) {
+  auto it = c->graphs.find(gid);
+  if (it == c->graphs.end()) return;
+  if (--it->second.refs <= 0 && it->second.release_pending) {
+    c->in_use -= it->second.bytes;
+    free_graph(it->second);
+    c->graphs.erase(it);
+  }
+}
+
+int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why) {
+  const size_t state = (size_t)r->n * r->shape.stride * sizeof(float);
+  const bool adam = r->sched.rule == QQA_STEP_ADAMW;
+  hipError_t e = hipSuccess;
+  auto get = [&](void** p, size_t b) {
+    if (e == hipSuccess) e = c->dpool.get(b, p);
+  };
+  get((void**)&r->P[0], state);
+  get((void**)&r->P[1], state);
+  if (adam) {
+    get((void**)&r->m, state);
+    get((void**)&r->v, state);
+  }
+  get((void**)&r->acc, 2 * (size_t)r->shape.stride * sizeof(unsigned long long));
+  r->out_size = out_bytes(r->n, r->S);
+  get((void**)&r->out_dev, r->out_size);
+  if (e == hipSuccess) e = c->hpool.get(r->out_size, (void**)&r->out_host);
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&r->ev[i]);
+  if (e != hipSuccess) {
+    release_request_buffers(c, r);
+    return fail(why, e == hipErrorOutOfMemory ? QQA_E_NOMEM : QQA_E_DEVICE,
+                std::string("request buffers: ") + hipGetErrorString(e));
+  }
+  return QQA_OK;
+}
+
+void release_request_buffers(qqa_ctx* c, Request* r) {
+  const size_t state = (size_t)r->n * r->shape.stride * sizeof(float);
+  c->dpool.put(r->P[0], state);
+  c->dpool.put(r->P[1], state);
+  c->dpool.put(r->m, state);
+  c->dpool.put(r->v, state);
+  c->dpool.put(r->acc, 2 * (size_t)r->shape.stride * sizeof(unsigned long long));
+  c->dpool.put(r->out_dev, r->out_size);
+  c->hpool.put(r->out_host, r->out_size);
+  r->P[0] = r->P[1] = r->m = r->v = nullptr;
+  r->acc = nullptr;
+  r->out_dev = r->out_host = nullptr;
+  for (int i = 0; i < 4; ++i)
+    if (r->ev[i]) {
+      (void)hipEventDestroy(r->ev[i]);
+      r->ev[i] = nullptr;
+    }
+}
+
+StepParams request_step_params(const Request* r, const DevGraph& g) {
+  StepParams p{};
+  p.row_ptr = g.row_ptr;
+  p.col = g.col;
+  p.w = r->problem == QQA_MAXCUT ? g.w : nullptr;
+  p.coupling = nullptr;
+  p.m = r->m;
+  p.v = r->v;
+  p.n = r->n;
+  fill_static_scalars(p, r->sched, r->problem, r->S, r->seed);
+  return p;
+}
+
+// Enqueue rounding, exact evaluation, best-x extraction and the copy of the result
+// record into pinned host memory; `final_P` is the state after the last update.
+hipError_t enqueue_finish(qqa_ctx* c, Request* r, const DevGraph& g, const float* final_P) {
+  int64_t *a, *b, *o;
+  int32_t* best;
+  uint8_t* x;
+  out_views(r->out_dev, r->n, r->S, &a, &b, &o, &best, &x);
+  EvalParams ep{};
+  ep.row_ptr = g.row_ptr;
+  ep.col = g.col;
+  ep.w = r->problem == QQA_MAXCUT ? g.w : nullptr;
+  ep.dense = g.dense;
+  ep.P = final_P;
+  ep.n = r->n;
+  ep.S = r->S;
+  ep.stride = r->shape.stride;
+  ep.problem = r->problem;
+  ep.lambda = r->sched.penalty_lambda;
+  ep.acc = r->acc;
+  ep.size_or_cut = a;
+  ep.viol = b;
+  ep.obj = o;
+  ep.best = best;
+  hipError_t e = launch_eval(ep, c->stream);
+  if (e == hipSuccess) e = launch_extract(final_P, r->n, r->shape.stride, best, x, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(r->out_host, r->out_dev, r->out_size, hipMemcpyDeviceToHost, c->stream);
+  return e;
+}
+
+int set_err(qqa_ctx* c, int code, const std::string& msg) {
+  c->err = msg;
+  return code;
+}
+
+}  // namespace qqa
+
+// ---------------------------------------------------------------------------------------
+// plain solve: init, K update launches, finish -- all enqueued on the context stream
+// ---------------------------------------------------------------------------------------
+static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem, const qqa_schedule* sched, int32_t S,
+                        int32_t steps, uint64_t seed, qqa_req* out_id) {
+  auto git = c->graphs.find(gid);
+  if (git == c->graphs.end()) return set_err(c, QQA_E_ARG, "unknown graph id");
+  DevGraph& g = git->second;
+  if (g.problem != problem) return set_err(c, QQA_E_ARG, "graph was uploaded for another problem type");
+  if (g.dense) return set_err(c, QQA_E_ARG, "dense coupling graphs are not supported by this solve path");
+  auto r = std::make_unique<Request>();
+  r->id = c->next_req++;
+  r->graph = gid;
+  r->temp_graph = temp;
+  r->problem = problem;
+  if (sched) r->sched = *sched; else qqa_schedule_default(&r->sched, problem, g.n);
+  std::string why;
+  if (!schedule_valid(r->sched, &why)) return set_err(c, QQA_E_ARG, why);
+  r->S = S;
+  r->K = steps;
+  r->seed = seed;
+  r->n = g.n;
+  r->shape = replica_shape(S);
+  r->footprint = request_footprint(g.n, S, r->sched.rule);
+  if (r->footprint + g.bytes > c->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the HBM budget");
+  if (c->in_use + r->footprint > c->budget)
+    return set_err(c, QQA_E_NOMEM, "HBM budget held by earlier requests; poll them first");
+  int rc = alloc_request_buffers(c, r.get(), &c->err);
+  if (rc) return rc;
+  c->in_use += r->footprint;
+  g.refs++;
+  r->t_submit = Clock::now();
+
+  hipError_t e = hipEventRecord(r->ev[0], c->stream);
+  if (e == hipSuccess) e = launch_init(seed, g.n, S, r->P[0], r->m, r->v, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(r->ev[1], c->stream);
+  StepParams p = request_step_params(r.get(), g);
+  for (int t = 0; t < steps && e == hipSuccess; ++t) {
+    p.P_in = r->P[t & 1];
+    p.P_out = r->P[(t + 1) & 1];
+    fill_step_scalars(p, r->sched, t, steps);
+    e = launch_step(p, c->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(r->ev[2], c->stream);
+  if (e == hipSuccess) e = enqueue_finish(c, r.get(), g, r->P[steps & 1]);
+  if (e == hipSuccess) e = hipEventRecord(r->ev[3], c->stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(c->stream);
+    release_request_buffers(c, r.get());
+    c->in_use -= r->footprint;
+    graph_unref(c, gid);
+    return set_err(c, QQA_E_DEVICE, std::string("enqueue: ") + hipGetErrorString(e));
+  }
+  r->state = Request::kRunning;
+  *out_id = r->id;
+  c->reqs.emplace(r->id, std::move(r));
+  return QQA_OK;
+}
+
+extern "C" {
+
+int qqa_create(qqa_ctx** out, int device, size_t hbm_budget_bytes, void* hip_stream) {
+  if (!out) return QQA_E_ARG;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return QQA_E_DEVICE;
+  auto c = std::make_unique<qqa_ctx>();
+  c->device = device;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+    c->own_stream = false;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return QQA_E_DEVICE;
+    c->own_stream = true;
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return QQA_E_DEVICE;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+  *out = c.release();
+  return QQA_OK;
+}
+
+void qqa_destroy(qqa_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  qqa_serve_stop(c);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->reqs) release_request_buffers(c, kv.second.get());
+  c->reqs.clear();
+  for (auto& kv : c->graphs) free_graph(kv.second);
+  c->graphs.clear();
+  c->dpool.trim();
+  c->hpool.trim();
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* qqa_last_error(const qqa_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+int qqa_graph_upload(qqa_ctx* c, const qqa_graph* g, qqa_problem problem, qqa_graph_id* out) {
+  if (!c || !g || !out) return c ? set_err(c, QQA_E_ARG, "NULL argument") : QQA_E_ARG;
+  if (problem != QQA_MIS && problem != QQA_MAXCUT) return set_err(c, QQA_E_ARG, "unknown problem");
+  (void)hipSetDevice(c->device);
+  DevGraph d;
+  int rc = upload_graph(c, *g, problem, &d, &c->err);
+  if (rc) return rc;
+  c->in_use += d.bytes;
+  const int64_t id = c->next_graph++;
+  c->graphs.emplace(id, d);
+  *out = id;
+  return QQA_OK;
+}
+
+int qqa_graph_release(qqa_ctx* c, qqa_graph_id id) {
+  if (!c) return QQA_E_ARG;
+  auto it = c->graphs.find(id);
+  if (it == c->graphs.end() || it->second.release_pending) return set_err(c, QQA_E_ARG, "unknown graph id");
+  it->second.release_pending = true;
+  if (it->second.refs == 0) {
+    c->in_use -= it->second.bytes;
+    free_graph(it->second);
+    c->graphs.erase(it);
+  }
+  return QQA_OK;
+}
+
+static int check_solve_args(qqa_ctx* c, qqa_problem problem, int32_t S, int32_t steps, qqa_req* out_id) {
+  if (!out_id) return set_err(c, QQA_E_ARG, "out_id is NULL");
+  if (problem != QQA_MIS && problem != QQA_MAXCUT) return set_err(c, QQA_E_ARG, "unknown problem");
+  if (S <= 0 || S > kMaxReplicas) return set_err(c, QQA_E_ARG, "S must be in [1, 4096]");
+  if (steps <= 0) return set_err(c, QQA_E_ARG, "steps must be positive");
+  return QQA_OK;
+}
+
+int qqa_solve(qqa_ctx* c, const qqa_graph* g, qqa_problem problem, const qqa_schedule* sched, int32_t S, int32_t steps,
+              uint64_t seed, qqa_req* out_id) {
+  if (!c) return QQA_E_ARG;
+  if (!g) return set_err(c, QQA_E_ARG, "graph is NULL");
+  int rc = check_solve_args(c, problem, S, steps, out_id);
+  if (rc) return rc;
+  qqa_graph_id gid;
+  rc = qqa_graph_upload(c, g, problem, &gid);
+  if (rc) return rc;
+  rc = submit_plain(c, gid, true, problem, sched, S, steps, seed, out_id);
+  qqa_graph_release(c, gid);  // freed when the request is collected
+  return rc;
+}
+
+int qqa_solve_resident(qqa_ctx* c, qqa_graph_id g, qqa_problem problem, const qqa_schedule* sched, int32_t S,
+                       int32_t steps, uint64_t seed, qqa_req* out_id) {
+  if (!c) return QQA_E_ARG;
+  int rc = check_solve_args(c, problem, S, steps, out_id);
+  if (rc) return rc;
+  (void)hipSetDevice(c->device);
+  return submit_plain(c, g, false, problem, sched, S, steps, seed, out_id);
+}
+
+int qqa_poll(qqa_ctx* c, qqa_req id, qqa_result* out, int32_t timeout_us) {
+  if (!c) return QQA_E_ARG;
+  (void)hipSetDevice(c->device);
+  if (c->server) {
+    int rc = serve_poll(c, id, out, timeout_us);
+    if (rc != QQA_E_UNKNOWN_REQ) return rc;
+  }
+  auto it = c->reqs.find(id);
+  if (it == c->reqs.end()) return set_err(c, QQA_E_UNKNOWN_REQ, "unknown request id");
+  Request* r = it->second.get();
+  const auto t0 = Clock::now();
+  for (;;) {
+    hipError_t q = hipEventQuery(r->ev[3]);
+    if (q == hipSuccess) break;
+    if (q != hipErrorNotReady) return set_err(c, QQA_E_DEVICE, std::string("poll: ") + hipGetErrorString(q));
+    if (timeout_us == 0) return QQA_PENDING;
+    if (timeout_us < 0) {
+      hipError_t s = hipEventSynchronize(r->ev[3]);
+      if (s != hipSuccess) return set_err(c, QQA_E_DEVICE, std::string("poll: ") + hipGetErrorString(s));
+      break;
+    }
+    if (std::chrono::duration<double, std::micro>(Clock::now() - t0).count() > timeout_us) return QQA_PENDING;
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  const auto t_done = Clock::now();
+  int rc = QQA_OK;
+  if (r->cancelled) {
+    rc = set_err(c, QQA_E_CANCELLED, "request was cancelled");
+  } else if (out) {
+    fill_result(r, out);
+    float ms = 0.f;
+    out->queue_ms = 0.0;
+    out->device_ms = hipEventElapsedTime(&ms, r->ev[0], r->ev[3]) == hipSuccess ? ms : -1.0;
+    out->step_loop_ms = hipEventElapsedTime(&ms, r->ev[1], r->ev[2]) == hipSuccess ? ms : -1.0;
+    out->latency_ms = std::chrono::duration<double, std::milli>(t_done - r->t_submit).count();
+  }
+  release_request_buffers(c, r);
+  c->in_use -= r->footprint;
+  graph_unref(c, r->graph);
+  c->reqs.erase(it);
+  return rc;
+}
+
+int qqa_cancel(qqa_ctx* c, qqa_req id) {
+  if (!c) return QQA_E_ARG;
+  if (c->server) {
+    int rc = serve_cancel(c, id);
+    if (rc != QQA_E_UNKNOWN_REQ) return rc;
+  }
+  auto it = c->reqs.find(id);
+  if (it == c->reqs.end()) return set_err(c, QQA_E_UNKNOWN_REQ, "unknown request id");
+  it->second->cancelled = true;  // device work already enqueued runs out; poll reports it
+  return QQA_OK;
+}
+
+}  // extern "C"
+
+namespace qqa {
+
+void fill_result(const Request* r, qqa_result* out) {
+  int64_t *a, *b, *o;
+  int32_t* best;
+  uint8_t* x;
+  out_views(r->out_host, r->n, r->S, &a, &b, &o, &best, &x);
+  const int s = *best;
+  out->best_replica = s;
+  out->best_objective = o[s];
+  out->best_size_or_cut = a[s];
+  out->best_violations = b[s];
+  out->feasible = b[s] == 0;
+  if (out->replica_objective) std::memcpy(out->replica_objective, o, sizeof(int64_t) * r->S);
+  if (out->replica_size_or_cut) std::memcpy(out->replica_size_or_cut, a, sizeof(int64_t) * r->S);
+  if (out->replica_violations) std::memcpy(out->replica_violations, b, sizeof(int64_t) * r->S);
+  if (out->best_x) std::memcpy(out->best_x, x, r->n);
+}
+
+}  // namespace qqa

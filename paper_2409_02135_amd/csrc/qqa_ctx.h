@@ -1,0 +1,96 @@
+// Context, resident-graph and request records shared by the runtime translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <unordered_map>
+
+#include "qqa.h"
+#include "qqa_internal.h"
+#include "qqa_runtime.h"
+
+namespace qqa {
+
+struct DevGraph {
+  int n = 0;
+  int64_t nnz = 0;
+  int problem = 0;
+  int32_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  float* w = nullptr;
+  float* dense = nullptr;
+  size_t bytes = 0;
+  int refs = 0;
+  bool release_pending = false;
+};
+
+struct Request {
+  enum State { kQueued = 0, kRunning = 1, kDone = 2 };
+  int64_t id = 0;
+  int state = kQueued;
+  bool cancelled = false;
+  int64_t graph = 0;
+  bool temp_graph = false;
+  int problem = 0;
+  qqa_schedule sched{};
+  int S = 0, K = 0, n = 0;
+  uint64_t seed = 0;
+  ReplicaShape shape{};
+  size_t footprint = 0;
+  float* P[2] = {nullptr, nullptr};
+  float* m = nullptr;
+  float* v = nullptr;
+  unsigned long long* acc = nullptr;
+  char* out_dev = nullptr;
+  char* out_host = nullptr;
+  size_t out_size = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // start, loop start, loop end, done
+  std::chrono::steady_clock::time_point t_submit, t_admit;
+};
+
+struct Server;
+
+}  // namespace qqa
+
+struct qqa_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0;
+  size_t in_use = 0;
+  std::string err;
+  qqa::Pool dpool{false};
+  qqa::Pool hpool{true};
+  std::unordered_map<int64_t, qqa::DevGraph> graphs;
+  int64_t next_graph = 1;
+  std::unordered_map<int64_t, std::unique_ptr<qqa::Request>> reqs;
+  int64_t next_req = 1;
+  std::unique_ptr<qqa::Server> server;
+  qqa_ctx();
+  ~qqa_ctx();
+};
+
+namespace qqa {
+
+size_t request_footprint(int n, int S, int rule);
+size_t out_bytes(int n, int S);
+void out_views(char* base, int n, int S, int64_t** a, int64_t** b, int64_t** o, int32_t** best, uint8_t** x);
+int upload_graph(qqa_ctx* c, const qqa_graph& g, int problem, DevGraph* out, std::string* why);
+void free_graph(DevGraph& d);
+void graph_unref(qqa_ctx* c, int64_t gid);
+int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why);
+void release_request_buffers(qqa_ctx* c, Request* r);
+StepParams request_step_params(const Request* r, const DevGraph& g);
+hipError_t enqueue_finish(qqa_ctx* c, Request* r, const DevGraph& g, const float* final_P);
+void fill_result(const Request* r, qqa_result* out);
+int set_err(qqa_ctx* c, int code, const std::string& msg);
+
+// continuous-batching server hooks (qqa_serve.cpp)
+int serve_poll(qqa_ctx* c, int64_t id, qqa_result* out, int32_t timeout_us);
+int serve_cancel(qqa_ctx* c, int64_t id);
+
+}  // namespace qqa

@@ -1,0 +1,77 @@
+// Internal interface between the HIP kernels (qqa_kernels.hip) and the host runtime
+// (qqa_runtime.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace qqa {
+
+enum : int32_t { kMIS = 0, kMAXCUT = 1 };
+enum : int32_t { kADAMW = 0, kLANGEVIN = 1 };
+enum : uint32_t { kStreamInit = 0, kStreamNoise = 1 };
+
+constexpr int kMaxReplicas = 4096;
+constexpr int kBlock = 256;
+
+// How the S replicas of one variable map onto lanes: a row is served by `lpr` adjacent
+// lanes (a power of two, at most one wavefront), each lane owns `qpl` float4 quads.
+struct ReplicaShape {
+  int lpr;     // lanes per row
+  int qpl;     // quads per lane
+  int nquads;  // ceil(S / 4)
+  int stride;  // floats per row = 4 * nquads
+};
+ReplicaShape replica_shape(int S);
+
+// Everything one launch of the fused update needs for one instance at one update index.
+// Per-update scalars (gamma_t, bias corrections) are computed on the host in double
+// precision and rounded once.
+struct StepParams {
+  const int32_t* row_ptr;  // sparse CSR (device), or nullptr when `coupling` is given
+  const int32_t* col;
+  const float* w;          // nullptr: unweighted
+  const float* coupling;   // dense path: precomputed coupling product, n x stride, or nullptr
+  const float* P_in;
+  float* P_out;
+  float* m;
+  float* v;
+  int32_t n, S, stride, problem, rule, alpha_e;
+  float lambda;            // MIS penalty
+  float lr, wd_factor;     // wd_factor = 1 - lr * weight_decay
+  float comm_alpha;
+  float beta1, omb1, beta2, omb2, eps;
+  float noise_scale;       // sqrt(2 lr T)
+  float ce;                // -2 alpha_e gamma_t
+  float inv_bc1, inv_bc2;  // 1 / (1 - beta^k)
+  uint32_t key0, key1;     // Philox key = seed
+  uint32_t k;              // update count t + 1 (Philox counter word 2)
+};
+
+struct EvalParams {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const float* w;
+  const float* dense;      // n x n or nullptr
+  const float* P;
+  int32_t n, S, stride, problem;
+  int64_t lambda;
+  unsigned long long* acc; // [2][stride]: size_or_cut, violations (zeroed by launch_eval)
+  int64_t* size_or_cut;    // [S] outputs
+  int64_t* viol;
+  int64_t* obj;
+  int32_t* best;           // [1]
+};
+
+hipError_t launch_philox(uint64_t seed, int n, int nquads, uint32_t k, uint32_t stream_id, uint32_t* out,
+                         hipStream_t st);
+hipError_t launch_noise(uint64_t seed, int n, int S, uint32_t k, float* xi, hipStream_t st);
+hipError_t launch_init(uint64_t seed, int n, int S, float* P, float* m, float* v, hipStream_t st);
+hipError_t launch_step(const StepParams& p, hipStream_t st);
+hipError_t launch_eval(const EvalParams& p, hipStream_t st);
+hipError_t launch_extract(const float* P, int n, int stride, const int32_t* best, uint8_t* x, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, size_t count, hipStream_t st);
+
+}  // namespace qqa

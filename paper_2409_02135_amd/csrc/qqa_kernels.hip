@@ -1,0 +1,504 @@
+// HIP kernels (gfx950) of the PQQA replica update: counter-based noise, initial state,
+// the fused sparse update, and exact rounding/evaluation.
+//
+// Data layout: replica state is row-major n x stride float32 with the replica index
+// contiguous, so the S values of one variable are one contiguous row.  A row is served
+// by `lpr` adjacent lanes of one wavefront (lpr = 64 for S >= 256, several rows per
+// wavefront for smaller S); each lane owns float4 quads of replicas, which makes every
+// neighbour-row gather a coalesced, 16-byte-per-lane load and gives one Philox call
+// (4 normals) per lane and quad.
+#include "qqa_internal.h"
+
+namespace qqa {
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the uniform / normal transforms.
+// ---------------------------------------------------------------------------------------
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                            uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// odd multiples of 2^-24 in (0,1): exact in binary32
+__device__ __forceinline__ float u01(uint32_t r) { return (float)((r >> 8) | 1u) * 0x1.0p-24f; }
+
+// Box-Muller on (u0,u1), (u2,u3): angle 2*pi*u as sincospi(2u).
+__device__ __forceinline__ float4 normals4(U4 r) {
+  const float R1 = sqrtf(-2.0f * logf(u01(r.x)));
+  const float R2 = sqrtf(-2.0f * logf(u01(r.z)));
+  float s1, c1, s2, c2;
+  sincospif(2.0f * u01(r.y), &s1, &c1);
+  sincospif(2.0f * u01(r.w), &s2, &c2);
+  return make_float4(R1 * c1, R1 * s1, R2 * c2, R2 * s2);
+}
+
+__global__ void philox_kernel(uint32_t k0, uint32_t k1, int n, int nquads, uint32_t k, uint32_t sid, uint32_t* out) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * nquads) return;
+  const int i = (int)(idx / nquads), q = (int)(idx % nquads);
+  const U4 r = philox4x32_10((uint32_t)i, (uint32_t)q, k, sid, k0, k1);
+  reinterpret_cast<uint4*>(out)[idx] = make_uint4(r.x, r.y, r.z, r.w);
+}
+
+__global__ void noise_kernel(uint32_t k0, uint32_t k1, int n, int nquads, int S, uint32_t k, float* xi) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * nquads) return;
+  const int i = (int)(idx / nquads), q = (int)(idx % nquads);
+  float4 z = normals4(philox4x32_10((uint32_t)i, (uint32_t)q, k, kStreamNoise, k0, k1));
+  const int s0 = 4 * q;
+  if (s0 + 1 >= S) z.y = 0.f;
+  if (s0 + 2 >= S) z.z = 0.f;
+  if (s0 + 3 >= S) z.w = 0.f;
+  reinterpret_cast<float4*>(xi)[idx] = z;
+}
+
+__global__ void init_kernel(uint32_t k0, uint32_t k1, int n, int nquads, int S, float* P, float* m, float* v) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * nquads) return;
+  const int i = (int)(idx / nquads), q = (int)(idx % nquads);
+  const U4 r = philox4x32_10((uint32_t)i, (uint32_t)q, 0u, kStreamInit, k0, k1);
+  const int s0 = 4 * q;
+  float4 p = make_float4(u01(r.x), s0 + 1 < S ? u01(r.y) : 0.f, s0 + 2 < S ? u01(r.z) : 0.f,
+                         s0 + 3 < S ? u01(r.w) : 0.f);
+  reinterpret_cast<float4*>(P)[idx] = p;
+  if (m) reinterpret_cast<float4*>(m)[idx] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (v) reinterpret_cast<float4*>(v)[idx] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// ---------------------------------------------------------------------------------------
+// Fused update of one row (all S replicas of variable `row`), lanes gl = 0..LPR-1.
+// ---------------------------------------------------------------------------------------
+template <int LPR>
+__device__ __forceinline__ float group_sum(float x) {
+  // butterfly inside the LPR-lane group: a fixed tree determined by LPR alone, and
+  // every lane ends with the same bits (IEEE addition is commutative)
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, LPR);
+  return x;
+}
+
+__device__ __forceinline__ float comp(const float4& v, int c) {
+  return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ void set_comp(float4& v, int c, float x) {
+  if (c == 0) v.x = x; else if (c == 1) v.y = x; else if (c == 2) v.z = x; else v.w = x;
+}
+
+__device__ __forceinline__ float ipow_odd(float z, int e) {
+  float r = z;
+  for (int i = 1; i < e; ++i) r *= z;
+  return r;
+}
+
+template <int LPR, int QPL>
+__device__ __forceinline__ void update_row(const StepParams& a, const int row, const int gl) {
+  const int nq = (a.S + 3) >> 2;
+  const bool maxcut = a.problem == kMAXCUT;
+
+  // (1) coupling product C_i = sum_j A_ij p_j (MIS) or sum_j A_ij (2 p_j - 1) (max-cut),
+  //     accumulated in CSR order so that the rounding sequence depends on the graph only
+  float4 acc[QPL];
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (a.coupling) {
+#pragma unroll
+    for (int k = 0; k < QPL; ++k) {
+      const int q = gl + LPR * k;
+      if (q < nq) acc[k] = *reinterpret_cast<const float4*>(a.coupling + (size_t)row * a.stride + 4 * q);
+    }
+  } else {
+    const int rs = a.row_ptr[row], re = a.row_ptr[row + 1];
+    for (int e0 = rs; e0 < re; e0 += 4) {
+      int j[4];
+      float w[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u;
+        j[u] = e < re ? a.col[e] : -1;
+        w[u] = e < re ? (a.w ? a.w[e] : 1.f) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (j[u] < 0) continue;
+        const float* pj = a.P_in + (size_t)j[u] * a.stride;
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) {
+          const int q = gl + LPR * k;
+          if (q < nq) {
+            float4 x = *reinterpret_cast<const float4*>(pj + 4 * q);
+            if (maxcut) {
+              x.x = 2.f * x.x - 1.f;
+              x.y = 2.f * x.y - 1.f;
+              x.z = 2.f * x.z - 1.f;
+              x.w = 2.f * x.w - 1.f;
+            }
+            acc[k].x = fmaf(w[u], x.x, acc[k].x);
+            acc[k].y = fmaf(w[u], x.y, acc[k].y);
+            acc[k].z = fmaf(w[u], x.z, acc[k].z);
+            acc[k].w = fmaf(w[u], x.w, acc[k].w);
+          }
+        }
+      }
+    }
+  }
+
+  // (2) own row and the replica statistics mu_i, sigma_i (two-pass, population STD)
+  const size_t base = (size_t)row * a.stride;
+  const bool adam = a.rule == kADAMW;
+  float4 p[QPL], mm[QPL], vv[QPL];
+  float sum = 0.f;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+    p[k] = mm[k] = vv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (q < nq) {
+      p[k] = *reinterpret_cast<const float4*>(a.P_in + base + 4 * q);
+      if (adam) {
+        mm[k] = *reinterpret_cast<const float4*>(a.m + base + 4 * q);
+        vv[k] = *reinterpret_cast<const float4*>(a.v + base + 4 * q);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (4 * q + c < a.S) sum += comp(p[k], c);
+    }
+  }
+  sum = group_sum<LPR>(sum);
+  const float mu = sum / (float)a.S;
+  float sq = 0.f;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+    if (q < nq) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (4 * q + c < a.S) {
+          const float d = comp(p[k], c) - mu;
+          sq = fmaf(d, d, sq);
+        }
+    }
+  }
+  sq = group_sum<LPR>(sq);
+  const float sigma = sqrtf(sq / (float)a.S);
+  const float cg = sigma > 0.f ? -a.comm_alpha / sigma : 0.f;
+
+  // (3) gradient, step, noise, clamp
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+    if (q >= nq) continue;
+    const float4 xi = normals4(philox4x32_10((uint32_t)row, (uint32_t)q, a.k, kStreamNoise, a.key0, a.key1));
+    float4 po, mo, vo;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float pc = comp(p[k], c);
+      const float C = comp(acc[k], c);
+      const float gf = maxcut ? C : fmaf(a.lambda, C, -1.f);
+      const float z = 2.f * pc - 1.f;
+      const float ge = a.ce * ipow_odd(z, a.alpha_e - 1);
+      const float gc = cg * (pc - mu);
+      const float g = gf + ge + gc;
+      float pn, mn = 0.f, vn = 0.f;
+      if (adam) {
+        pn = pc * a.wd_factor;
+        mn = fmaf(a.beta1, comp(mm[k], c), a.omb1 * g);
+        vn = fmaf(a.beta2, comp(vv[k], c), a.omb2 * (g * g));
+        const float den = sqrtf(vn * a.inv_bc2) + a.eps;
+        pn = pn - a.lr * (mn * a.inv_bc1) / den;
+      } else {
+        pn = pc - a.lr * g;
+      }
+      pn = fmaf(a.noise_scale, comp(xi, c), pn);
+      pn = fminf(fmaxf(pn, 0.f), 1.f);
+      const bool valid = 4 * q + c < a.S;
+      set_comp(po, c, valid ? pn : 0.f);
+      set_comp(mo, c, valid ? mn : 0.f);
+      set_comp(vo, c, valid ? vn : 0.f);
+    }
+    *reinterpret_cast<float4*>(a.P_out + base + 4 * q) = po;
+    if (adam) {
+      *reinterpret_cast<float4*>(a.m + base + 4 * q) = mo;
+      *reinterpret_cast<float4*>(a.v + base + 4 * q) = vo;
+    }
+  }
+}
+
+template <int LPR, int QPL>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepParams a) {
+  const int row = (int)(((long long)blockIdx.x * kBlock + threadIdx.x) / LPR);
+  if (row >= a.n) return;  // whole LPR-lane groups leave together
+  update_row<LPR, QPL>(a, row, threadIdx.x & (LPR - 1));
+}
+
+// ---------------------------------------------------------------------------------------
+// Exact rounding + evaluation.  Each lane keeps int64 partial counts for the replicas it
+// owns over a grid-stride of rows, the block folds them in LDS, then one atomic per
+// replica per block; integer addition makes the result independent of order.
+// ---------------------------------------------------------------------------------------
+template <int LPR, int QPL>
+__global__ __launch_bounds__(kBlock) void eval_kernel(EvalParams a) {
+  extern __shared__ unsigned long long sh[];  // [2][stride]
+  const int nq = (a.S + 3) >> 2;
+  for (int s = threadIdx.x; s < 2 * a.stride; s += kBlock) sh[s] = 0ull;
+  __syncthreads();
+  const int gpb = kBlock / LPR;
+  const int gl = threadIdx.x & (LPR - 1);
+  const bool maxcut = a.problem == kMAXCUT;
+  long long ca[QPL][4], cb[QPL][4];
+#pragma unroll
+  for (int k = 0; k < QPL; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ca[k][c] = cb[k][c] = 0;
+
+  for (int row = blockIdx.x * gpb + threadIdx.x / LPR; row < a.n; row += gridDim.x * gpb) {
+    bool xi[QPL][4];
+#pragma unroll
+    for (int k = 0; k < QPL; ++k) {
+      const int q = gl + LPR * k;
+      float4 pv = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (q < nq) pv = *reinterpret_cast<const float4*>(a.P + (size_t)row * a.stride + 4 * q);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        xi[k][c] = comp(pv, c) > 0.5f;
+        if (!maxcut) ca[k][c] += xi[k][c];
+      }
+    }
+    const int deg = a.dense ? a.n : a.row_ptr[row + 1] - a.row_ptr[row];
+    for (int u = 0; u < deg; ++u) {
+      int j;
+      float w;
+      if (a.dense) {
+        j = u;
+        w = a.dense[(size_t)row * a.n + u];
+      } else {
+        const int e = a.row_ptr[row] + u;
+        j = a.col[e];
+        w = a.w ? a.w[e] : 1.f;
+      }
+      if (j <= row || w == 0.f) continue;  // each undirected edge once
+      const long long qw = maxcut ? (long long)(w * 65536.0f) : 0;
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+        const int q = gl + LPR * k;
+        if (q >= nq) continue;
+        const float4 pj = *reinterpret_cast<const float4*>(a.P + (size_t)j * a.stride + 4 * q);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const bool xj = comp(pj, c) > 0.5f;
+          if (maxcut) ca[k][c] += (xi[k][c] != xj) ? qw : 0;
+          else cb[k][c] += (xi[k][c] && xj);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+    if (q >= nq) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int s = 4 * q + c;
+      if (s >= a.S) continue;
+      if (ca[k][c]) atomicAdd(&sh[s], (unsigned long long)ca[k][c]);
+      if (cb[k][c]) atomicAdd(&sh[a.stride + s], (unsigned long long)cb[k][c]);
+    }
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < a.S; s += kBlock) {
+    if (sh[s]) atomicAdd(&a.acc[s], sh[s]);
+    if (sh[a.stride + s]) atomicAdd(&a.acc[a.stride + s], sh[a.stride + s]);
+  }
+}
+
+// objectives and the lexicographic best replica (violations > 0, l, index)
+__global__ __launch_bounds__(kBlock) void finalize_kernel(EvalParams a) {
+  __shared__ int best_s[kBlock];
+  int mine = -1;
+  bool mi = false;
+  long long mo = 0;
+  for (int s = threadIdx.x; s < a.S; s += kBlock) {
+    const long long A = (long long)a.acc[s], B = (long long)a.acc[a.stride + s];
+    const long long o = a.problem == kMAXCUT ? -A : -A + a.lambda * B;
+    a.size_or_cut[s] = A;
+    a.viol[s] = B;
+    a.obj[s] = o;
+    const bool inf = B > 0;
+    if (mine < 0 || (inf < mi) || (inf == mi && o < mo)) {
+      mine = s;
+      mi = inf;
+      mo = o;
+    }
+  }
+  best_s[threadIdx.x] = mine;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      const int x = best_s[threadIdx.x], y = best_s[threadIdx.x + off];
+      if (y >= 0) {
+        bool take = x < 0;
+        if (!take) {
+          const long long Bx = (long long)a.acc[a.stride + x], By = (long long)a.acc[a.stride + y];
+          const long long Ax = (long long)a.acc[x], Ay = (long long)a.acc[y];
+          const long long ox = a.problem == kMAXCUT ? -Ax : -Ax + a.lambda * Bx;
+          const long long oy = a.problem == kMAXCUT ? -Ay : -Ay + a.lambda * By;
+          const bool ix = Bx > 0, iy = By > 0;
+          take = (iy < ix) || (iy == ix && (oy < ox || (oy == ox && y < x)));
+        }
+        if (take) best_s[threadIdx.x] = y;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.best[0] = best_s[0];
+}
+
+__global__ void extract_kernel(const float* P, int n, int stride, const int32_t* best, uint8_t* x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = P[(size_t)i * stride + best[0]] > 0.5f ? 1 : 0;
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, size_t count) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------------------
+ReplicaShape replica_shape(int S) {
+  ReplicaShape r;
+  r.nquads = (S + 3) / 4;
+  r.stride = 4 * r.nquads;
+  int lpr = 1;
+  while (lpr < r.nquads && lpr < 64) lpr <<= 1;
+  r.lpr = lpr;
+  int qpl = 1;
+  while (lpr * qpl < r.nquads) qpl <<= 1;
+  r.qpl = qpl;
+  return r;
+}
+
+static unsigned grid_for(long long threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+hipError_t launch_philox(uint64_t seed, int n, int nquads, uint32_t k, uint32_t sid, uint32_t* out, hipStream_t st) {
+  const long long work = (long long)n * nquads;
+  if (work == 0) return hipSuccess;
+  hipLaunchKernelGGL(philox_kernel, dim3(grid_for(work)), dim3(kBlock), 0, st, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), n, nquads, k, sid, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise(uint64_t seed, int n, int S, uint32_t k, float* xi, hipStream_t st) {
+  const int nq = (S + 3) / 4;
+  const long long work = (long long)n * nq;
+  if (work == 0) return hipSuccess;
+  hipLaunchKernelGGL(noise_kernel, dim3(grid_for(work)), dim3(kBlock), 0, st, (uint32_t)seed, (uint32_t)(seed >> 32),
+                     n, nq, S, k, xi);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(uint64_t seed, int n, int S, float* P, float* m, float* v, hipStream_t st) {
+  const int nq = (S + 3) / 4;
+  const long long work = (long long)n * nq;
+  if (work == 0) return hipSuccess;
+  hipLaunchKernelGGL(init_kernel, dim3(grid_for(work)), dim3(kBlock), 0, st, (uint32_t)seed, (uint32_t)(seed >> 32),
+                     n, nq, S, P, m, v);
+  return hipGetLastError();
+}
+
+template <int LPR, int QPL>
+static void launch_step_t(const StepParams& p, hipStream_t st) {
+  hipLaunchKernelGGL((step_kernel<LPR, QPL>), dim3(grid_for((long long)p.n * LPR)), dim3(kBlock), 0, st, p);
+}
+
+hipError_t launch_step(const StepParams& p, hipStream_t st) {
+  if (p.n == 0) return hipSuccess;
+  const ReplicaShape r = replica_shape(p.S);
+  switch (r.lpr) {
+    case 1: launch_step_t<1, 1>(p, st); break;
+    case 2: launch_step_t<2, 1>(p, st); break;
+    case 4: launch_step_t<4, 1>(p, st); break;
+    case 8: launch_step_t<8, 1>(p, st); break;
+    case 16: launch_step_t<16, 1>(p, st); break;
+    case 32: launch_step_t<32, 1>(p, st); break;
+    default:
+      switch (r.qpl) {
+        case 1: launch_step_t<64, 1>(p, st); break;
+        case 2: launch_step_t<64, 2>(p, st); break;
+        case 4: launch_step_t<64, 4>(p, st); break;
+        case 8: launch_step_t<64, 8>(p, st); break;
+        case 16: launch_step_t<64, 16>(p, st); break;
+        default: return hipErrorInvalidValue;
+      }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, size_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for((long long)count)), dim3(kBlock), 0, st, p, count);
+  return hipGetLastError();
+}
+
+template <int LPR, int QPL>
+static void launch_eval_t(const EvalParams& p, hipStream_t st) {
+  const int gpb = kBlock / LPR;
+  int blocks = (p.n + gpb - 1) / gpb;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  const size_t shmem = 2 * (size_t)p.stride * sizeof(unsigned long long);
+  hipLaunchKernelGGL((eval_kernel<LPR, QPL>), dim3(blocks), dim3(kBlock), shmem, st, p);
+}
+
+hipError_t launch_eval(const EvalParams& p, hipStream_t st) {
+  hipError_t e = launch_fill_u64(p.acc, 2 * (size_t)p.stride, st);
+  if (e != hipSuccess) return e;
+  const ReplicaShape r = replica_shape(p.S);
+  if (p.n > 0) {
+    switch (r.lpr) {
+      case 1: launch_eval_t<1, 1>(p, st); break;
+      case 2: launch_eval_t<2, 1>(p, st); break;
+      case 4: launch_eval_t<4, 1>(p, st); break;
+      case 8: launch_eval_t<8, 1>(p, st); break;
+      case 16: launch_eval_t<16, 1>(p, st); break;
+      case 32: launch_eval_t<32, 1>(p, st); break;
+      default:
+        switch (r.qpl) {
+          case 1: launch_eval_t<64, 1>(p, st); break;
+          case 2: launch_eval_t<64, 2>(p, st); break;
+          case 4: launch_eval_t<64, 4>(p, st); break;
+          case 8: launch_eval_t<64, 8>(p, st); break;
+          case 16: launch_eval_t<64, 16>(p, st); break;
+          default: return hipErrorInvalidValue;
+        }
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlock), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract(const float* P, int n, int stride, const int32_t* best, uint8_t* x, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(extract_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, P, n, stride, best, x);
+  return hipGetLastError();
+}
+
+}  // namespace qqa

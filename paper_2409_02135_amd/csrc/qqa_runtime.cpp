@@ -1,0 +1,331 @@
+// Host runtime behind include/qqa.h: argument and graph validation, device uploads,
+// a size-keyed buffer pool, and the request lifecycle (submit -> device work -> poll).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "qqa.h"
+#include "qqa_internal.h"
+#include "qqa_runtime.h"
+
+using namespace qqa;
+
+namespace qqa {
+
+// ---------------------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------------------
+static thread_local std::string g_dev_error;
+
+int fail(std::string* where, int code, const std::string& msg) {
+  if (where) *where = msg;
+  return code;
+}
+
+// ---------------------------------------------------------------------------------------
+// schedule helpers
+// ---------------------------------------------------------------------------------------
+bool schedule_valid(const qqa_schedule& s, std::string* why) {
+  auto finite = [](float x) { return std::isfinite(x); };
+  if (!finite(s.gamma_min) || !finite(s.gamma_max) || !finite(s.lr) || !finite(s.weight_decay) ||
+      !finite(s.temperature) || !finite(s.comm_alpha) || !finite(s.beta1) || !finite(s.beta2) ||
+      !finite(s.adam_eps)) {
+    *why = "schedule has a non-finite value";
+    return false;
+  }
+  if (s.gamma_min > s.gamma_max) { *why = "gamma_min > gamma_max"; return false; }
+  if (s.entropy_alpha < 2 || s.entropy_alpha > 64 || (s.entropy_alpha & 1)) {
+    *why = "entropy_alpha must be even and in [2, 64]";
+    return false;
+  }
+  if (!(s.lr > 0.f) || s.weight_decay < 0.f || s.temperature < 0.f || s.comm_alpha < 0.f) {
+    *why = "need lr > 0, weight_decay >= 0, temperature >= 0, comm_alpha >= 0";
+    return false;
+  }
+  if (s.beta1 < 0.f || s.beta1 >= 1.f || s.beta2 < 0.f || s.beta2 >= 1.f || s.adam_eps < 0.f) {
+    *why = "need 0 <= beta < 1 and adam_eps >= 0";
+    return false;
+  }
+  if (s.penalty_lambda < 0 || s.penalty_lambda > (1 << 20)) { *why = "penalty_lambda out of range"; return false; }
+  if (s.rule != QQA_STEP_ADAMW && s.rule != QQA_STEP_LANGEVIN) { *why = "unknown step rule"; return false; }
+  return true;
+}
+
+// Fill the per-update scalars of update t (0-based) of a K-update schedule.  gamma_t
+// rises linearly from gamma_min (t = 0) to gamma_max (t = K-1); bias corrections use
+// k = t + 1.  Everything is computed in double and rounded once to float.
+void fill_step_scalars(StepParams& p, const qqa_schedule& s, int t, int K) {
+  const double gmin = s.gamma_min, gmax = s.gamma_max;
+  const double gamma = K <= 1 ? gmin : gmin + (gmax - gmin) * (double)t / (double)(K - 1);
+  const double k = (double)t + 1.0;
+  p.ce = (float)(-2.0 * (double)s.entropy_alpha * gamma);
+  p.inv_bc1 = (float)(1.0 / (1.0 - std::pow((double)s.beta1, k)));
+  p.inv_bc2 = (float)(1.0 / (1.0 - std::pow((double)s.beta2, k)));
+  p.k = (uint32_t)(t + 1);
+}
+
+void fill_static_scalars(StepParams& p, const qqa_schedule& s, int problem, int S, uint64_t seed) {
+  p.S = S;
+  p.stride = replica_shape(S).stride;
+  p.problem = problem;
+  p.rule = s.rule;
+  p.alpha_e = s.entropy_alpha;
+  p.lambda = (float)s.penalty_lambda;
+  p.lr = s.lr;
+  p.wd_factor = (float)(1.0 - (double)s.lr * (double)s.weight_decay);
+  p.comm_alpha = s.comm_alpha;
+  p.beta1 = s.beta1;
+  p.omb1 = (float)(1.0 - (double)s.beta1);
+  p.beta2 = s.beta2;
+  p.omb2 = (float)(1.0 - (double)s.beta2);
+  p.eps = s.adam_eps;
+  p.noise_scale = (float)std::sqrt(2.0 * (double)s.lr * (double)s.temperature);
+  p.key0 = (uint32_t)seed;
+  p.key1 = (uint32_t)(seed >> 32);
+}
+
+// ---------------------------------------------------------------------------------------
+// graph validation (host)
+// ---------------------------------------------------------------------------------------
+static bool on_grid(float w) {
+  const double q = (double)w * 65536.0;
+  return std::fabs(w) < 128.f && q == std::rint(q);
+}
+
+int validate_graph(const qqa_graph& g, int problem, std::string* why) {
+  if (g.n <= 0) return fail(why, QQA_E_GRAPH, "graph needs n > 0");
+  if (g.dense) {
+    const int n = g.n;
+    if ((int64_t)n * n > (int64_t)1 << 31) return fail(why, QQA_E_GRAPH, "dense graph too large");
+    for (int i = 0; i < n; ++i) {
+      if (g.dense[(size_t)i * n + i] != 0.f) return fail(why, QQA_E_GRAPH, "dense graph has a nonzero diagonal");
+      for (int j = i + 1; j < n; ++j) {
+        const float a = g.dense[(size_t)i * n + j], b = g.dense[(size_t)j * n + i];
+        if (a != b) return fail(why, QQA_E_GRAPH, "dense graph is not symmetric");
+        if (!std::isfinite(a)) return fail(why, QQA_E_GRAPH, "dense graph has a non-finite weight");
+        if (problem == QQA_MIS && a != 0.f && a != 1.f)
+          return fail(why, QQA_E_GRAPH, "MIS dense adjacency must be 0/1");
+        if (problem == QQA_MAXCUT && !on_grid(a))
+          return fail(why, QQA_E_GRAPH, "max-cut weight not a multiple of 2^-16 with |w| < 128");
+      }
+    }
+    return QQA_OK;
+  }
+  if (!g.row_ptr || (g.nnz > 0 && !g.col_idx)) return fail(why, QQA_E_GRAPH, "CSR arrays missing");
+  if (g.nnz < 0 || g.nnz >= ((int64_t)1 << 31)) return fail(why, QQA_E_GRAPH, "nnz out of range");
+  if (g.row_ptr[0] != 0 || g.row_ptr[g.n] != g.nnz) return fail(why, QQA_E_GRAPH, "row_ptr must run from 0 to nnz");
+  for (int i = 0; i < g.n; ++i)
+    if (g.row_ptr[i + 1] < g.row_ptr[i]) return fail(why, QQA_E_GRAPH, "row_ptr is not monotone");
+  // sorted copy of each row for duplicate and symmetry checks
+  std::vector<int32_t> cols(g.col_idx, g.col_idx + g.nnz);
+  std::vector<float> ws;
+  const bool weighted = g.weight != nullptr && problem == QQA_MAXCUT;
+  if (weighted) ws.assign(g.weight, g.weight + g.nnz);
+  for (int i = 0; i < g.n; ++i) {
+    const int64_t a = g.row_ptr[i], b = g.row_ptr[i + 1];
+    for (int64_t e = a; e < b; ++e) {
+      if (cols[e] < 0 || cols[e] >= g.n) return fail(why, QQA_E_GRAPH, "column index out of range");
+      if (cols[e] == i) return fail(why, QQA_E_GRAPH, "self-loop");
+      if (weighted && !on_grid(ws[e]))
+        return fail(why, QQA_E_GRAPH, "max-cut weight not a multiple of 2^-16 with |w| < 128");
+    }
+    if (weighted) {
+      std::vector<std::pair<int32_t, float>> row;
+      row.reserve(b - a);
+      for (int64_t e = a; e < b; ++e) row.emplace_back(cols[e], ws[e]);
+      std::sort(row.begin(), row.end());
+      for (int64_t e = a; e < b; ++e) { cols[e] = row[e - a].first; ws[e] = row[e - a].second; }
+    } else {
+      std::sort(cols.begin() + a, cols.begin() + b);
+    }
+    for (int64_t e = a + 1; e < b; ++e)
+      if (cols[e] == cols[e - 1]) return fail(why, QQA_E_GRAPH, "duplicate edge");
+  }
+  for (int i = 0; i < g.n; ++i) {
+    for (int64_t e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
+      const int j = cols[e];
+      auto first = cols.begin() + g.row_ptr[j], last = cols.begin() + g.row_ptr[j + 1];
+      auto it = std::lower_bound(first, last, i);
+      if (it == last || *it != i) return fail(why, QQA_E_GRAPH, "graph is not symmetric");
+      if (weighted && ws[it - cols.begin()] != ws[e]) return fail(why, QQA_E_GRAPH, "weights are not symmetric");
+    }
+  }
+  return QQA_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// device buffer pool: exact-size reuse, so repeated solves of one shape never call
+// hipMalloc / hipFree (both of which synchronise) after the first.
+// ---------------------------------------------------------------------------------------
+hipError_t Pool::get(size_t bytes, void** out) {
+  bytes = (bytes + 255) & ~size_t(255);
+  auto it = free_.find(bytes);
+  if (it != free_.end()) {
+    *out = it->second;
+    free_.erase(it);
+    return hipSuccess;
+  }
+  hipError_t e = pinned_ ? hipHostMalloc(out, bytes, hipHostMallocDefault) : hipMalloc(out, bytes);
+  if (e == hipSuccess) held_ += bytes;
+  return e;
+}
+
+void Pool::put(void* p, size_t bytes) {
+  if (!p) return;
+  bytes = (bytes + 255) & ~size_t(255);
+  free_.emplace(bytes, p);
+}
+
+void Pool::trim() {
+  for (auto& kv : free_) {
+    if (pinned_) (void)hipHostFree(kv.second);
+    else (void)hipFree(kv.second);
+    held_ -= kv.first;
+  }
+  free_.clear();
+}
+
+}  // namespace qqa
+
+// =========================================================================================
+// C ABI
+// =========================================================================================
+extern "C" {
+
+void qqa_schedule_default(qqa_schedule* s, qqa_problem problem, int32_t n) {
+  if (!s) return;
+  s->gamma_min = problem == QQA_MAXCUT ? (n >= 1000 ? -20.f : -5.f) : -2.f;
+  s->gamma_max = 0.1f;
+  s->lr = 0.1f;
+  s->weight_decay = 0.01f;
+  s->temperature = 1e-3f;
+  s->comm_alpha = 0.1f;
+  s->entropy_alpha = 4;
+  s->beta1 = 0.9f;
+  s->beta2 = 0.999f;
+  s->adam_eps = 1e-8f;
+  s->penalty_lambda = 2;
+  s->rule = QQA_STEP_ADAMW;
+}
+
+int qqa_graph_validate(const qqa_graph* g, qqa_problem problem, char* why, size_t why_len) {
+  std::string msg;
+  int rc = g ? validate_graph(*g, problem, &msg) : fail(&msg, QQA_E_GRAPH, "graph is NULL");
+  if (why && why_len) {
+    std::snprintf(why, why_len, "%s", msg.c_str());
+  }
+  return rc;
+}
+
+int32_t qqa_replica_stride(int32_t S) { return S <= 0 ? 0 : replica_shape(S).stride; }
+
+const char* qqa_dev_last_error(void) { return g_dev_error.c_str(); }
+
+#define DEV_CHECK(expr)                                                                        \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(&g_dev_error, QQA_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+int qqa_dev_philox(uint64_t seed, int32_t n, int32_t nquads, uint32_t k, uint32_t stream_id, uint32_t* out,
+                   void* stream) {
+  if (n < 0 || nquads < 0 || (!out && (int64_t)n * nquads > 0)) return fail(&g_dev_error, QQA_E_ARG, "bad philox arguments");
+  DEV_CHECK(launch_philox(seed, n, nquads, k, stream_id, out, (hipStream_t)stream));
+  return QQA_OK;
+}
+
+int qqa_dev_noise(uint64_t seed, int32_t n, int32_t S, uint32_t k, float* xi, void* stream) {
+  if (n < 0 || S <= 0 || S > kMaxReplicas || (!xi && n > 0)) return fail(&g_dev_error, QQA_E_ARG, "bad noise arguments");
+  DEV_CHECK(launch_noise(seed, n, S, k, xi, (hipStream_t)stream));
+  return QQA_OK;
+}
+
+int qqa_dev_init(uint64_t seed, int32_t n, int32_t S, float* P, float* m, float* v, void* stream) {
+  if (n < 0 || S <= 0 || S > kMaxReplicas || (!P && n > 0)) return fail(&g_dev_error, QQA_E_ARG, "bad init arguments");
+  DEV_CHECK(launch_init(seed, n, S, P, m, v, (hipStream_t)stream));
+  return QQA_OK;
+}
+
+static int dev_graph_check(const qqa_dev_graph* g) {
+  if (!g || g->n < 0) return fail(&g_dev_error, QQA_E_ARG, "graph is NULL or n < 0");
+  if (g->dense) return fail(&g_dev_error, QQA_E_ARG, "dense coupling is handled by the dense path");
+  if (g->n > 0 && !g->row_ptr) return fail(&g_dev_error, QQA_E_ARG, "row_ptr missing");
+  if (g->nnz > 0 && !g->col_idx) return fail(&g_dev_error, QQA_E_ARG, "col_idx missing");
+  return QQA_OK;
+}
+
+int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule* sched, int32_t S, int32_t t,
+                 int32_t K, uint64_t seed, const float* P_in, float* P_out, float* m, float* v, void* stream) {
+  int rc = dev_graph_check(g);
+  if (rc) return rc;
+  if (problem != QQA_MIS && problem != QQA_MAXCUT) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
+  if (S <= 0 || S > kMaxReplicas) return fail(&g_dev_error, QQA_E_ARG, "S must be in [1, 4096]");
+  if (K <= 0 || t < 0 || t >= K) return fail(&g_dev_error, QQA_E_ARG, "need 0 <= t < K");
+  qqa_schedule s;
+  if (sched) s = *sched; else qqa_schedule_default(&s, problem, g->n);
+  std::string why;
+  if (!schedule_valid(s, &why)) return fail(&g_dev_error, QQA_E_ARG, why);
+  if (g->n > 0 && (!P_in || !P_out)) return fail(&g_dev_error, QQA_E_ARG, "P_in/P_out missing");
+  if (P_in == P_out && g->n > 0) return fail(&g_dev_error, QQA_E_ARG, "P_out must not alias P_in");
+  if (s.rule == QQA_STEP_ADAMW && g->n > 0 && (!m || !v)) return fail(&g_dev_error, QQA_E_ARG, "AdamW needs m and v");
+  StepParams p{};
+  p.row_ptr = g->row_ptr;
+  p.col = g->col_idx;
+  p.w = problem == QQA_MAXCUT ? g->weight : nullptr;
+  p.coupling = nullptr;
+  p.P_in = P_in;
+  p.P_out = P_out;
+  p.m = m;
+  p.v = v;
+  p.n = g->n;
+  fill_static_scalars(p, s, problem, S, seed);
+  fill_step_scalars(p, s, t, K);
+  DEV_CHECK(launch_step(p, (hipStream_t)stream));
+  return QQA_OK;
+}
+
+int qqa_dev_eval(const qqa_dev_graph* g, qqa_problem problem, int32_t penalty_lambda, int32_t S, const float* P,
+                 int64_t* size_or_cut, int64_t* viol, int64_t* obj, int32_t* best, void* stream) {
+  if (!g || g->n < 0) return fail(&g_dev_error, QQA_E_ARG, "graph is NULL or n < 0");
+  if (!g->dense && g->n > 0 && !g->row_ptr) return fail(&g_dev_error, QQA_E_ARG, "row_ptr missing");
+  if (problem != QQA_MIS && problem != QQA_MAXCUT) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
+  if (S <= 0 || S > kMaxReplicas) return fail(&g_dev_error, QQA_E_ARG, "S must be in [1, 4096]");
+  if (!size_or_cut || !viol || !obj || !best || (g->n > 0 && !P)) return fail(&g_dev_error, QQA_E_ARG, "output missing");
+  const ReplicaShape r = replica_shape(S);
+  unsigned long long* acc = nullptr;
+  DEV_CHECK(hipMallocAsync((void**)&acc, 2 * (size_t)r.stride * sizeof(unsigned long long), (hipStream_t)stream));
+  EvalParams p{};
+  p.row_ptr = g->row_ptr;
+  p.col = g->col_idx;
+  p.w = problem == QQA_MAXCUT ? g->weight : nullptr;
+  p.dense = g->dense;
+  p.P = P;
+  p.n = g->n;
+  p.S = S;
+  p.stride = r.stride;
+  p.problem = problem;
+  p.lambda = penalty_lambda;
+  p.acc = acc;
+  p.size_or_cut = size_or_cut;
+  p.viol = viol;
+  p.obj = obj;
+  p.best = best;
+  hipError_t e = launch_eval(p, (hipStream_t)stream);
+  hipError_t e2 = hipFreeAsync(acc, (hipStream_t)stream);
+  DEV_CHECK(e);
+  DEV_CHECK(e2);
+  return QQA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+"""Whole solves through the request-level C ABI: result records are self-consistent, the
+discrete objectives are exact for the returned solution, repeated solves are
+deterministic, error paths report the documented codes, and over ten solver seeds the
+solution quality lies within the FP64 oracle's seed-to-seed spread."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import qqa_inputs as qi
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_stats.json")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_02135_amd as q
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+def objective_of(g, x, problem, lam=2):
+    """l(x) written from the energies: MIS -sum x + lam * #edges inside x; max-cut
+    -sum over cut edges of w (units of 2^-16)."""
+    e = qi.edge_list(g)
+    x = x.astype(np.int64)
+    if problem == "mis":
+        return -int(x.sum()) + lam * int(np.sum(x[e[:, 0]] & x[e[:, 1]]))
+    rows = np.repeat(np.arange(g["n"]), np.diff(g["row_ptr"]))
+    keep = rows < g["col"]
+    w = np.rint(g["weight"][keep].astype(np.float64) * 65536).astype(np.int64)
+    return -int(np.sum(w[x[rows[keep]] != x[g["col"][keep]]]))
+
+
+@pytest.mark.parametrize("problem", ["mis", "maxcut"])
+def test_result_record_is_consistent(ctx, problem):
+    g = qi.erdos_renyi(700, 6.0, 2)
+    if problem == "maxcut":
+        g = qi.pm1_weights(g, 3)
+    S = 48
+    res = ctx.poll(ctx.solve(g, problem, S, 400, 5))
+    assert res["obj"].shape == (S,)
+    if problem == "mis":
+        assert np.array_equal(res["obj"], -res["size_or_cut"] + 2 * res["viol"])
+    else:
+        assert np.array_equal(res["obj"], -res["size_or_cut"]) and not res["viol"].any()
+    b = res["best_replica"]
+    key = [(int(res["viol"][s] > 0), int(res["obj"][s]), s) for s in range(S)]
+    assert min(key)[2] == b
+    assert res["best_objective"] == res["obj"][b] == objective_of(g, res["best_x"], problem)
+    assert res["feasible"] == (res["viol"][b] == 0)
+    assert res["device_ms"] > 0 and res["step_loop_ms"] > 0 and res["step_loop_ms"] <= res["device_ms"]
+
+
+def test_repeated_solves_are_bitwise_identical(ctx):
+    g = qi.pm1_weights(qi.barabasi_albert(3000, 4, 5), 6)
+    gid = ctx.upload(g, "maxcut")
+    a = ctx.poll(ctx.solve_resident(gid, g["n"], "maxcut", 128, 300, 11))
+    b = ctx.poll(ctx.solve_resident(gid, g["n"], "maxcut", 128, 300, 11))
+    c = ctx.poll(ctx.solve_resident(gid, g["n"], "maxcut", 128, 300, 12))
+    ctx.release(gid)
+    assert np.array_equal(a["obj"], b["obj"]) and np.array_equal(a["best_x"], b["best_x"])
+    assert not np.array_equal(a["obj"], c["obj"])
+
+
+def test_pipelined_requests_and_nonblocking_poll(ctx):
+    g = qi.erdos_renyi(5000, 5.0, 7)
+    gid = ctx.upload(g, "mis")
+    ids = [ctx.solve_resident(gid, g["n"], "mis", 64, 200, s) for s in range(4)]
+    first = ctx.poll(ids[-1], timeout_us=0)  # probably still running; either answer is valid
+    results = [ctx.poll(i) if not (i == ids[-1] and first is not None) else first for i in ids]
+    ctx.release(gid)
+    for r in results:
+        assert r["feasible"] or r["best_violations"] > 0
+    alone = ctx.poll(ctx.solve(g, "mis", 64, 200, 2))
+    assert np.array_equal(alone["obj"], results[2]["obj"])
+
+
+def test_error_codes(ctx):
+    import paper_2409_02135_amd as q
+    g = qi.erdos_renyi(100, 3.0, 1)
+    bad = dict(g)
+    bad["col"] = g["col"].copy()
+    bad["col"][0] = 100
+    with pytest.raises(q.QQAError) as e:
+        ctx.solve(bad, "mis", 8, 10, 0)
+    assert e.value.code == q.QQA_E_GRAPH
+    with pytest.raises(q.QQAError) as e:
+        ctx.solve(g, "mis", 0, 10, 0)
+    assert e.value.code == q.QQA_E_ARG
+    with pytest.raises(q.QQAError) as e:
+        ctx.solve(g, "mis", 8, 10, 0, sched=q.schedule("mis", 100, entropy_alpha=3))
+    assert e.value.code == q.QQA_E_ARG
+    small = q.Context(0, hbm_budget=1 << 20)
+    with pytest.raises(q.QQAError) as e:
+        small.solve(qi.erdos_renyi(20000, 5.0, 0), "mis", 256, 10, 0)
+    assert e.value.code == q.QQA_E_ADMISSION
+    small.close()
+    rid = ctx.solve(g, "mis", 8, 50, 0)
+    ctx.cancel(rid)
+    with pytest.raises(q.QQAError) as e:
+        ctx.poll(rid)
+    assert e.value.code == q.QQA_E_CANCELLED
+    ctx._pending[12345] = (1, 1)
+    with pytest.raises(q.QQAError) as e:
+        ctx.poll(12345)
+    assert e.value.code == q.QQA_E_UNKNOWN_REQ
+
+
+def _graph_for(recipe):
+    kind, n, d, gseed, problem, S, K = recipe
+    if kind == "rrg":
+        g = qi.random_regular(n, d, gseed)
+    elif kind == "er":
+        g = qi.erdos_renyi(n, d, gseed)
+    else:
+        g = qi.barabasi_albert(n, d, gseed)
+    if problem == "maxcut":
+        g = qi.pm1_weights(g, gseed + 1)
+    return g, problem, S, K
+
+
+@pytest.mark.parametrize("workload", ["rrg256_d3_mis_S16_K2000", "er2000_d5_mis_S256_K1000",
+                                      "ba2000_m4_pm1_maxcut_S128_K1000"])
+def test_ten_seed_quality_within_oracle_spread(ctx, workload):
+    gold = json.load(open(GOLD))["workloads"][workload]
+    g, problem, S, K = _graph_for(gold["recipe"])
+    ref_best = np.array([gold["seeds"][str(s)]["best_objective"] for s in range(10)], np.float64)
+    ref_mean = np.array([gold["seeds"][str(s)]["mean_objective"] for s in range(10)], np.float64)
+    gid = ctx.upload(g, problem)
+    ids = [ctx.solve_resident(gid, g["n"], problem, S, K, s) for s in range(10)]
+    res = [ctx.poll(i) for i in ids]
+    ctx.release(gid)
+    best = np.array([r["best_objective"] for r in res], np.float64)
+    mean = np.array([r["obj"].mean() for r in res], np.float64)
+    for r in res:
+        assert r["best_objective"] == objective_of(g, r["best_x"], problem)
+    # the GPU's 10-seed means lie inside the oracle's [min, max] over its 10 seeds
+    assert ref_best.min() <= best.mean() <= ref_best.max(), (best, ref_best)
+    assert ref_mean.min() <= mean.mean() <= ref_mean.max(), (mean, ref_mean)
+    # Welch t statistic, reported
+    t = (best.mean() - ref_best.mean()) / np.sqrt(best.var(ddof=1) / 10 + ref_best.var(ddof=1) / 10 + 1e-12)
+    print(f"{workload}: gpu best {best.mean():.2f} oracle {ref_best.mean():.2f} welch t {t:.2f}")
