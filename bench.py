@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--updates", type=int, default=0,
+                    help="override the updates per solve (short runs under hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is "
@@ -103,6 +105,8 @@ def main():
     import paper_2409_02135_amd as q
 
     family, n, d, problem, S, K = WORKLOADS[args.workload]
+    if args.updates > 0:
+        K = args.updates
     g = make_graph(family, n, d, problem)
     nnz = int(g["col"].size)
     ctx = q.Context(0)

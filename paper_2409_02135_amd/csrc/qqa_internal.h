@@ -45,6 +45,7 @@ struct StepParams {
   float beta1, omb1, beta2, omb2, eps;
   float noise_scale;       // sqrt(2 lr T)
   float ce;                // -2 alpha_e gamma_t
+  float inv_S;             // 1 / S
   float inv_bc1, inv_bc2;  // 1 / (1 - beta^k)
   uint32_t key0, key1;     // Philox key = seed
   uint32_t k;              // update count t + 1 (Philox counter word 2)

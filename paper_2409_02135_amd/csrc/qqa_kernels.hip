@@ -22,14 +22,15 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
                                             uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    // 32x32 -> 64-bit products: one v_mad_u64_u32 each gives both halves
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = lo1;
+    c1 = (uint32_t)p1;
     c2 = n2;
-    c3 = lo0;
+    c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -39,14 +40,16 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 // odd multiples of 2^-24 in (0,1): exact in binary32
 __device__ __forceinline__ float u01(uint32_t r) { return (float)((r >> 8) | 1u) * 0x1.0p-24f; }
 
-// Box-Muller on (u0,u1), (u2,u3): angle 2*pi*u as sincospi(2u).
+// Box-Muller on (u0,u1), (u2,u3) with the hardware transcendental units:
+// R = sqrt(-2 ln u) = sqrt(-2 ln2 * log2 u) (v_log_f32, v_sqrt_f32); the angle 2 pi u is
+// passed to v_sin_f32 / v_cos_f32 in revolutions (their argument is scaled by 2 pi).
 __device__ __forceinline__ float4 normals4(U4 r) {
-  const float R1 = sqrtf(-2.0f * logf(u01(r.x)));
-  const float R2 = sqrtf(-2.0f * logf(u01(r.z)));
-  float s1, c1, s2, c2;
-  sincospif(2.0f * u01(r.y), &s1, &c1);
-  sincospif(2.0f * u01(r.w), &s2, &c2);
-  return make_float4(R1 * c1, R1 * s1, R2 * c2, R2 * s2);
+  const float m2ln2 = -1.38629436111989061883f;  // -2 ln 2
+  const float R1 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01(r.x)));
+  const float R2 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01(r.z)));
+  const float a1 = u01(r.y), a2 = u01(r.w);
+  return make_float4(R1 * __builtin_amdgcn_cosf(a1), R1 * __builtin_amdgcn_sinf(a1), R2 * __builtin_amdgcn_cosf(a2),
+                     R2 * __builtin_amdgcn_sinf(a2));
 }
 
 __global__ void philox_kernel(uint32_t k0, uint32_t k1, int n, int nquads, uint32_t k, uint32_t sid, uint32_t* out) {
@@ -107,10 +110,28 @@ __device__ __forceinline__ float ipow_odd(float z, int e) {
   return r;
 }
 
-template <int LPR, int QPL>
+// FULL: S == 4 * LPR * QPL, every lane owns whole, valid quads (no replica masks).
+template <int LPR, int QPL, bool FULL>
 __device__ __forceinline__ void update_row(const StepParams& a, const int row, const int gl) {
-  const int nq = (a.S + 3) >> 2;
+  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
   const bool maxcut = a.problem == kMAXCUT;
+  const bool adam = a.rule == kADAMW;
+  const size_t base = (size_t)row * a.stride;
+
+  // own row first, so its loads overlap the neighbour gathers below
+  float4 p[QPL], mm[QPL], vv[QPL];
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+    p[k] = mm[k] = vv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (FULL || q < nq) {
+      p[k] = *reinterpret_cast<const float4*>(a.P_in + base + 4 * q);
+      if (adam) {
+        mm[k] = *reinterpret_cast<const float4*>(a.m + base + 4 * q);
+        vv[k] = *reinterpret_cast<const float4*>(a.v + base + 4 * q);
+      }
+    }
+  }
 
   // (1) coupling product C_i = sum_j A_ij p_j (MIS) or sum_j A_ij (2 p_j - 1) (max-cut),
   //     accumulated in CSR order so that the rounding sequence depends on the graph only
@@ -121,7 +142,7 @@ __device__ __forceinline__ void update_row(const StepParams& a, const int row, c
 #pragma unroll
     for (int k = 0; k < QPL; ++k) {
       const int q = gl + LPR * k;
-      if (q < nq) acc[k] = *reinterpret_cast<const float4*>(a.coupling + (size_t)row * a.stride + 4 * q);
+      if (FULL || q < nq) acc[k] = *reinterpret_cast<const float4*>(a.coupling + base + 4 * q);
     }
   } else {
     const int rs = a.row_ptr[row], re = a.row_ptr[row + 1];
@@ -141,7 +162,7 @@ __device__ __forceinline__ void update_row(const StepParams& a, const int row, c
 #pragma unroll
         for (int k = 0; k < QPL; ++k) {
           const int q = gl + LPR * k;
-          if (q < nq) {
+          if (FULL || q < nq) {
             float4 x = *reinterpret_cast<const float4*>(pj + 4 * q);
             if (maxcut) {
               x.x = 2.f * x.x - 1.f;
@@ -159,50 +180,37 @@ __device__ __forceinline__ void update_row(const StepParams& a, const int row, c
     }
   }
 
-  // (2) own row and the replica statistics mu_i, sigma_i (two-pass, population STD)
-  const size_t base = (size_t)row * a.stride;
-  const bool adam = a.rule == kADAMW;
-  float4 p[QPL], mm[QPL], vv[QPL];
+  // (2) replica statistics mu_i, sigma_i (two passes, population STD)
   float sum = 0.f;
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int q = gl + LPR * k;
-    p[k] = mm[k] = vv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (q < nq) {
-      p[k] = *reinterpret_cast<const float4*>(a.P_in + base + 4 * q);
-      if (adam) {
-        mm[k] = *reinterpret_cast<const float4*>(a.m + base + 4 * q);
-        vv[k] = *reinterpret_cast<const float4*>(a.v + base + 4 * q);
-      }
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (4 * q + c < a.S) sum += comp(p[k], c);
-    }
+    for (int c = 0; c < 4; ++c)
+      if (FULL || 4 * q + c < a.S) sum += comp(p[k], c);
   }
   sum = group_sum<LPR>(sum);
-  const float mu = sum / (float)a.S;
+  const float mu = sum * a.inv_S;
   float sq = 0.f;
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int q = gl + LPR * k;
-    if (q < nq) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (4 * q + c < a.S) {
-          const float d = comp(p[k], c) - mu;
-          sq = fmaf(d, d, sq);
-        }
-    }
+    for (int c = 0; c < 4; ++c)
+      if (FULL || 4 * q + c < a.S) {
+        const float d = comp(p[k], c) - mu;
+        sq = fmaf(d, d, sq);
+      }
   }
   sq = group_sum<LPR>(sq);
-  const float sigma = sqrtf(sq / (float)a.S);
-  const float cg = sigma > 0.f ? -a.comm_alpha / sigma : 0.f;
+  const float sigma = __builtin_amdgcn_sqrtf(sq * a.inv_S);
+  const float cg = sigma > 0.f ? -a.comm_alpha * __builtin_amdgcn_rcpf(sigma) : 0.f;
 
   // (3) gradient, step, noise, clamp
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int q = gl + LPR * k;
-    if (q >= nq) continue;
+    if (!FULL && q >= nq) continue;
     const float4 xi = normals4(philox4x32_10((uint32_t)row, (uint32_t)q, a.k, kStreamNoise, a.key0, a.key1));
     float4 po, mo, vo;
 #pragma unroll
@@ -216,17 +224,16 @@ __device__ __forceinline__ void update_row(const StepParams& a, const int row, c
       const float g = gf + ge + gc;
       float pn, mn = 0.f, vn = 0.f;
       if (adam) {
-        pn = pc * a.wd_factor;
         mn = fmaf(a.beta1, comp(mm[k], c), a.omb1 * g);
         vn = fmaf(a.beta2, comp(vv[k], c), a.omb2 * (g * g));
-        const float den = sqrtf(vn * a.inv_bc2) + a.eps;
-        pn = pn - a.lr * (mn * a.inv_bc1) / den;
+        const float den = __builtin_amdgcn_sqrtf(vn * a.inv_bc2) + a.eps;
+        pn = pc * a.wd_factor - a.lr * (mn * a.inv_bc1) * __builtin_amdgcn_rcpf(den);
       } else {
         pn = pc - a.lr * g;
       }
       pn = fmaf(a.noise_scale, comp(xi, c), pn);
       pn = fminf(fmaxf(pn, 0.f), 1.f);
-      const bool valid = 4 * q + c < a.S;
+      const bool valid = FULL || 4 * q + c < a.S;
       set_comp(po, c, valid ? pn : 0.f);
       set_comp(mo, c, valid ? mn : 0.f);
       set_comp(vo, c, valid ? vn : 0.f);
@@ -239,11 +246,14 @@ __device__ __forceinline__ void update_row(const StepParams& a, const int row, c
   }
 }
 
-template <int LPR, int QPL>
+template <int LPR, int QPL, bool FULL>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepParams a) {
-  const int row = (int)(((long long)blockIdx.x * kBlock + threadIdx.x) / LPR);
+  int row = (int)(((long long)blockIdx.x * kBlock + threadIdx.x) / LPR);
+  // a whole wavefront serves one row when LPR = 64: make that explicit so the CSR reads
+  // become scalar loads and neighbour addresses a scalar base plus the lane offset
+  if (LPR == 64) row = __builtin_amdgcn_readfirstlane(row);
   if (row >= a.n) return;  // whole LPR-lane groups leave together
-  update_row<LPR, QPL>(a, row, threadIdx.x & (LPR - 1));
+  update_row<LPR, QPL, FULL>(a, row, threadIdx.x & (LPR - 1));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -424,7 +434,11 @@ hipError_t launch_init(uint64_t seed, int n, int S, float* P, float* m, float* v
 
 template <int LPR, int QPL>
 static void launch_step_t(const StepParams& p, hipStream_t st) {
-  hipLaunchKernelGGL((step_kernel<LPR, QPL>), dim3(grid_for((long long)p.n * LPR)), dim3(kBlock), 0, st, p);
+  const dim3 grid(grid_for((long long)p.n * LPR)), block(kBlock);
+  if (p.S == 4 * LPR * QPL)
+    hipLaunchKernelGGL((step_kernel<LPR, QPL, true>), grid, block, 0, st, p);
+  else
+    hipLaunchKernelGGL((step_kernel<LPR, QPL, false>), grid, block, 0, st, p);
 }
 
 hipError_t launch_step(const StepParams& p, hipStream_t st) {

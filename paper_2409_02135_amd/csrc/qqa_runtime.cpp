@@ -77,6 +77,7 @@ void fill_step_scalars(StepParams& p, const qqa_schedule& s, int t, int K) {
 
 void fill_static_scalars(StepParams& p, const qqa_schedule& s, int problem, int S, uint64_t seed) {
   p.S = S;
+  p.inv_S = (float)(1.0 / (double)S);
   p.stride = replica_shape(S).stride;
   p.problem = problem;
   p.rule = s.rule;

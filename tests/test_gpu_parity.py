@@ -14,12 +14,18 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 # ---- per-step tolerance contract ---------------------------------------------------------
-# P in [0,1]: |dP| <= 1e-5.  m, v: |d| <= 1e-5 * max(|ref|, scale of the summed terms).
-# Elements are exempt (and counted) where the float32 result is not determined to that
-# accuracy by the inputs: the oracle's pre-clamp value lies within 1e-5 of 0 or 1, the
-# gradient cancels (|g| < 1e-3 (|gf| + |ge| + |gc|)), or 0 < sigma_i < 1e-3.
+# P in [0,1]: |dP| <= 1e-5 (absolute, i.e. relative to the range of P).  The clamp is
+# 1-Lipschitz, so it needs no exemption.  m, v: |d| <= 1e-5 * max(|ref|, scale of the summed
+# terms), the terms being (1-b1) (|gf| + |ge| + |gc|) for m and (1-b2) (|gf| + |ge| + |gc|)^2
+# for v, because a float32 gradient carries an absolute error of a few ulp of that sum.
+# Elements are exempt (and counted) where float32 cannot determine the result from the
+# inputs: the gradient cancels to below 1e-5 of its summed terms (AdamW's normalisation
+# turns its sign into a full step), or 0 < sigma_i < 1e-4 (the STD term divides the
+# rounding error of p - mu by sigma).
 TOL_P = 1e-5
 TOL_REL = 1e-5
+CANCEL = 1e-5
+SIGMA_MIN = 1e-4
 MAX_EXEMPT_FRAC = 1e-4
 
 
@@ -64,25 +70,26 @@ def oracle_params(orc, q, sched, problem):
 
 def check_step(label, gpu, ref, S, adam, beta1, beta2):
     Pg, mg, vg = (x[:, :S].astype(np.float64) for x in gpu)
-    stride_pad = gpu[0][:, S:]
-    assert np.all(stride_pad == 0.0), f"{label}: padding replicas not zero"
+    assert np.all(gpu[0][:, S:] == 0.0), f"{label}: padding replicas not zero"
     assert np.all(np.isfinite(Pg)) and Pg.min() >= 0 and Pg.max() <= 1, f"{label}: P out of box"
-    pre, g, gabs, sig = ref["pre_clamp"], ref["g"], ref["gabs"], ref["sigma"][:, None]
-    exempt = ((np.abs(pre) < TOL_P) | (np.abs(pre - 1.0) < TOL_P) | (np.abs(g) < 1e-3 * gabs)
-              | ((sig > 0) & (sig < 1e-3)))
+    g, gabs, sig = ref["g"], ref["gabs"], ref["sigma"][:, None]
+    exempt = (np.abs(g) < CANCEL * gabs) | ((sig > 0) & (sig < SIGMA_MIN))
     n_ex = int(exempt.sum())
-    assert n_ex <= max(2, MAX_EXEMPT_FRAC * exempt.size), f"{label}: {n_ex} exempt of {exempt.size}"
     ok = ~exempt
     dP = np.abs(Pg - ref["P"])[ok]
-    assert dP.size == 0 or dP.max() <= TOL_P, f"{label}: max |dP| = {dP.max():.3g}"
+    stats = {"exempt": n_ex, "of": int(exempt.size), "max_dP": float(dP.max()) if dP.size else 0.0}
     if adam:
-        dm = np.abs(mg - ref["m"])[ok]
         sm = np.maximum(np.abs(ref["m"]), (1 - beta1) * gabs)[ok]
-        assert np.all(dm <= TOL_REL * sm), f"{label}: m rel err {np.max(dm / sm):.3g}"
-        dv = np.abs(vg - ref["v"])[ok]
         sv = np.maximum(np.abs(ref["v"]), (1 - beta2) * gabs * gabs)[ok]
-        assert np.all(dv <= TOL_REL * sv), f"{label}: v rel err {np.max(dv / sv):.3g}"
-    return n_ex, float(dP.max()) if dP.size else 0.0
+        rm = np.abs(mg - ref["m"])[ok] / sm
+        rv = np.abs(vg - ref["v"])[ok] / sv
+        stats.update(max_rel_m=float(rm.max()) if rm.size else 0.0, max_rel_v=float(rv.max()) if rv.size else 0.0)
+    print(label, stats)
+    assert n_ex <= max(2, MAX_EXEMPT_FRAC * exempt.size), f"{label}: {stats}"
+    assert stats["max_dP"] <= TOL_P, f"{label}: {stats}"
+    if adam:
+        assert stats["max_rel_m"] <= TOL_REL and stats["max_rel_v"] <= TOL_REL, f"{label}: {stats}"
+    return stats
 
 
 # ---- Philox / noise / init -------------------------------------------------------------------
