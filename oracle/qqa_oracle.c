@@ -287,10 +287,33 @@ void orc_grad(const orc_params *pr, const orc_graph *g, int32_t S, const double 
     }
 }
 
+/* Sum of the magnitudes of every term that makes up the objective gradient gf of replica
+   s at variable i: 1 + lambda sum_j |A_ij p_j| (MIS) or sum_j |A_ij (2 p_j - 1)| (max-cut).
+   A diagnostic for comparisons: it sets the scale of the rounding error of any
+   finite-precision evaluation of gf. */
+static double objective_term_magnitude(const orc_params *pr, const orc_graph *g, int32_t S, const double *P,
+                                       int32_t i, int32_t s) {
+    const int32_t n = g->n;
+    double acc = pr->problem == ORC_MIS ? 1.0 : 0.0;
+    const double scale = pr->problem == ORC_MIS ? pr->lambda : 1.0;
+    if (g->dense) {
+        for (int32_t j = 0; j < n; ++j) {
+            double pj = P[(size_t)j * S + s];
+            acc += scale * fabs(g->W[(size_t)i * n + j] * (pr->problem == ORC_MIS ? pj : 2.0 * pj - 1.0));
+        }
+    } else {
+        for (int64_t e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e) {
+            double pj = P[(size_t)g->col[e] * S + s];
+            acc += scale * fabs(edge_weight(g, e) * (pr->problem == ORC_MIS ? pj : 2.0 * pj - 1.0));
+        }
+    }
+    return acc;
+}
+
 /* ---- one update (Sensitive Transitions, Eq. 11, with AdamW in place of the plain step) ---
    t is the 0-based update index (AdamW step count k = t + 1), K the schedule length.
    Optional diagnostics (n*S): pre_clamp = value before the clamp, gsum = g,
-   gabs = |gf| + |ge| + |gc|;  sigma (n).                                                   */
+   gabs = (magnitude of all terms of gf) + |ge| + |gc|;  sigma (n).                         */
 void orc_step(const orc_params *pr, const orc_graph *g, int32_t S, int32_t t, int32_t K, uint64_t seed,
               const double *P_in, double *P_out, double *m, double *v,
               double *pre_clamp, double *gsum, double *gabs, double *sigma) {
@@ -323,7 +346,9 @@ void orc_step(const orc_params *pr, const orc_graph *g, int32_t S, int32_t t, in
         p = p + noise_scale * xi[e]; /* sqrt(2 eta T) xi */
         if (pre_clamp) pre_clamp[e] = p;
         if (gsum) gsum[e] = grad;
-        if (gabs) gabs[e] = fabs(gf[e]) + fabs(ge[e]) + fabs(gc[e]);
+        if (gabs)
+            gabs[e] = objective_term_magnitude(pr, g, S, P_in, (int32_t)(e / (size_t)S), (int32_t)(e % (size_t)S)) +
+                      fabs(ge[e]) + fabs(gc[e]);
         P_out[e] = p < 0.0 ? 0.0 : (p > 1.0 ? 1.0 : p); /* sigma = Clamp to [0,1] */
     }
     free(gf); free(ge); free(gc); free(xi);

@@ -60,6 +60,14 @@ int upload_graph(qqa_ctx* c, const qqa_graph& g, int problem, DevGraph* out, std
     if (e == hipSuccess) e = dev_copy((void**)&d.col, g.col_idx, (size_t)g.nnz * sizeof(int32_t));
     if (e == hipSuccess && problem == QQA_MAXCUT && g.weight)
       e = dev_copy((void**)&d.w, g.weight, (size_t)g.nnz * sizeof(float));
+    std::vector<HubChunk> chunks;
+    std::vector<int32_t> hub_first;
+    build_hub_plan(rp.data(), g.n, &chunks, &hub_first);
+    if (e == hipSuccess && !chunks.empty()) {
+      d.nchunks = (int)chunks.size();
+      e = dev_copy((void**)&d.chunks, chunks.data(), chunks.size() * sizeof(HubChunk));
+      if (e == hipSuccess) e = dev_copy((void**)&d.hub_first, hub_first.data(), hub_first.size() * sizeof(int32_t));
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host arrays may go away on return
   }
   if (e == hipSuccess && g.dense) e = hipStreamSynchronize(c->stream);
@@ -77,6 +85,8 @@ void free_graph(DevGraph& d) {
   if (d.col) (void)hipFree(d.col);
   if (d.w) (void)hipFree(d.w);
   if (d.dense) (void)hipFree(d.dense);
+  if (d.chunks) (void)hipFree(d.chunks);
+  if (d.hub_first) (void)hipFree(d.hub_first);
   d = DevGraph{};
 }
 
@@ -90,7 +100,7 @@ void graph_unref(qqa_ctx* c, int64_t gid) {
   }
 }
 
-int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why) {
+int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks) {
   const size_t state = (size_t)r->n * r->shape.stride * sizeof(float);
   const bool adam = r->sched.rule == QQA_STEP_ADAMW;
   hipError_t e = hipSuccess;
@@ -104,6 +114,8 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why) {
     get((void**)&r->v, state);
   }
   get((void**)&r->acc, 2 * (size_t)r->shape.stride * sizeof(unsigned long long));
+  r->hub_bytes = (size_t)nchunks * r->shape.stride * sizeof(float);
+  if (nchunks) get((void**)&r->hub_partial, r->hub_bytes);
   r->out_size = out_bytes(r->n, r->S);
   get((void**)&r->out_dev, r->out_size);
   if (e == hipSuccess) e = c->hpool.get(r->out_size, (void**)&r->out_host);
@@ -123,6 +135,8 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
   c->dpool.put(r->m, state);
   c->dpool.put(r->v, state);
   c->dpool.put(r->acc, 2 * (size_t)r->shape.stride * sizeof(unsigned long long));
+  c->dpool.put(r->hub_partial, r->hub_bytes);
+  r->hub_partial = nullptr;
   c->dpool.put(r->out_dev, r->out_size);
   c->hpool.put(r->out_host, r->out_size);
   r->P[0] = r->P[1] = r->m = r->v = nullptr;
@@ -141,6 +155,8 @@ StepParams request_step_params(const Request* r, const DevGraph& g) {
   p.col = g.col;
   p.w = r->problem == QQA_MAXCUT ? g.w : nullptr;
   p.coupling = nullptr;
+  p.hub_first = g.hub_first;
+  p.hub_partial = r->hub_partial;
   p.m = r->m;
   p.v = r->v;
   p.n = r->n;
@@ -207,11 +223,11 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   r->seed = seed;
   r->n = g.n;
   r->shape = replica_shape(S);
-  r->footprint = request_footprint(g.n, S, r->sched.rule);
+  r->footprint = request_footprint(g.n, S, r->sched.rule) + (size_t)g.nchunks * r->shape.stride * sizeof(float);
   if (r->footprint + g.bytes > c->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the HBM budget");
   if (c->in_use + r->footprint > c->budget)
     return set_err(c, QQA_E_NOMEM, "HBM budget held by earlier requests; poll them first");
-  int rc = alloc_request_buffers(c, r.get(), &c->err);
+  int rc = alloc_request_buffers(c, r.get(), &c->err, g.nchunks);
   if (rc) return rc;
   c->in_use += r->footprint;
   g.refs++;
@@ -225,7 +241,8 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
     p.P_in = r->P[t & 1];
     p.P_out = r->P[(t + 1) & 1];
     fill_step_scalars(p, r->sched, t, steps);
-    e = launch_step(p, c->stream);
+    if (g.nchunks) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
+    if (e == hipSuccess) e = launch_step(p, c->stream);
   }
   if (e == hipSuccess) e = hipEventRecord(r->ev[2], c->stream);
   if (e == hipSuccess) e = enqueue_finish(c, r.get(), g, r->P[steps & 1]);

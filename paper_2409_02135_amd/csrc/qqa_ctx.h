@@ -23,6 +23,9 @@ struct DevGraph {
   int32_t* col = nullptr;
   float* w = nullptr;
   float* dense = nullptr;
+  HubChunk* chunks = nullptr;  // split plan of rows above kHubDegree neighbours
+  int32_t* hub_first = nullptr;
+  int nchunks = 0;
   size_t bytes = 0;
   int refs = 0;
   bool release_pending = false;
@@ -45,6 +48,8 @@ struct Request {
   float* m = nullptr;
   float* v = nullptr;
   unsigned long long* acc = nullptr;
+  float* hub_partial = nullptr;  // nchunks x stride
+  size_t hub_bytes = 0;
   char* out_dev = nullptr;
   char* out_host = nullptr;
   size_t out_size = 0;
@@ -82,7 +87,7 @@ void out_views(char* base, int n, int S, int64_t** a, int64_t** b, int64_t** o, 
 int upload_graph(qqa_ctx* c, const qqa_graph& g, int problem, DevGraph* out, std::string* why);
 void free_graph(DevGraph& d);
 void graph_unref(qqa_ctx* c, int64_t gid);
-int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why);
+int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks);
 void release_request_buffers(qqa_ctx* c, Request* r);
 StepParams request_step_params(const Request* r, const DevGraph& g);
 hipError_t enqueue_finish(qqa_ctx* c, Request* r, const DevGraph& g, const float* final_P);

@@ -15,6 +15,10 @@ enum : uint32_t { kStreamInit = 0, kStreamNoise = 1 };
 
 constexpr int kMaxReplicas = 4096;
 constexpr int kBlock = 256;
+// Rows with more than kHubDegree neighbours are split into chunks of kHubChunk edges whose
+// partial coupling sums are computed by their own lane groups (hub_partial_kernel).
+constexpr int kHubDegree = 64;
+constexpr int kHubChunk = 32;
 
 // How the S replicas of one variable map onto lanes: a row is served by `lpr` adjacent
 // lanes (a power of two, at most one wavefront), each lane owns `qpl` float4 quads.
@@ -34,6 +38,8 @@ struct StepParams {
   const int32_t* col;
   const float* w;          // nullptr: unweighted
   const float* coupling;   // dense path: precomputed coupling product, n x stride, or nullptr
+  const int32_t* hub_first;  // per row: first chunk of a split row, -1 otherwise (nullptr: no hubs)
+  const float* hub_partial;  // per chunk: partial coupling sums, nchunks x stride
   const float* P_in;
   float* P_out;
   float* m;
@@ -71,6 +77,14 @@ hipError_t launch_philox(uint64_t seed, int n, int nquads, uint32_t k, uint32_t 
 hipError_t launch_noise(uint64_t seed, int n, int S, uint32_t k, float* xi, hipStream_t st);
 hipError_t launch_init(uint64_t seed, int n, int S, float* P, float* m, float* v, hipStream_t st);
 hipError_t launch_step(const StepParams& p, hipStream_t st);
+
+// Chunks of split rows: {row, first edge}; the chunk ends at min(first + kHubChunk, row end).
+struct HubChunk {
+  int32_t row;
+  int32_t e0;
+};
+// Partial coupling sums of every chunk into p.hub_partial (reads P_in, row_ptr, col, w).
+hipError_t launch_hub_partials(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st);
 hipError_t launch_eval(const EvalParams& p, hipStream_t st);
 hipError_t launch_extract(const float* P, int n, int stride, const int32_t* best, uint8_t* x, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, size_t count, hipStream_t st);

@@ -110,6 +110,67 @@ __device__ __forceinline__ float ipow_odd(float z, int e) {
   return r;
 }
 
+// acc += sum over edges e in [e_begin, e_end) of w_e * f(p_col(e)), in edge order, with
+// f(p) = p (MIS) or 2p - 1 (max-cut); four neighbour rows are loaded per iteration.
+template <int LPR, int QPL, bool FULL>
+__device__ __forceinline__ void gather_coupling(const StepParams& a, const int e_begin, const int e_end, const int gl,
+                                                const int nq, const bool maxcut, float4 (&acc)[QPL]) {
+  for (int e0 = e_begin; e0 < e_end; e0 += 4) {
+    int j[4];
+    float w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u;
+      j[u] = e < e_end ? a.col[e] : -1;
+      w[u] = e < e_end ? (a.w ? a.w[e] : 1.f) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (j[u] < 0) continue;
+      const float* pj = a.P_in + (size_t)j[u] * a.stride;
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+        const int q = gl + LPR * k;
+        if (FULL || q < nq) {
+          float4 x = *reinterpret_cast<const float4*>(pj + 4 * q);
+          if (maxcut) {
+            x.x = 2.f * x.x - 1.f;
+            x.y = 2.f * x.y - 1.f;
+            x.z = 2.f * x.z - 1.f;
+            x.w = 2.f * x.w - 1.f;
+          }
+          acc[k].x = fmaf(w[u], x.x, acc[k].x);
+          acc[k].y = fmaf(w[u], x.y, acc[k].y);
+          acc[k].z = fmaf(w[u], x.z, acc[k].z);
+          acc[k].w = fmaf(w[u], x.w, acc[k].w);
+        }
+      }
+    }
+  }
+}
+
+// Partial coupling sum of one chunk of a split row.
+template <int LPR, int QPL, bool FULL>
+__global__ __launch_bounds__(kBlock) void hub_partial_kernel(StepParams a, const HubChunk* chunks, int nchunks) {
+  int c = (int)(((long long)blockIdx.x * kBlock + threadIdx.x) / LPR);
+  if (LPR == 64) c = __builtin_amdgcn_readfirstlane(c);
+  if (c >= nchunks) return;
+  const int gl = threadIdx.x & (LPR - 1);
+  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
+  const HubChunk ch = chunks[c];
+  const int e_end = min(ch.e0 + kHubChunk, a.row_ptr[ch.row + 1]);
+  float4 acc[QPL];
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  gather_coupling<LPR, QPL, FULL>(a, ch.e0, e_end, gl, nq, a.problem == kMAXCUT, acc);
+  float* out = const_cast<float*>(a.hub_partial) + (size_t)c * a.stride;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+    if (FULL || q < nq) *reinterpret_cast<float4*>(out + 4 * q) = acc[k];
+  }
+}
+
 // FULL: S == 4 * LPR * QPL, every lane owns whole, valid quads (no replica masks).
 template <int LPR, int QPL, bool FULL>
 __device__ __forceinline__ void update_row(const StepParams& a, const int row, const int gl) {
@@ -144,40 +205,26 @@ __device__ __forceinline__ void update_row(const StepParams& a, const int row, c
       const int q = gl + LPR * k;
       if (FULL || q < nq) acc[k] = *reinterpret_cast<const float4*>(a.coupling + base + 4 * q);
     }
-  } else {
-    const int rs = a.row_ptr[row], re = a.row_ptr[row + 1];
-    for (int e0 = rs; e0 < re; e0 += 4) {
-      int j[4];
-      float w[4];
+  } else if (a.hub_first && a.hub_first[row] >= 0) {
+    // split row: partial sums of its chunks, added in chunk order
+    const int first = a.hub_first[row];
+    const int nch = (a.row_ptr[row + 1] - a.row_ptr[row] + kHubChunk - 1) / kHubChunk;
+    for (int c = 0; c < nch; ++c) {
+      const float* part = a.hub_partial + (size_t)(first + c) * a.stride;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + u;
-        j[u] = e < re ? a.col[e] : -1;
-        w[u] = e < re ? (a.w ? a.w[e] : 1.f) : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (j[u] < 0) continue;
-        const float* pj = a.P_in + (size_t)j[u] * a.stride;
-#pragma unroll
-        for (int k = 0; k < QPL; ++k) {
-          const int q = gl + LPR * k;
-          if (FULL || q < nq) {
-            float4 x = *reinterpret_cast<const float4*>(pj + 4 * q);
-            if (maxcut) {
-              x.x = 2.f * x.x - 1.f;
-              x.y = 2.f * x.y - 1.f;
-              x.z = 2.f * x.z - 1.f;
-              x.w = 2.f * x.w - 1.f;
-            }
-            acc[k].x = fmaf(w[u], x.x, acc[k].x);
-            acc[k].y = fmaf(w[u], x.y, acc[k].y);
-            acc[k].z = fmaf(w[u], x.z, acc[k].z);
-            acc[k].w = fmaf(w[u], x.w, acc[k].w);
-          }
+      for (int k = 0; k < QPL; ++k) {
+        const int q = gl + LPR * k;
+        if (FULL || q < nq) {
+          const float4 x = *reinterpret_cast<const float4*>(part + 4 * q);
+          acc[k].x += x.x;
+          acc[k].y += x.y;
+          acc[k].z += x.z;
+          acc[k].w += x.w;
         }
       }
     }
+  } else {
+    gather_coupling<LPR, QPL, FULL>(a, a.row_ptr[row], a.row_ptr[row + 1], gl, nq, maxcut, acc);
   }
 
   // (2) replica statistics mu_i, sigma_i (two passes, population STD)
@@ -439,6 +486,38 @@ static void launch_step_t(const StepParams& p, hipStream_t st) {
     hipLaunchKernelGGL((step_kernel<LPR, QPL, true>), grid, block, 0, st, p);
   else
     hipLaunchKernelGGL((step_kernel<LPR, QPL, false>), grid, block, 0, st, p);
+}
+
+template <int LPR, int QPL>
+static void launch_hub_t(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st) {
+  const dim3 grid(grid_for((long long)nchunks * LPR)), block(kBlock);
+  if (p.S == 4 * LPR * QPL)
+    hipLaunchKernelGGL((hub_partial_kernel<LPR, QPL, true>), grid, block, 0, st, p, chunks, nchunks);
+  else
+    hipLaunchKernelGGL((hub_partial_kernel<LPR, QPL, false>), grid, block, 0, st, p, chunks, nchunks);
+}
+
+hipError_t launch_hub_partials(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st) {
+  if (nchunks == 0) return hipSuccess;
+  const ReplicaShape r = replica_shape(p.S);
+  switch (r.lpr) {
+    case 1: launch_hub_t<1, 1>(p, chunks, nchunks, st); break;
+    case 2: launch_hub_t<2, 1>(p, chunks, nchunks, st); break;
+    case 4: launch_hub_t<4, 1>(p, chunks, nchunks, st); break;
+    case 8: launch_hub_t<8, 1>(p, chunks, nchunks, st); break;
+    case 16: launch_hub_t<16, 1>(p, chunks, nchunks, st); break;
+    case 32: launch_hub_t<32, 1>(p, chunks, nchunks, st); break;
+    default:
+      switch (r.qpl) {
+        case 1: launch_hub_t<64, 1>(p, chunks, nchunks, st); break;
+        case 2: launch_hub_t<64, 2>(p, chunks, nchunks, st); break;
+        case 4: launch_hub_t<64, 4>(p, chunks, nchunks, st); break;
+        case 8: launch_hub_t<64, 8>(p, chunks, nchunks, st); break;
+        case 16: launch_hub_t<64, 16>(p, chunks, nchunks, st); break;
+        default: return hipErrorInvalidValue;
+      }
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_step(const StepParams& p, hipStream_t st) {

@@ -165,6 +165,20 @@ int validate_graph(const qqa_graph& g, int problem, std::string* why) {
   return QQA_OK;
 }
 
+void build_hub_plan(const int32_t* row_ptr, int n, std::vector<HubChunk>* chunks, std::vector<int32_t>* hub_first) {
+  chunks->clear();
+  hub_first->assign(n, -1);
+  bool any = false;
+  for (int i = 0; i < n; ++i) {
+    const int deg = row_ptr[i + 1] - row_ptr[i];
+    if (deg <= kHubDegree) continue;
+    any = true;
+    (*hub_first)[i] = (int32_t)chunks->size();
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; e += kHubChunk) chunks->push_back(HubChunk{i, e});
+  }
+  if (!any) hub_first->clear();
+}
+
 // ---------------------------------------------------------------------------------------
 // device buffer pool: exact-size reuse, so repeated solves of one shape never call
 // hipMalloc / hipFree (both of which synchronise) after the first.
@@ -280,6 +294,7 @@ int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule
   if (g->n > 0 && (!P_in || !P_out)) return fail(&g_dev_error, QQA_E_ARG, "P_in/P_out missing");
   if (P_in == P_out && g->n > 0) return fail(&g_dev_error, QQA_E_ARG, "P_out must not alias P_in");
   if (s.rule == QQA_STEP_ADAMW && g->n > 0 && (!m || !v)) return fail(&g_dev_error, QQA_E_ARG, "AdamW needs m and v");
+  hipStream_t st = (hipStream_t)stream;
   StepParams p{};
   p.row_ptr = g->row_ptr;
   p.col = g->col_idx;
@@ -292,7 +307,36 @@ int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule
   p.n = g->n;
   fill_static_scalars(p, s, problem, S, seed);
   fill_step_scalars(p, s, t, K);
-  DEV_CHECK(launch_step(p, (hipStream_t)stream));
+  if (g->n == 0) return QQA_OK;
+  // the same row split the solver uses: read the row pointers back to plan it
+  std::vector<int32_t> rp(g->n + 1);
+  DEV_CHECK(hipMemcpyAsync(rp.data(), g->row_ptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  DEV_CHECK(hipStreamSynchronize(st));
+  std::vector<HubChunk> chunks;
+  std::vector<int32_t> hub_first;
+  build_hub_plan(rp.data(), g->n, &chunks, &hub_first);
+  HubChunk* d_chunks = nullptr;
+  int32_t* d_first = nullptr;
+  float* d_part = nullptr;
+  if (!chunks.empty()) {
+    DEV_CHECK(hipMallocAsync((void**)&d_chunks, chunks.size() * sizeof(HubChunk), st));
+    DEV_CHECK(hipMallocAsync((void**)&d_first, hub_first.size() * sizeof(int32_t), st));
+    DEV_CHECK(hipMallocAsync((void**)&d_part, chunks.size() * (size_t)p.stride * sizeof(float), st));
+    DEV_CHECK(hipMemcpyAsync(d_chunks, chunks.data(), chunks.size() * sizeof(HubChunk), hipMemcpyHostToDevice, st));
+    DEV_CHECK(hipMemcpyAsync(d_first, hub_first.data(), hub_first.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    p.hub_first = d_first;
+    p.hub_partial = d_part;
+    DEV_CHECK(launch_hub_partials(p, d_chunks, (int)chunks.size(), st));
+  }
+  hipError_t e = launch_step(p, st);
+  if (!chunks.empty()) {
+    (void)hipFreeAsync(d_chunks, st);
+    (void)hipFreeAsync(d_first, st);
+    (void)hipFreeAsync(d_part, st);
+    // host vectors go out of scope: the copies above must have completed
+    DEV_CHECK(hipStreamSynchronize(st));
+  }
+  DEV_CHECK(e);
   return QQA_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <map>
 #include <string>
+#include <vector>
 
 #include "qqa.h"
 #include "qqa_internal.h"
@@ -18,6 +19,8 @@ bool schedule_valid(const qqa_schedule& s, std::string* why);
 void fill_step_scalars(StepParams& p, const qqa_schedule& s, int t, int K);
 void fill_static_scalars(StepParams& p, const qqa_schedule& s, int problem, int S, uint64_t seed);
 int validate_graph(const qqa_graph& g, int problem, std::string* why);
+// Split plan for rows with more than kHubDegree neighbours (see qqa_internal.h).
+void build_hub_plan(const int32_t* row_ptr, int n, std::vector<HubChunk>* chunks, std::vector<int32_t>* hub_first);
 
 // Size-keyed free list over hipMalloc (device) or hipHostMalloc (pinned host).
 class Pool {

@@ -16,8 +16,9 @@ torch = pytest.importorskip("torch")
 # ---- per-step tolerance contract ---------------------------------------------------------
 # P in [0,1]: |dP| <= 1e-5 (absolute, i.e. relative to the range of P).  The clamp is
 # 1-Lipschitz, so it needs no exemption.  m, v: |d| <= 1e-5 * max(|ref|, scale of the summed
-# terms), the terms being (1-b1) (|gf| + |ge| + |gc|) for m and (1-b2) (|gf| + |ge| + |gc|)^2
-# for v, because a float32 gradient carries an absolute error of a few ulp of that sum.
+# terms): G = sum of the magnitudes of every term of the gradient (each neighbour's
+# contribution to gf, then ge and gc), (1-b1) G for m and (1-b2) G^2 for v, because a
+# float32 gradient carries an absolute error of a few ulp of G.
 # Elements are exempt (and counted) where float32 cannot determine the result from the
 # inputs: the gradient cancels to below 1e-5 of its summed terms (AdamW's normalisation
 # turns its sign into a full step), or 0 < sigma_i < 1e-4 (the STD term divides the
@@ -289,3 +290,26 @@ def test_full_size_step_and_eval(orc, shape):
     for k in ("size_or_cut", "viol", "obj"):
         assert np.array_equal(got[k], ref_e[k]), k
     assert got["best"] == ref_e["best"]
+
+
+@pytest.mark.parametrize("S", [4, 16, 128, 256, 600])
+def test_step_parity_split_hub_rows(orc, S):
+    """Rows above the split threshold (a 3000-neighbour hub, and mid-size hubs) take the
+    chunked partial-sum path."""
+    n = 3001
+    er = qi.edge_list(qi.erdos_renyi(n, 4.0, 9))
+    hub = np.stack([np.zeros(n - 1, np.int64), np.arange(1, n, dtype=np.int64)], axis=1)
+    mid = np.stack([np.full(200, 7, np.int64), np.arange(1000, 1200, dtype=np.int64)], axis=1)
+    e = np.concatenate([hub, mid, er])
+    e = np.stack([e.min(1), e.max(1)], 1)
+    e = np.unique(e, axis=0)
+    e = e[e[:, 0] != e[:, 1]]
+    for problem in ("mis", "maxcut"):
+        g = qi.csr_from_edges(n, e, np.where(np.arange(len(e)) % 3 == 0, -1.0, 1.0).astype(np.float32)
+                              if problem == "maxcut" else None)
+        q = qqa()
+        sched = q.schedule(problem, n)
+        P, m, v = qi.synthetic_state(n, S, seed=S)
+        gpu = run_gpu_step(q, g, problem, sched, S, 5, 50, 3, P, m, v)
+        ref = orc.step(oracle_params(orc, q, sched, problem), g, 5, 50, 3, P, m, v)
+        check_step(f"hub/{problem}/S{S}", gpu, ref, S, True, sched.beta1, sched.beta2)
