@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lanes", type=int, default=-1,
+                    help="replica layout (lanes per row); -1 = autotune before timing, 0 = default")
     ap.add_argument("--updates", type=int, default=0,
                     help="override the updates per solve (short runs under hardware counters)")
     args = ap.parse_args()
@@ -111,7 +113,10 @@ def main():
     nnz = int(g["col"].size)
     ctx = q.Context(0)
     gid = ctx.upload(g, problem)
-    print(f"# workload {args.workload}: n={n} nnz={nnz} S={S} updates={K}", file=sys.stderr, flush=True)
+    lanes = ctx.autotune(gid, problem, S) if args.lanes < 0 else args.lanes
+    ctx.set_replica_layout(S, lanes)
+    print(f"# workload {args.workload}: n={n} nnz={nnz} S={S} updates={K} lanes_per_row={lanes}",
+          file=sys.stderr, flush=True)
 
     for w in range(args.warmup):
         ctx.poll(ctx.solve_resident(gid, n, problem, S, K, 1000 + w), want_x=False)
@@ -149,7 +154,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "problem": problem, "graph": family, "n": n, "nnz": nnz,
                    "degree_param": d, "S": S, "updates_per_solve": K, "graph_seed": 0,
-                   "parallelism": "single GPU"},
+                   "lanes_per_row": lanes, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(dev_ms, 50)), "p99": float(np.percentile(dev_ms, 99)),
                        "basis": "device time per solve (events on the solver stream)"},
         "roofline": {"bound": "hbm", "kernel": "step_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -153,6 +153,20 @@ int qqa_solve_batch(qqa_ctx *c, int32_t count, const qqa_graph_id *graphs, const
                     const qqa_schedule *sched, const int32_t *S, const int32_t *steps,
                     const uint64_t *seeds, qqa_req *out_ids);
 
+/* Replica layout: how many adjacent lanes of a 64-lane wavefront serve the S replicas of
+ * one variable (a power of two <= 64; each lane then owns ceil(S / (4 * lanes)) float4
+ * quads, and a wavefront serves 64 / lanes variables).  The layout changes only the
+ * summation order of the cross-replica mean and STD (a fixed tree per layout).  A context
+ * applies one layout per S to all of its solves -- plain, batched and served -- so a
+ * result never depends on which form ran it.  lanes_per_row = 0 restores the default
+ * (the fewest quads per lane).  Set it before submitting solves with that S. */
+int qqa_set_replica_layout(qqa_ctx *c, int32_t S, int32_t lanes_per_row);
+
+/* Autotuner: time every supported layout for S on an uploaded graph (a few updates each,
+ * on scratch state), keep the fastest for S in this context and return it in
+ * *lanes_per_row (may be NULL). */
+int qqa_autotune(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, int32_t S, int32_t *lanes_per_row);
+
 /* Wait up to timeout_us (0 = do not wait, < 0 = forever) for a request.  Returns QQA_OK
  * and fills *out when done (the handle is then released), QQA_PENDING if still
  * running, or an error. */
@@ -201,10 +215,12 @@ int qqa_dev_init(uint64_t seed, int32_t n, int32_t S, float *P, float *m, float 
 
 /* One update t (0-based, AdamW step count t+1) of a K-update schedule:
  * reads P_in, writes P_out (must not alias P_in: neighbours read P_in), updates m, v in
- * place.  Sparse or dense coupling per `g`. */
+ * place.  lanes_per_row selects the replica layout (0 = default; see
+ * qqa_set_replica_layout).  Rows of more than 64 neighbours are split into 32-edge chunks
+ * whose partial sums are added in chunk order, as in every solve. */
 int qqa_dev_step(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule *sched, int32_t S,
                  int32_t t, int32_t K, uint64_t seed, const float *P_in, float *P_out, float *m,
-                 float *v, void *stream);
+                 float *v, int32_t lanes_per_row, void *stream);
 
 /* Round x = [P > 1/2] and evaluate every replica exactly.  Outputs are device arrays:
  * size_or_cut[S], viol[S], obj[S] (int64) and best[1] (int32). */

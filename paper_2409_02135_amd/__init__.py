@@ -89,7 +89,9 @@ def lib():
             "qqa_dev_philox": (C.c_int, [u64, i32, i32, u32, u32, vp, vp]),
             "qqa_dev_noise": (C.c_int, [u64, i32, i32, u32, vp, vp]),
             "qqa_dev_init": (C.c_int, [u64, i32, i32, vp, vp, vp, vp]),
-            "qqa_dev_step": (C.c_int, [vp, i32, vp, i32, i32, i32, u64, vp, vp, vp, vp, vp]),
+            "qqa_dev_step": (C.c_int, [vp, i32, vp, i32, i32, i32, u64, vp, vp, vp, vp, i32, vp]),
+            "qqa_set_replica_layout": (C.c_int, [vp, i32, i32]),
+            "qqa_autotune": (C.c_int, [vp, i64, i32, i32, vp]),
             "qqa_dev_eval": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
@@ -181,9 +183,11 @@ def qqa_dev_init(seed, n, S, P, m=None, v=None, stream=None):
     return _dev_check(lib().qqa_dev_init(seed, n, S, _ptr(P), _ptr(m), _ptr(v), _stream(stream)))
 
 
-def qqa_dev_step(g: DevGraph, problem, sched: qqa_schedule | None, S, t, K, seed, P_in, P_out, m, v, stream=None):
+def qqa_dev_step(g: DevGraph, problem, sched: qqa_schedule | None, S, t, K, seed, P_in, P_out, m, v,
+                 lanes_per_row=0, stream=None):
     return _dev_check(lib().qqa_dev_step(C.byref(g.struct), PROBLEMS[problem], None if sched is None else C.byref(sched),
-                                         S, t, K, seed, _ptr(P_in), _ptr(P_out), _ptr(m), _ptr(v), _stream(stream)))
+                                         S, t, K, seed, _ptr(P_in), _ptr(P_out), _ptr(m), _ptr(v), lanes_per_row,
+                                         _stream(stream)))
 
 
 def qqa_dev_eval(g: DevGraph, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best, stream=None):
@@ -249,6 +253,14 @@ class Context:
         gid = C.c_int64()
         self._check(lib().qqa_graph_upload(self._c, C.byref(st), PROBLEMS[problem], C.byref(gid)))
         return gid.value
+
+    def set_replica_layout(self, S: int, lanes_per_row: int):
+        self._check(lib().qqa_set_replica_layout(self._c, S, lanes_per_row))
+
+    def autotune(self, gid: int, problem, S: int) -> int:
+        out = C.c_int32()
+        self._check(lib().qqa_autotune(self._c, gid, PROBLEMS[problem], S, C.byref(out)))
+        return out.value
 
     def release(self, gid: int):
         self._check(lib().qqa_graph_release(self._c, gid))

@@ -161,6 +161,7 @@ StepParams request_step_params(const Request* r, const DevGraph& g) {
   p.v = r->v;
   p.n = r->n;
   fill_static_scalars(p, r->sched, r->problem, r->S, r->seed);
+  p.lanes_per_row = r->lanes_per_row;
   return p;
 }
 
@@ -223,6 +224,7 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   r->seed = seed;
   r->n = g.n;
   r->shape = replica_shape(S);
+  r->lanes_per_row = c->layout_for(S);
   r->footprint = request_footprint(g.n, S, r->sched.rule) + (size_t)g.nchunks * r->shape.stride * sizeof(float);
   if (r->footprint + g.bytes > c->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the HBM budget");
   if (c->in_use + r->footprint > c->budget)
@@ -355,6 +357,70 @@ int qqa_solve_resident(qqa_ctx* c, qqa_graph_id g, qqa_problem problem, const qq
   if (rc) return rc;
   (void)hipSetDevice(c->device);
   return submit_plain(c, g, false, problem, sched, S, steps, seed, out_id);
+}
+
+int qqa_set_replica_layout(qqa_ctx* c, int32_t S, int32_t lanes_per_row) {
+  if (!c) return QQA_E_ARG;
+  if (S <= 0 || S > kMaxReplicas) return set_err(c, QQA_E_ARG, "S must be in [1, 4096]");
+  if (lanes_per_row < 0 || lanes_per_row > 64 || !layout_supported(S, lanes_per_row))
+    return set_err(c, QQA_E_ARG, "unsupported replica layout");
+  if (lanes_per_row == 0) c->layout.erase(S);
+  else c->layout[S] = replica_shape(S, lanes_per_row).lpr;
+  return QQA_OK;
+}
+
+int qqa_autotune(qqa_ctx* c, qqa_graph_id gid, qqa_problem problem, int32_t S, int32_t* lanes_per_row) {
+  if (!c) return QQA_E_ARG;
+  auto git = c->graphs.find(gid);
+  if (git == c->graphs.end()) return set_err(c, QQA_E_ARG, "unknown graph id");
+  if (S <= 0 || S > kMaxReplicas) return set_err(c, QQA_E_ARG, "S must be in [1, 4096]");
+  const DevGraph& g = git->second;
+  if (g.dense) return set_err(c, QQA_E_ARG, "the dense path has no replica layout to tune");
+  (void)hipSetDevice(c->device);
+  Request r;
+  r.problem = problem;
+  qqa_schedule_default(&r.sched, problem, g.n);
+  r.S = S;
+  r.n = g.n;
+  r.shape = replica_shape(S);
+  const size_t fp = request_footprint(g.n, S, r.sched.rule) + (size_t)g.nchunks * r.shape.stride * sizeof(float);
+  if (c->in_use + fp > c->budget) return set_err(c, QQA_E_NOMEM, "no budget left for tuning state");
+  int rc = alloc_request_buffers(c, &r, &c->err, g.nchunks);
+  if (rc) return rc;
+  const int warm = 3, timed = 12;
+  int best = 0;
+  float best_ms = 1e30f;
+  hipError_t e = launch_init(1, g.n, S, r.P[0], r.m, r.v, c->stream);
+  int last_lpr = -1;
+  for (int want = 1; want <= 64 && e == hipSuccess; want <<= 1) {
+    const ReplicaShape sh = replica_shape(S, want);
+    if (sh.lpr == last_lpr || !layout_supported(S, want)) continue;
+    last_lpr = sh.lpr;
+    r.lanes_per_row = sh.lpr;
+    StepParams p = request_step_params(&r, g);
+    for (int t = 0; t < warm + timed && e == hipSuccess; ++t) {
+      if (t == warm) e = hipEventRecord(r.ev[1], c->stream);
+      p.P_in = r.P[t & 1];
+      p.P_out = r.P[(t + 1) & 1];
+      fill_step_scalars(p, r.sched, t, warm + timed);
+      if (g.nchunks) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
+      if (e == hipSuccess) e = launch_step(p, c->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(r.ev[2], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(r.ev[2]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.ev[1], r.ev[2]);
+    if (e == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = sh.lpr;
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  release_request_buffers(c, &r);
+  if (e != hipSuccess) return set_err(c, QQA_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  c->layout[S] = best;
+  if (lanes_per_row) *lanes_per_row = best;
+  return QQA_OK;
 }
 
 int qqa_poll(qqa_ctx* c, qqa_req id, qqa_result* out, int32_t timeout_us) {

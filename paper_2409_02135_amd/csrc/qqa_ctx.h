@@ -43,6 +43,7 @@ struct Request {
   int S = 0, K = 0, n = 0;
   uint64_t seed = 0;
   ReplicaShape shape{};
+  int lanes_per_row = 0;
   size_t footprint = 0;
   float* P[2] = {nullptr, nullptr};
   float* m = nullptr;
@@ -75,6 +76,11 @@ struct qqa_ctx {
   std::unordered_map<int64_t, std::unique_ptr<qqa::Request>> reqs;
   int64_t next_req = 1;
   std::unique_ptr<qqa::Server> server;
+  std::unordered_map<int, int> layout;  // S -> lanes per row (absent: default)
+  int layout_for(int S) const {
+    auto it = layout.find(S);
+    return it == layout.end() ? 0 : it->second;
+  }
   qqa_ctx();
   ~qqa_ctx();
 };

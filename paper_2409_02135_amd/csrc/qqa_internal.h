@@ -29,6 +29,8 @@ struct ReplicaShape {
   int stride;  // floats per row = 4 * nquads
 };
 ReplicaShape replica_shape(int S);
+ReplicaShape replica_shape(int S, int lanes_per_row);
+bool layout_supported(int S, int lanes_per_row);
 
 // Everything one launch of the fused update needs for one instance at one update index.
 // Per-update scalars (gamma_t, bias corrections) are computed on the host in double
@@ -45,6 +47,7 @@ struct StepParams {
   float* m;
   float* v;
   int32_t n, S, stride, problem, rule, alpha_e;
+  int32_t lanes_per_row;   // replica layout (0 = default); selects the kernel instance
   float lambda;            // MIS penalty
   float lr, wd_factor;     // wd_factor = 1 - lr * weight_decay
   float comm_alpha;

@@ -438,18 +438,43 @@ __global__ void fill_u64_kernel(unsigned long long* p, size_t count) {
 // ---------------------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------------------
-ReplicaShape replica_shape(int S) {
+ReplicaShape replica_shape(int S) { return replica_shape(S, 0); }
+
+// lanes_per_row = 0: the default layout (fewest quads per lane, at most one wavefront per
+// row); otherwise the requested power of two, with enough quads per lane to cover S.
+ReplicaShape replica_shape(int S, int lanes_per_row) {
   ReplicaShape r;
   r.nquads = (S + 3) / 4;
   r.stride = 4 * r.nquads;
   int lpr = 1;
-  while (lpr < r.nquads && lpr < 64) lpr <<= 1;
+  if (lanes_per_row > 0) {
+    while (lpr < lanes_per_row && lpr < 64) lpr <<= 1;
+    while (lpr > 1 && lpr / 2 >= r.nquads) lpr >>= 1;  // no group wider than the row needs
+  } else {
+    while (lpr < r.nquads && lpr < 64) lpr <<= 1;
+  }
   r.lpr = lpr;
   int qpl = 1;
   while (lpr * qpl < r.nquads) qpl <<= 1;
   r.qpl = qpl;
   return r;
 }
+
+// every (lanes per row, quads per lane) pair the kernels are built for
+#define QQA_FOR_EACH_LAYOUT(X)                                                                   \
+  X(1, 1) X(1, 2) X(1, 4) X(1, 8) X(2, 1) X(2, 2) X(2, 4) X(2, 8) X(4, 1) X(4, 2) X(4, 4) X(4, 8)   \
+  X(8, 1) X(8, 2) X(8, 4) X(8, 8) X(16, 1) X(16, 2) X(16, 4) X(16, 8) X(32, 1) X(32, 2) X(32, 4)  \
+  X(32, 8) X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
+
+bool layout_supported(int S, int lanes_per_row) {
+  const ReplicaShape r = replica_shape(S, lanes_per_row);
+#define X(L, Q) \
+  if (r.lpr == L && r.qpl == Q) return true;
+  QQA_FOR_EACH_LAYOUT(X)
+#undef X
+  return false;
+}
+
 
 static unsigned grid_for(long long threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
 
@@ -499,49 +524,30 @@ static void launch_hub_t(const StepParams& p, const HubChunk* chunks, int nchunk
 
 hipError_t launch_hub_partials(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st) {
   if (nchunks == 0) return hipSuccess;
-  const ReplicaShape r = replica_shape(p.S);
-  switch (r.lpr) {
-    case 1: launch_hub_t<1, 1>(p, chunks, nchunks, st); break;
-    case 2: launch_hub_t<2, 1>(p, chunks, nchunks, st); break;
-    case 4: launch_hub_t<4, 1>(p, chunks, nchunks, st); break;
-    case 8: launch_hub_t<8, 1>(p, chunks, nchunks, st); break;
-    case 16: launch_hub_t<16, 1>(p, chunks, nchunks, st); break;
-    case 32: launch_hub_t<32, 1>(p, chunks, nchunks, st); break;
-    default:
-      switch (r.qpl) {
-        case 1: launch_hub_t<64, 1>(p, chunks, nchunks, st); break;
-        case 2: launch_hub_t<64, 2>(p, chunks, nchunks, st); break;
-        case 4: launch_hub_t<64, 4>(p, chunks, nchunks, st); break;
-        case 8: launch_hub_t<64, 8>(p, chunks, nchunks, st); break;
-        case 16: launch_hub_t<64, 16>(p, chunks, nchunks, st); break;
-        default: return hipErrorInvalidValue;
-      }
+  const ReplicaShape r = replica_shape(p.S, p.lanes_per_row);
+#define X(L, Q)                                 \
+  if (r.lpr == L && r.qpl == Q) {               \
+    launch_hub_t<L, Q>(p, chunks, nchunks, st); \
+    return hipGetLastError();                   \
   }
-  return hipGetLastError();
+  QQA_FOR_EACH_LAYOUT(X)
+#undef X
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_step(const StepParams& p, hipStream_t st) {
   if (p.n == 0) return hipSuccess;
-  const ReplicaShape r = replica_shape(p.S);
-  switch (r.lpr) {
-    case 1: launch_step_t<1, 1>(p, st); break;
-    case 2: launch_step_t<2, 1>(p, st); break;
-    case 4: launch_step_t<4, 1>(p, st); break;
-    case 8: launch_step_t<8, 1>(p, st); break;
-    case 16: launch_step_t<16, 1>(p, st); break;
-    case 32: launch_step_t<32, 1>(p, st); break;
-    default:
-      switch (r.qpl) {
-        case 1: launch_step_t<64, 1>(p, st); break;
-        case 2: launch_step_t<64, 2>(p, st); break;
-        case 4: launch_step_t<64, 4>(p, st); break;
-        case 8: launch_step_t<64, 8>(p, st); break;
-        case 16: launch_step_t<64, 16>(p, st); break;
-        default: return hipErrorInvalidValue;
-      }
+  const ReplicaShape r = replica_shape(p.S, p.lanes_per_row);
+#define X(L, Q)                   \
+  if (r.lpr == L && r.qpl == Q) { \
+    launch_step_t<L, Q>(p, st);   \
+    return hipGetLastError();     \
   }
-  return hipGetLastError();
+  QQA_FOR_EACH_LAYOUT(X)
+#undef X
+  return hipErrorInvalidValue;
 }
+
 
 hipError_t launch_fill_u64(unsigned long long* p, size_t count, hipStream_t st) {
   if (count == 0) return hipSuccess;
@@ -564,23 +570,15 @@ hipError_t launch_eval(const EvalParams& p, hipStream_t st) {
   if (e != hipSuccess) return e;
   const ReplicaShape r = replica_shape(p.S);
   if (p.n > 0) {
-    switch (r.lpr) {
-      case 1: launch_eval_t<1, 1>(p, st); break;
-      case 2: launch_eval_t<2, 1>(p, st); break;
-      case 4: launch_eval_t<4, 1>(p, st); break;
-      case 8: launch_eval_t<8, 1>(p, st); break;
-      case 16: launch_eval_t<16, 1>(p, st); break;
-      case 32: launch_eval_t<32, 1>(p, st); break;
-      default:
-        switch (r.qpl) {
-          case 1: launch_eval_t<64, 1>(p, st); break;
-          case 2: launch_eval_t<64, 2>(p, st); break;
-          case 4: launch_eval_t<64, 4>(p, st); break;
-          case 8: launch_eval_t<64, 8>(p, st); break;
-          case 16: launch_eval_t<64, 16>(p, st); break;
-          default: return hipErrorInvalidValue;
-        }
+    bool launched = false;
+#define X(L, Q)                         \
+    if (!launched && r.lpr == L && r.qpl == Q) { \
+      launch_eval_t<L, Q>(p, st);       \
+      launched = true;                  \
     }
+    QQA_FOR_EACH_LAYOUT(X)
+#undef X
+    if (!launched) return hipErrorInvalidValue;
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

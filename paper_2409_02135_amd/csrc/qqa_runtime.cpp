@@ -281,7 +281,8 @@ static int dev_graph_check(const qqa_dev_graph* g) {
 }
 
 int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule* sched, int32_t S, int32_t t,
-                 int32_t K, uint64_t seed, const float* P_in, float* P_out, float* m, float* v, void* stream) {
+                 int32_t K, uint64_t seed, const float* P_in, float* P_out, float* m, float* v,
+                 int32_t lanes_per_row, void* stream) {
   int rc = dev_graph_check(g);
   if (rc) return rc;
   if (problem != QQA_MIS && problem != QQA_MAXCUT) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
@@ -294,6 +295,8 @@ int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule
   if (g->n > 0 && (!P_in || !P_out)) return fail(&g_dev_error, QQA_E_ARG, "P_in/P_out missing");
   if (P_in == P_out && g->n > 0) return fail(&g_dev_error, QQA_E_ARG, "P_out must not alias P_in");
   if (s.rule == QQA_STEP_ADAMW && g->n > 0 && (!m || !v)) return fail(&g_dev_error, QQA_E_ARG, "AdamW needs m and v");
+  if (lanes_per_row < 0 || lanes_per_row > 64 || !layout_supported(S, lanes_per_row))
+    return fail(&g_dev_error, QQA_E_ARG, "unsupported replica layout");
   hipStream_t st = (hipStream_t)stream;
   StepParams p{};
   p.row_ptr = g->row_ptr;
@@ -307,6 +310,7 @@ int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule
   p.n = g->n;
   fill_static_scalars(p, s, problem, S, seed);
   fill_step_scalars(p, s, t, K);
+  p.lanes_per_row = lanes_per_row;
   if (g->n == 0) return QQA_OK;
   // the same row split the solver uses: read the row pointers back to plan it
   std::vector<int32_t> rp(g->n + 1);

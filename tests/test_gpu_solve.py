@@ -149,3 +149,20 @@ def test_ten_seed_quality_within_oracle_spread(ctx, workload):
     # Welch t statistic, reported
     t = (best.mean() - ref_best.mean()) / np.sqrt(best.var(ddof=1) / 10 + ref_best.var(ddof=1) / 10 + 1e-12)
     print(f"{workload}: gpu best {best.mean():.2f} oracle {ref_best.mean():.2f} welch t {t:.2f}")
+
+
+def test_autotune_and_layout_choice(ctx):
+    """The tuner picks a supported layout; a fixed layout gives a whole solve of the same
+    quality (the layout only reorders the replica statistics' sums)."""
+    g = qi.erdos_renyi(4000, 5.0, 3)
+    gid = ctx.upload(g, "mis")
+    lanes = ctx.autotune(gid, "mis", 128)
+    assert lanes in (1, 2, 4, 8, 16, 32)
+    a = ctx.poll(ctx.solve_resident(gid, g["n"], "mis", 128, 300, 4))
+    ctx.set_replica_layout(128, 8)
+    b = ctx.poll(ctx.solve_resident(gid, g["n"], "mis", 128, 300, 4))
+    ctx.set_replica_layout(128, 0)
+    ctx.release(gid)
+    for r in (a, b):
+        assert r["best_objective"] == objective_of(g, r["best_x"], "mis") and r["feasible"]
+    assert abs(a["obj"].mean() - b["obj"].mean()) < 0.02 * abs(a["obj"].mean())
