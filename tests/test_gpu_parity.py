@@ -27,7 +27,7 @@ torch = pytest.importorskip("torch")
 # must still lie within the conditioned bound.
 TOL_P = 1e-5
 TOL_REL = 1e-5
-ULPS = 3e-7          # float32 gradient error bound, relative to G (about 5 ulp)
+ULPS = 2e-7          # float32 gradient error bound, relative to G (a few ulp)
 MAX_EXEMPT_FRAC = 1e-4
 
 
@@ -96,7 +96,10 @@ def check_step(label, gpu, ref, S, adam, beta1, beta2, sens=None, comm_alpha=0.1
     std_err = np.where(sig > 0, comm_alpha * ULPS / np.maximum(sig, 1e-300), 0.0)
     exempt = std_err > 0.5 * TOL_REL * gabs
     if sens is not None:
-        exempt |= sens * (dg + std_err) > TOL_P / 2
+        # an update that leaves [0,1] by more than its own error bound clamps exactly
+        b = sens * (dg + std_err)
+        pre = ref["pre_clamp"]
+        exempt |= (b > TOL_P / 2) & (pre > -b) & (pre < 1.0 + b)
     n_ex = int(exempt.sum())
     ok = ~exempt
     dP_all = np.abs(Pg - ref["P"])
@@ -344,8 +347,14 @@ def test_step_parity_split_hub_rows(orc, S):
 def test_step_parity_every_replica_layout(orc, S, lanes):
     """Every (lanes per row, quads per lane) layout the autotuner may pick."""
     q = qqa()
-    if S // 4 < lanes // 2:
+    nq = (S + 3) // 4
+    if nq < lanes // 2:
         pytest.skip("layout wider than the row")
+    qpl = 1
+    while lanes * qpl < nq:
+        qpl *= 2
+    if qpl > (16 if lanes == 64 else 8):
+        pytest.skip("more quads per lane than the kernels are built for")
     g = qi.pm1_weights(qi.barabasi_albert(700, 4, 3), 4)
     sched = q.schedule("maxcut", g["n"])
     P, m, v = qi.synthetic_state(g["n"], S, seed=lanes)
