@@ -310,10 +310,13 @@ static double objective_term_magnitude(const orc_params *pr, const orc_graph *g,
     return acc;
 }
 
+static double p_row_in(const double *P, int32_t S, size_t e) { (void)S; return P[e]; }
+
 /* ---- one update (Sensitive Transitions, Eq. 11, with AdamW in place of the plain step) ---
    t is the 0-based update index (AdamW step count k = t + 1), K the schedule length.
    Optional diagnostics (n*S): pre_clamp = value before the clamp, gsum = g,
-   gabs = (magnitude of all terms of gf) + |ge| + |gc|;  sigma (n).                         */
+   gabs = magnitude of all terms of g before cancellation: those of gf, |ge|, and
+   alpha_c (|p| + |mu_i|) / sigma_i for gc;  sigma (n).                                     */
 void orc_step(const orc_params *pr, const orc_graph *g, int32_t S, int32_t t, int32_t K, uint64_t seed,
               const double *P_in, double *P_out, double *m, double *v,
               double *pre_clamp, double *gsum, double *gabs, double *sigma) {
@@ -325,7 +328,15 @@ void orc_step(const orc_params *pr, const orc_graph *g, int32_t S, int32_t t, in
     double *ge = (double *)malloc(NS * sizeof(double));
     double *gc = (double *)malloc(NS * sizeof(double));
     double *xi = (double *)malloc(NS * sizeof(double));
-    orc_grad(pr, g, S, P_in, gamma, gf, ge, gc, sigma);
+    double *sigma_row = (double *)malloc((size_t)n * sizeof(double));
+    double *mu_row = (double *)malloc((size_t)n * sizeof(double));
+    orc_grad(pr, g, S, P_in, gamma, gf, ge, gc, sigma_row);
+    if (sigma) memcpy(sigma, sigma_row, (size_t)n * sizeof(double));
+    for (int32_t i = 0; i < n; ++i) {
+        double mu = 0.0;
+        for (int32_t s = 0; s < S; ++s) mu += P_in[(size_t)i * S + s];
+        mu_row[i] = mu / (double)S;
+    }
     orc_noise(seed, n, S, k, xi);
     const double bc1 = 1.0 - pow(pr->beta1, (double)k);
     const double bc2 = 1.0 - pow(pr->beta2, (double)k);
@@ -346,12 +357,15 @@ void orc_step(const orc_params *pr, const orc_graph *g, int32_t S, int32_t t, in
         p = p + noise_scale * xi[e]; /* sqrt(2 eta T) xi */
         if (pre_clamp) pre_clamp[e] = p;
         if (gsum) gsum[e] = grad;
-        if (gabs)
-            gabs[e] = objective_term_magnitude(pr, g, S, P_in, (int32_t)(e / (size_t)S), (int32_t)(e % (size_t)S)) +
-                      fabs(ge[e]) + fabs(gc[e]);
+        if (gabs) {
+            const int32_t i = (int32_t)(e / (size_t)S);
+            double comm = 0.0;
+            if (sigma_row[i] > 0.0) comm = pr->comm_alpha * (fabs(p_row_in(P_in, S, e)) + fabs(mu_row[i])) / sigma_row[i];
+            gabs[e] = objective_term_magnitude(pr, g, S, P_in, i, (int32_t)(e % (size_t)S)) + fabs(ge[e]) + comm;
+        }
         P_out[e] = p < 0.0 ? 0.0 : (p > 1.0 ? 1.0 : p); /* sigma = Clamp to [0,1] */
     }
-    free(gf); free(ge); free(gc); free(xi);
+    free(gf); free(ge); free(gc); free(xi); free(sigma_row); free(mu_row);
 }
 
 /* Updates t0 .. t1-1 of a K-update schedule applied in place to (P, m, v). */
