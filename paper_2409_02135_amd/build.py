@@ -13,8 +13,8 @@ LIB = os.path.join(PKG, "libqqa.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["qqa_kernels.hip", "qqa_runtime.cpp", "qqa_ctx.cpp", "qqa_serve.cpp"]
-HEADERS = ["qqa_internal.h", "qqa_runtime.h", "qqa_ctx.h"]
+SOURCES = ["qqa_kernels.hip", "qqa_slots.hip", "qqa_runtime.cpp", "qqa_ctx.cpp", "qqa_serve.cpp"]
+HEADERS = ["qqa_internal.h", "qqa_runtime.h", "qqa_ctx.h", "qqa_device.h", "qqa_batch.h"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -22,6 +22,8 @@ FLAGS = [
     "-mcode-object-version=5",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # explicit fmaf only: identical rounding in every kernel that shares a device function
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-result",
 ]
 

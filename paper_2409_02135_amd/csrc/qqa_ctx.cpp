@@ -129,6 +129,12 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
 }
 
 void release_request_buffers(qqa_ctx* c, Request* r) {
+  if (r->owner) {
+    for (int i = 0; i < 4; ++i) r->ev[i] = nullptr;
+    r->out_dev = r->out_host = nullptr;
+    r->owner.reset();
+    return;
+  }
   const size_t state = (size_t)r->n * r->shape.stride * sizeof(float);
   c->dpool.put(r->P[0], state);
   c->dpool.put(r->P[1], state);
@@ -454,7 +460,7 @@ int qqa_poll(qqa_ctx* c, qqa_req id, qqa_result* out, int32_t timeout_us) {
   } else if (out) {
     fill_result(r, out);
     float ms = 0.f;
-    out->queue_ms = 0.0;
+    out->queue_ms = r->queue_ms;
     out->device_ms = hipEventElapsedTime(&ms, r->ev[0], r->ev[3]) == hipSuccess ? ms : -1.0;
     out->step_loop_ms = hipEventElapsedTime(&ms, r->ev[1], r->ev[2]) == hipSuccess ? ms : -1.0;
     out->latency_ms = std::chrono::duration<double, std::milli>(t_done - r->t_submit).count();

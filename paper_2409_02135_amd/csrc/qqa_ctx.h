@@ -56,6 +56,10 @@ struct Request {
   size_t out_size = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // start, loop start, loop end, done
   std::chrono::steady_clock::time_point t_submit, t_admit;
+  // set when the buffers and events belong to a shared owner (a batch or the server);
+  // releasing the request then only drops its reference
+  std::shared_ptr<void> owner;
+  double queue_ms = 0.0;
 };
 
 struct Server;

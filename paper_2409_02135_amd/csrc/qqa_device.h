@@ -1,0 +1,237 @@
+// Device functions shared by every kernel that updates replica rows (single-instance,
+// split-row, persistent and multi-instance slot kernels), so that all of them perform the
+// same floating-point operations in the same order for a given row.
+#pragma once
+
+#include "qqa_internal.h"
+
+namespace qqa {
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the uniform / normal transforms.
+// ---------------------------------------------------------------------------------------
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                            uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    // 32x32 -> 64-bit products: one v_mad_u64_u32 each gives both halves
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0;
+    c1 = (uint32_t)p1;
+    c2 = n2;
+    c3 = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// odd multiples of 2^-24 in (0,1): exact in binary32
+__device__ __forceinline__ float u01(uint32_t r) { return (float)((r >> 8) | 1u) * 0x1.0p-24f; }
+
+// Box-Muller on (u0,u1), (u2,u3) with the hardware transcendental units:
+// R = sqrt(-2 ln u) = sqrt(-2 ln2 * log2 u) (v_log_f32, v_sqrt_f32); the angle 2 pi u is
+// passed to v_sin_f32 / v_cos_f32 in revolutions (their argument is scaled by 2 pi).
+__device__ __forceinline__ float4 normals4(U4 r) {
+  const float m2ln2 = -1.38629436111989061883f;  // -2 ln 2
+  const float R1 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01(r.x)));
+  const float R2 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01(r.z)));
+  const float a1 = u01(r.y), a2 = u01(r.w);
+  return make_float4(R1 * __builtin_amdgcn_cosf(a1), R1 * __builtin_amdgcn_sinf(a1), R2 * __builtin_amdgcn_cosf(a2),
+                     R2 * __builtin_amdgcn_sinf(a2));
+}
+
+// ---------------------------------------------------------------------------------------
+// Fused update of one row (all S replicas of variable `row`), lanes gl = 0..LPR-1.
+// ---------------------------------------------------------------------------------------
+template <int LPR>
+__device__ __forceinline__ float group_sum(float x) {
+  // butterfly inside the LPR-lane group: a fixed tree determined by LPR alone, and
+  // every lane ends with the same bits (IEEE addition is commutative)
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, LPR);
+  return x;
+}
+
+__device__ __forceinline__ float comp(const float4& v, int c) {
+  return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ void set_comp(float4& v, int c, float x) {
+  if (c == 0) v.x = x; else if (c == 1) v.y = x; else if (c == 2) v.z = x; else v.w = x;
+}
+
+__device__ __forceinline__ float ipow_odd(float z, int e) {
+  float r = z;
+  for (int i = 1; i < e; ++i) r *= z;
+  return r;
+}
+
+// acc += sum over edges e in [e_begin, e_end) of w_e * f(p_col(e)), in edge order, with
+// f(p) = p (MIS) or 2p - 1 (max-cut); four neighbour rows are loaded per iteration.
+template <int LPR, int QPL, bool FULL>
+__device__ __forceinline__ void gather_coupling(const StepParams& a, const int e_begin, const int e_end, const int gl,
+                                                const int nq, const bool maxcut, float4 (&acc)[QPL]) {
+  for (int e0 = e_begin; e0 < e_end; e0 += 4) {
+    int j[4];
+    float w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u;
+      j[u] = e < e_end ? a.col[e] : -1;
+      w[u] = e < e_end ? (a.w ? a.w[e] : 1.f) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (j[u] < 0) continue;
+      const float* pj = a.P_in + (size_t)j[u] * a.stride;
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+        const int q = gl + LPR * k;
+        if (FULL || q < nq) {
+          float4 x = *reinterpret_cast<const float4*>(pj + 4 * q);
+          if (maxcut) {
+            x.x = 2.f * x.x - 1.f;
+            x.y = 2.f * x.y - 1.f;
+            x.z = 2.f * x.z - 1.f;
+            x.w = 2.f * x.w - 1.f;
+          }
+          acc[k].x = fmaf(w[u], x.x, acc[k].x);
+          acc[k].y = fmaf(w[u], x.y, acc[k].y);
+          acc[k].z = fmaf(w[u], x.z, acc[k].z);
+          acc[k].w = fmaf(w[u], x.w, acc[k].w);
+        }
+      }
+    }
+  }
+}
+
+// FULL: S == 4 * LPR * QPL, every lane owns whole, valid quads (no replica masks).
+template <int LPR, int QPL, bool FULL>
+__device__ __forceinline__ void update_row(const StepParams& a, const int row, const int gl) {
+  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
+  const bool maxcut = a.problem == kMAXCUT;
+  const bool adam = a.rule == kADAMW;
+  const size_t base = (size_t)row * a.stride;
+
+  // own row first, so its loads overlap the neighbour gathers below
+  float4 p[QPL], mm[QPL], vv[QPL];
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+    p[k] = mm[k] = vv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (FULL || q < nq) {
+      p[k] = *reinterpret_cast<const float4*>(a.P_in + base + 4 * q);
+      if (adam) {
+        mm[k] = *reinterpret_cast<const float4*>(a.m + base + 4 * q);
+        vv[k] = *reinterpret_cast<const float4*>(a.v + base + 4 * q);
+      }
+    }
+  }
+
+  // (1) coupling product C_i = sum_j A_ij p_j (MIS) or sum_j A_ij (2 p_j - 1) (max-cut),
+  //     accumulated in CSR order so that the rounding sequence depends on the graph only
+  float4 acc[QPL];
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (a.coupling) {
+#pragma unroll
+    for (int k = 0; k < QPL; ++k) {
+      const int q = gl + LPR * k;
+      if (FULL || q < nq) acc[k] = *reinterpret_cast<const float4*>(a.coupling + base + 4 * q);
+    }
+  } else if (a.hub_first && a.hub_first[row] >= 0) {
+    // split row: partial sums of its chunks, added in chunk order
+    const int first = a.hub_first[row];
+    const int nch = (a.row_ptr[row + 1] - a.row_ptr[row] + kHubChunk - 1) / kHubChunk;
+    for (int c = 0; c < nch; ++c) {
+      const float* part = a.hub_partial + (size_t)(first + c) * a.stride;
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+        const int q = gl + LPR * k;
+        if (FULL || q < nq) {
+          const float4 x = *reinterpret_cast<const float4*>(part + 4 * q);
+          acc[k].x += x.x;
+          acc[k].y += x.y;
+          acc[k].z += x.z;
+          acc[k].w += x.w;
+        }
+      }
+    }
+  } else {
+    gather_coupling<LPR, QPL, FULL>(a, a.row_ptr[row], a.row_ptr[row + 1], gl, nq, maxcut, acc);
+  }
+
+  // (2) replica statistics mu_i, sigma_i (two passes, population STD)
+  float sum = 0.f;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (FULL || 4 * q + c < a.S) sum += comp(p[k], c);
+  }
+  sum = group_sum<LPR>(sum);
+  const float mu = sum * a.inv_S;
+  float sq = 0.f;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (FULL || 4 * q + c < a.S) {
+        const float d = comp(p[k], c) - mu;
+        sq = fmaf(d, d, sq);
+      }
+  }
+  sq = group_sum<LPR>(sq);
+  const float sigma = __builtin_amdgcn_sqrtf(sq * a.inv_S);
+  const float cg = sigma > 0.f ? -a.comm_alpha * __builtin_amdgcn_rcpf(sigma) : 0.f;
+
+  // (3) gradient, step, noise, clamp
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+    if (!FULL && q >= nq) continue;
+    const float4 xi = normals4(philox4x32_10((uint32_t)row, (uint32_t)q, a.k, kStreamNoise, a.key0, a.key1));
+    float4 po, mo, vo;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float pc = comp(p[k], c);
+      const float C = comp(acc[k], c);
+      const float gf = maxcut ? C : fmaf(a.lambda, C, -1.f);
+      const float z = 2.f * pc - 1.f;
+      const float ge = a.ce * ipow_odd(z, a.alpha_e - 1);
+      const float gc = cg * (pc - mu);
+      const float g = gf + ge + gc;
+      float pn, mn = 0.f, vn = 0.f;
+      if (adam) {
+        mn = fmaf(a.beta1, comp(mm[k], c), a.omb1 * g);
+        vn = fmaf(a.beta2, comp(vv[k], c), a.omb2 * (g * g));
+        const float den = __builtin_amdgcn_sqrtf(vn * a.inv_bc2) + a.eps;
+        pn = pc * a.wd_factor - a.lr * (mn * a.inv_bc1) * __builtin_amdgcn_rcpf(den);
+      } else {
+        pn = pc - a.lr * g;
+      }
+      pn = fmaf(a.noise_scale, comp(xi, c), pn);
+      pn = fminf(fmaxf(pn, 0.f), 1.f);
+      const bool valid = FULL || 4 * q + c < a.S;
+      set_comp(po, c, valid ? pn : 0.f);
+      set_comp(mo, c, valid ? mn : 0.f);
+      set_comp(vo, c, valid ? vn : 0.f);
+    }
+    *reinterpret_cast<float4*>(a.P_out + base + 4 * q) = po;
+    if (adam) {
+      *reinterpret_cast<float4*>(a.m + base + 4 * q) = mo;
+      *reinterpret_cast<float4*>(a.v + base + 4 * q) = vo;
+    }
+  }
+}
+
+}  // namespace qqa

@@ -32,6 +32,12 @@ ReplicaShape replica_shape(int S);
 ReplicaShape replica_shape(int S, int lanes_per_row);
 bool layout_supported(int S, int lanes_per_row);
 
+// Chunks of split rows: {row, first edge}; the chunk ends at min(first + kHubChunk, row end).
+struct HubChunk {
+  int32_t row;
+  int32_t e0;
+};
+
 // Everything one launch of the fused update needs for one instance at one update index.
 // Per-update scalars (gamma_t, bias corrections) are computed on the host in double
 // precision and rounded once.
@@ -75,17 +81,58 @@ struct EvalParams {
   int32_t* best;           // [1]
 };
 
+// ---- multi-instance slots ------------------------------------------------------------
+// One slot per instance in a batch or in the server.  A launch over a work list advances
+// every active slot by one update; the update index of a slot is t = clock + t_arg - start,
+// so a captured sequence of launches (t_arg = 0..R-1) can be replayed after the clock
+// moves on.  Per-update scalars come from the slot's table, computed on the host exactly
+// as for a single solve, so a slot follows the same arithmetic as a solve run alone.
+struct SlotDesc {
+  StepParams p;                 // static fields; P_in / P_out / per-update fields set per launch
+  float* P[2];                  // ping-pong state
+  const float4* table;          // per update t: {ce, inv_bc1, inv_bc2, 0}
+  const HubChunk* chunks;       // split plan of the slot's graph
+  int32_t nchunks;
+  int32_t K;                    // updates
+  int32_t start;                // clock value of the slot's first update
+  int32_t active;               // 0: skipped by every kernel
+  uint64_t seed;
+  int64_t lambda64;             // MIS penalty for the exact evaluation
+  unsigned long long* acc;      // [2][stride] evaluation accumulators
+  int64_t* size_or_cut;         // [S] outputs
+  int64_t* viol;
+  int64_t* obj;
+  int32_t* best;
+  uint8_t* x;                   // [n]
+};
+
+struct WorkItem {
+  int32_t slot;
+  int32_t row0;                 // first row; a block covers kBlock / lanes_per_row rows
+};
+struct HubItem {
+  int32_t slot;
+  int32_t chunk;
+};
+
+// Launches over a work list of one replica layout.  `clock` is a device int.
+hipError_t launch_slot_init(const SlotDesc* slots, const WorkItem* items, int nitems, int lanes_per_row, hipStream_t st);
+hipError_t launch_slot_step(const SlotDesc* slots, const WorkItem* items, int nitems, int S, int lanes_per_row,
+                            const int32_t* clock, int t_arg, hipStream_t st);
+hipError_t launch_slot_hubs(const SlotDesc* slots, const HubItem* items, int nitems, int S, int lanes_per_row,
+                            const int32_t* clock, int t_arg, hipStream_t st);
+hipError_t launch_clock_advance(int32_t* clock, int by, hipStream_t st);
+// Evaluation of slots whose update loop is complete: zero accumulators, accumulate,
+// finalize (objectives + best replica), extract x of the best replica.
+hipError_t launch_slot_eval(const SlotDesc* slots, const int32_t* slot_ids, int nslots, const WorkItem* items,
+                            int nitems, int S, int lanes_per_row, hipStream_t st);
+
 hipError_t launch_philox(uint64_t seed, int n, int nquads, uint32_t k, uint32_t stream_id, uint32_t* out,
                          hipStream_t st);
 hipError_t launch_noise(uint64_t seed, int n, int S, uint32_t k, float* xi, hipStream_t st);
 hipError_t launch_init(uint64_t seed, int n, int S, float* P, float* m, float* v, hipStream_t st);
 hipError_t launch_step(const StepParams& p, hipStream_t st);
 
-// Chunks of split rows: {row, first edge}; the chunk ends at min(first + kHubChunk, row end).
-struct HubChunk {
-  int32_t row;
-  int32_t e0;
-};
 // Partial coupling sums of every chunk into p.hub_partial (reads P_in, row_ptr, col, w).
 hipError_t launch_hub_partials(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st);
 hipError_t launch_eval(const EvalParams& p, hipStream_t st);

@@ -1,26 +1,334 @@
-// Ragged multi-instance batches and the continuous-batching server.
+// Ragged multi-instance batches (qqa_solve_batch) and the continuous-batching server.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
 #include "qqa.h"
+#include "qqa_batch.h"
 #include "qqa_ctx.h"
 
 using namespace qqa;
+using Clock = std::chrono::steady_clock;
 
 namespace qqa {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+std::vector<float4> schedule_table(const qqa_schedule& s, int K) {
+  std::vector<float4> t((size_t)K);
+  StepParams p{};
+  for (int i = 0; i < K; ++i) {
+    fill_step_scalars(p, s, i, K);
+    t[i] = make_float4(p.ce, p.inv_bc1, p.inv_bc2, 0.f);
+  }
+  return t;
+}
+
+SlotLayout slot_layout(int n, int S, int rule, int nchunks) {
+  const size_t stride = (size_t)replica_shape(S).stride;
+  const size_t state = align256((size_t)n * stride * sizeof(float));
+  SlotLayout L{};
+  size_t o = 0;
+  L.P0 = o;
+  o += state;
+  L.P1 = o;
+  o += state;
+  L.m = o;
+  if (rule == QQA_STEP_ADAMW) o += state;
+  L.v = o;
+  if (rule == QQA_STEP_ADAMW) o += state;
+  L.hub = o;
+  o += align256((size_t)nchunks * stride * sizeof(float));
+  L.acc = o;
+  o += align256(2 * stride * sizeof(unsigned long long));
+  L.bytes = o;
+  L.out_size = out_bytes(n, S);
+  return L;
+}
+
+SlotDesc make_slot(const DevGraph& g, int problem, const qqa_schedule& sched, int S, int K, uint64_t seed,
+                   int lanes_per_row, char* arena, const SlotLayout& L, char* out, const float4* table, int start) {
+  SlotDesc d{};
+  StepParams& p = d.p;
+  p.row_ptr = g.row_ptr;
+  p.col = g.col;
+  p.w = problem == QQA_MAXCUT ? g.w : nullptr;
+  p.coupling = nullptr;
+  p.hub_first = g.hub_first;
+  p.hub_partial = g.nchunks ? reinterpret_cast<float*>(arena + L.hub) : nullptr;
+  p.m = sched.rule == QQA_STEP_ADAMW ? reinterpret_cast<float*>(arena + L.m) : nullptr;
+  p.v = sched.rule == QQA_STEP_ADAMW ? reinterpret_cast<float*>(arena + L.v) : nullptr;
+  p.n = g.n;
+  fill_static_scalars(p, sched, problem, S, seed);
+  p.lanes_per_row = lanes_per_row;
+  d.P[0] = reinterpret_cast<float*>(arena + L.P0);
+  d.P[1] = reinterpret_cast<float*>(arena + L.P1);
+  d.table = table;
+  d.chunks = g.chunks;
+  d.nchunks = g.nchunks;
+  d.K = K;
+  d.start = start;
+  d.active = 1;
+  d.seed = seed;
+  d.lambda64 = sched.penalty_lambda;
+  d.acc = reinterpret_cast<unsigned long long*>(arena + L.acc);
+  int64_t *a, *b, *o;
+  int32_t* best;
+  uint8_t* x;
+  out_views(out, g.n, S, &a, &b, &o, &best, &x);
+  d.size_or_cut = a;
+  d.viol = b;
+  d.obj = o;
+  d.best = best;
+  d.x = x;
+  return d;
+}
+
+void append_items(int slot, const DevGraph& g, int lanes_per_row, std::vector<WorkItem>* items,
+                  std::vector<HubItem>* hubs) {
+  const int rows_per_block = kBlock / lanes_per_row;
+  for (int r = 0; r < g.n; r += rows_per_block) items->push_back(WorkItem{slot, r});
+  for (int c = 0; c < g.nchunks; ++c) hubs->push_back(HubItem{slot, c});
+}
+
+BatchRun::~BatchRun() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c) {
+    c->dpool.put(arena, arena_bytes);
+    c->hpool.put(host_out, host_out_bytes);
+    c->in_use -= footprint;
+  }
+}
+
 struct Server {};
 
 int serve_poll(qqa_ctx*, int64_t, qqa_result*, int32_t) { return QQA_E_UNKNOWN_REQ; }
 int serve_cancel(qqa_ctx*, int64_t) { return QQA_E_UNKNOWN_REQ; }
+
 }  // namespace qqa
 
 qqa_ctx::qqa_ctx() = default;
 qqa_ctx::~qqa_ctx() = default;
 
+namespace {
+
+// One replica layout class of a batch: its slots' row blocks and split-row chunks.
+struct LayoutClass {
+  int S = 0, lanes = 0;
+  std::vector<WorkItem> items;
+  std::vector<HubItem> hubs;
+  std::vector<int32_t> ids;
+  size_t off_items = 0, off_hubs = 0, off_ids = 0;
+};
+
+}  // namespace
+
 extern "C" {
 
-int qqa_solve_batch(qqa_ctx* c, int32_t, const qqa_graph_id*, const qqa_problem*, const qqa_schedule*, const int32_t*,
-                    const int32_t*, const uint64_t*, qqa_req*) {
-  return c ? set_err(c, QQA_E_ARG, "batched solves are not available in this build") : QQA_E_ARG;
+int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const qqa_problem* problems,
+                    const qqa_schedule* sched, const int32_t* S, const int32_t* steps, const uint64_t* seeds,
+                    qqa_req* out_ids) {
+  if (!c) return QQA_E_ARG;
+  if (count <= 0 || !graphs || !problems || !S || !steps || !seeds || !out_ids)
+    return set_err(c, QQA_E_ARG, "batch arguments missing");
+  (void)hipSetDevice(c->device);
+  struct Inst {
+    const DevGraph* g;
+    int64_t gid;
+    int problem, S, K, lanes, table;
+    uint64_t seed;
+    qqa_schedule s;
+    SlotLayout L;
+    size_t off, out_off;
+  };
+  std::vector<Inst> inst((size_t)count);
+  std::vector<std::vector<float4>> tables;
+  std::map<std::string, int> table_of;
+  int maxK = 0;
+  size_t arena = 0, out_total = 0;
+  for (int i = 0; i < count; ++i) {
+    Inst& I = inst[i];
+    auto git = c->graphs.find(graphs[i]);
+    if (git == c->graphs.end() || git->second.release_pending) return set_err(c, QQA_E_ARG, "unknown graph id in batch");
+    I.g = &git->second;
+    I.gid = graphs[i];
+    I.problem = problems[i];
+    if (I.problem != QQA_MIS && I.problem != QQA_MAXCUT) return set_err(c, QQA_E_ARG, "unknown problem");
+    if (I.g->problem != I.problem) return set_err(c, QQA_E_ARG, "graph was uploaded for another problem type");
+    if (I.g->dense) return set_err(c, QQA_E_ARG, "dense graphs are solved one at a time");
+    I.S = S[i];
+    I.K = steps[i];
+    if (I.S <= 0 || I.S > kMaxReplicas || I.K <= 0) return set_err(c, QQA_E_ARG, "need 1 <= S <= 4096 and steps > 0");
+    I.seed = seeds[i];
+    if (sched) I.s = sched[i]; else qqa_schedule_default(&I.s, (qqa_problem)I.problem, I.g->n);
+    std::string why;
+    if (!schedule_valid(I.s, &why)) return set_err(c, QQA_E_ARG, why);
+    I.lanes = replica_shape(I.S, c->layout_for(I.S)).lpr;
+    I.L = slot_layout(I.g->n, I.S, I.s.rule, I.g->nchunks);
+    I.off = arena;
+    arena += I.L.bytes;
+    I.out_off = out_total;
+    out_total += align256(I.L.out_size);
+    std::string key(reinterpret_cast<const char*>(&I.s), sizeof(qqa_schedule));
+    key += std::to_string(I.K);
+    auto it = table_of.find(key);
+    if (it == table_of.end()) {
+      it = table_of.emplace(key, (int)tables.size()).first;
+      tables.push_back(schedule_table(I.s, I.K));
+    }
+    I.table = it->second;
+    maxK = std::max(maxK, I.K);
+  }
+  // layout classes
+  std::map<std::pair<int, int>, LayoutClass> classes;
+  for (int i = 0; i < count; ++i) {
+    LayoutClass& lc = classes[{inst[i].S, inst[i].lanes}];
+    lc.S = inst[i].S;
+    lc.lanes = inst[i].lanes;
+    append_items(i, *inst[i].g, inst[i].lanes, &lc.items, &lc.hubs);
+    lc.ids.push_back(i);
+  }
+  // arena tail: tables, slot descriptors, work lists, clock, then the result records
+  std::vector<size_t> table_off(tables.size());
+  for (size_t k = 0; k < tables.size(); ++k) {
+    table_off[k] = arena;
+    arena += align256(tables[k].size() * sizeof(float4));
+  }
+  const size_t off_slots = arena;
+  arena += align256((size_t)count * sizeof(SlotDesc));
+  for (auto& kv : classes) {
+    LayoutClass& lc = kv.second;
+    lc.off_items = arena;
+    arena += align256(lc.items.size() * sizeof(WorkItem));
+    lc.off_hubs = arena;
+    arena += align256(lc.hubs.size() * sizeof(HubItem));
+    lc.off_ids = arena;
+    arena += align256(lc.ids.size() * sizeof(int32_t));
+  }
+  const size_t off_clock = arena;
+  arena += 256;
+  const size_t off_out = arena;
+  arena += out_total;
+
+  auto run = std::make_shared<BatchRun>();
+  run->footprint = arena;
+  hipError_t e = hipSuccess;
+  if (arena > c->budget) return set_err(c, QQA_E_ADMISSION, "batch footprint exceeds the HBM budget");
+  if (c->in_use + arena > c->budget) return set_err(c, QQA_E_NOMEM, "HBM budget held by earlier requests");
+  e = c->dpool.get(arena, (void**)&run->arena);
+  if (e == hipSuccess) {
+    run->arena_bytes = arena;
+    e = c->hpool.get(out_total, (void**)&run->host_out);
+  }
+  if (e == hipSuccess) run->host_out_bytes = out_total;
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&run->ev[i]);
+  run->c = c;  // from here on the destructor returns what was taken
+  c->in_use += arena;
+  if (e != hipSuccess) return set_err(c, e == hipErrorOutOfMemory ? QQA_E_NOMEM : QQA_E_DEVICE, hipGetErrorString(e));
+
+  // host image of everything up to the result records, uploaded in one copy
+  std::vector<char> image(off_out, 0);
+  char* A = run->arena;
+  for (size_t k = 0; k < tables.size(); ++k)
+    std::memcpy(image.data() + table_off[k], tables[k].data(), tables[k].size() * sizeof(float4));
+  for (int i = 0; i < count; ++i) {
+    const Inst& I = inst[i];
+    SlotDesc d = make_slot(*I.g, I.problem, I.s, I.S, I.K, I.seed, I.lanes, A + I.off, I.L, A + off_out + I.out_off,
+                           reinterpret_cast<const float4*>(A + table_off[I.table]), 0);
+    std::memcpy(image.data() + off_slots + (size_t)i * sizeof(SlotDesc), &d, sizeof(SlotDesc));
+  }
+  for (auto& kv : classes) {
+    const LayoutClass& lc = kv.second;
+    std::memcpy(image.data() + lc.off_items, lc.items.data(), lc.items.size() * sizeof(WorkItem));
+    std::memcpy(image.data() + lc.off_hubs, lc.hubs.data(), lc.hubs.size() * sizeof(HubItem));
+    std::memcpy(image.data() + lc.off_ids, lc.ids.data(), lc.ids.size() * sizeof(int32_t));
+  }
+  const SlotDesc* d_slots = reinterpret_cast<const SlotDesc*>(A + off_slots);
+  int32_t* d_clock = reinterpret_cast<int32_t*>(A + off_clock);
+  hipStream_t st = c->stream;
+  // the state buffers are written by the init kernel; upload tables onwards
+  const size_t up0 = tables.empty() ? off_slots : table_off[0];
+  e = hipMemcpyAsync(A + up0, image.data() + up0, off_out - up0, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host image goes out of scope
+
+  const auto t_submit = Clock::now();
+  if (e == hipSuccess) e = hipEventRecord(run->ev[0], st);
+  for (auto& kv : classes) {
+    const LayoutClass& lc = kv.second;
+    if (e == hipSuccess)
+      e = launch_slot_init(d_slots, reinterpret_cast<const WorkItem*>(A + lc.off_items), (int)lc.items.size(), lc.lanes,
+                           st);
+  }
+  if (e == hipSuccess) e = hipEventRecord(run->ev[1], st);
+  // the update loop: R launches per layout class and a clock advance, captured once and
+  // replayed until the longest instance has run all of its updates
+  const int R = std::min(maxK, 64);
+  if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t ce = hipSuccess;
+    for (int r = 0; r < R && ce == hipSuccess; ++r)
+      for (auto& kv : classes) {
+        const LayoutClass& lc = kv.second;
+        if (ce == hipSuccess && !lc.hubs.empty())
+          ce = launch_slot_hubs(d_slots, reinterpret_cast<const HubItem*>(A + lc.off_hubs), (int)lc.hubs.size(), lc.S,
+                                lc.lanes, d_clock, r, st);
+        if (ce == hipSuccess)
+          ce = launch_slot_step(d_slots, reinterpret_cast<const WorkItem*>(A + lc.off_items), (int)lc.items.size(),
+                                lc.S, lc.lanes, d_clock, r, st);
+      }
+    if (ce == hipSuccess) ce = launch_clock_advance(d_clock, R, st);
+    e = hipStreamEndCapture(st, &run->graph);
+    if (e == hipSuccess) e = ce;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&run->exec, run->graph, nullptr, nullptr, 0);
+  for (int done = 0; done < maxK && e == hipSuccess; done += R) e = hipGraphLaunch(run->exec, st);
+  if (e == hipSuccess) e = hipEventRecord(run->ev[2], st);
+  for (auto& kv : classes) {
+    const LayoutClass& lc = kv.second;
+    if (e == hipSuccess)
+      e = launch_slot_eval(d_slots, reinterpret_cast<const int32_t*>(A + lc.off_ids), (int)lc.ids.size(),
+                           reinterpret_cast<const WorkItem*>(A + lc.off_items), (int)lc.items.size(), lc.S, lc.lanes,
+                           st);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(run->host_out, A + off_out, out_total, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipEventRecord(run->ev[3], st);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    return set_err(c, QQA_E_DEVICE, std::string("batch enqueue: ") + hipGetErrorString(e));
+  }
+  for (int i = 0; i < count; ++i) {
+    const Inst& I = inst[i];
+    auto r = std::make_unique<Request>();
+    r->id = c->next_req++;
+    r->graph = I.gid;
+    r->problem = I.problem;
+    r->sched = I.s;
+    r->S = I.S;
+    r->K = I.K;
+    r->n = I.g->n;
+    r->seed = I.seed;
+    r->shape = replica_shape(I.S);
+    r->lanes_per_row = I.lanes;
+    r->out_host = run->host_out + I.out_off;
+    r->out_size = I.L.out_size;
+    for (int k = 0; k < 4; ++k) r->ev[k] = run->ev[k];
+    r->owner = run;
+    r->t_submit = t_submit;
+    r->state = Request::kRunning;
+    c->graphs[I.gid].refs++;
+    out_ids[i] = r->id;
+    c->reqs.emplace(r->id, std::move(r));
+  }
+  return QQA_OK;
 }
 
 int qqa_serve_start(qqa_ctx* c, int32_t) {

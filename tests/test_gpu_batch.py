@@ -1,0 +1,76 @@
+"""Ragged multi-instance batches through qqa_solve_batch: every instance's result is the
+same, bit for bit, as the same solve submitted alone, and is self-consistent."""
+
+import numpy as np
+import pytest
+
+import qqa_inputs as qi
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_02135_amd as q
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+def _instances():
+    rng = np.random.default_rng(0)
+    out = []
+    for k in range(14):
+        n = int(rng.integers(50, 3000))
+        if k % 3 == 2:
+            g = qi.pm1_weights(qi.barabasi_albert(n, 4, k), k)  # split hub rows for the larger ones
+            problem = "maxcut"
+        else:
+            g = qi.erdos_renyi(n, float(rng.uniform(3, 20)), k)
+            problem = "mis"
+        S = [16, 32, 32, 128, 7, 256][k % 6]
+        K = int(rng.integers(40, 160))
+        out.append((g, problem, S, K, 100 + k))
+    return out
+
+
+def test_batch_equals_alone_bitwise(ctx):
+    inst = _instances()
+    gids = [ctx.upload(g, p) for g, p, S, K, seed in inst]
+    ids = ctx.solve_batch(gids, [g["n"] for g, *_ in inst], [p for _, p, *_ in inst], [i[2] for i in inst],
+                          [i[3] for i in inst], [i[4] for i in inst])
+    batched = [ctx.poll(i) for i in ids]
+    for (g, p, S, K, seed), gid, b in zip(inst, gids, batched):
+        alone = ctx.poll(ctx.solve_resident(gid, g["n"], p, S, K, seed))
+        assert np.array_equal(b["obj"], alone["obj"]), (g["n"], p, S, K)
+        assert np.array_equal(b["size_or_cut"], alone["size_or_cut"])
+        assert np.array_equal(b["best_x"], alone["best_x"])
+        assert b["best_replica"] == alone["best_replica"]
+        assert b["step_loop_ms"] > 0
+    for gid in gids:
+        ctx.release(gid)
+
+
+def test_batch_of_one_and_repeat(ctx):
+    g = qi.erdos_renyi(800, 6.0, 3)
+    gid = ctx.upload(g, "mis")
+    a = ctx.poll(ctx.solve_batch([gid], [g["n"]], ["mis"], [64], [120], [9])[0])
+    b = ctx.poll(ctx.solve_batch([gid, gid], [g["n"]] * 2, ["mis"] * 2, [64, 64], [120, 120], [9, 10])[0])
+    ctx.release(gid)
+    assert np.array_equal(a["obj"], b["obj"]) and np.array_equal(a["best_x"], b["best_x"])
+
+
+def test_batch_rejects_bad_arguments(ctx):
+    import paper_2409_02135_amd as q
+    g = qi.erdos_renyi(100, 3.0, 1)
+    gid = ctx.upload(g, "mis")
+    with pytest.raises(q.QQAError) as e:
+        ctx.solve_batch([gid], [100], ["maxcut"], [16], [10], [0])
+    assert e.value.code == q.QQA_E_ARG
+    with pytest.raises(q.QQAError) as e:
+        ctx.solve_batch([gid, 999], [100, 100], ["mis", "mis"], [16, 16], [10, 10], [0, 1])
+    assert e.value.code == q.QQA_E_ARG
+    ctx.release(gid)
