@@ -122,7 +122,22 @@ typedef struct {
     double device_ms;            /* device time from first to last kernel of the request */
     double step_loop_ms;         /* device time of the K-update loop */
     double latency_ms;           /* submit -> result ready (host clock) */
+    int32_t engine;              /* qqa_engine that ran the update loop */
 } qqa_result;
+
+/* How the update loop runs.  STREAM: one launch per update, state streamed through
+ * memory.  PERSISTENT: one cooperative launch for all updates; every lane group keeps
+ * its rows' p, m, v in registers and only the new p goes to memory, updates separated by
+ * a grid barrier.  LDS_BLOCK: one workgroup with P in LDS (small instances).  BATCH: a
+ * ragged multi-instance launch (qqa_solve_batch, the server).  All engines perform the
+ * same arithmetic per row and give identical results. */
+typedef enum {
+    QQA_ENGINE_AUTO = -1,
+    QQA_ENGINE_STREAM = 0,
+    QQA_ENGINE_PERSISTENT = 1,
+    QQA_ENGINE_LDS_BLOCK = 2,
+    QQA_ENGINE_BATCH = 3
+} qqa_engine;
 
 /* device: HIP ordinal.  hbm_budget_bytes: cap on the device memory the context may
  * hold for requests (0 = 90% of free memory at creation).  hip_stream: stream to run
@@ -166,6 +181,12 @@ int qqa_set_replica_layout(qqa_ctx *c, int32_t S, int32_t lanes_per_row);
  * on scratch state), keep the fastest for S in this context and return it in
  * *lanes_per_row (may be NULL). */
 int qqa_autotune(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, int32_t S, int32_t *lanes_per_row);
+
+/* Engine policy of a context for single solves: QQA_ENGINE_AUTO (default) runs an instance
+ * on LDS_BLOCK or PERSISTENT when it qualifies (one quad per lane in a full-width layout,
+ * no rows split into chunks, state fits on chip), else STREAM; QQA_ENGINE_STREAM always
+ * streams. */
+int qqa_set_engine(qqa_ctx *c, qqa_engine policy);
 
 /* Wait up to timeout_us (0 = do not wait, < 0 = forever) for a request.  Returns QQA_OK
  * and fills *out when done (the handle is then released), QQA_PENDING if still
@@ -221,6 +242,15 @@ int qqa_dev_init(uint64_t seed, int32_t n, int32_t S, float *P, float *m, float 
 int qqa_dev_step(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule *sched, int32_t S,
                  int32_t t, int32_t K, uint64_t seed, const float *P_in, float *P_out, float *m,
                  float *v, int32_t lanes_per_row, void *stream);
+
+/* Updates t0 .. t1-1 of a K-update schedule with the given engine (QQA_ENGINE_AUTO picks
+ * as a context would) on caller buffers: P0 and P1 ping-pong (P[t0 & 1] holds the state
+ * before update t0, P[t1 & 1] the state after), m and v updated in place.  Returns
+ * QQA_E_ARG if the engine cannot run this instance, QQA_E_DEVICE if a persistent
+ * launch's barrier timed out.  Synchronous for the persistent engines' abort check. */
+int qqa_dev_run(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule *sched, int32_t S,
+                int32_t t0, int32_t t1, int32_t K, uint64_t seed, float *P0, float *P1, float *m, float *v,
+                int32_t engine, int32_t lanes_per_row, void *stream);
 
 /* Round x = [P > 1/2] and evaluate every replica exactly.  Outputs are device arrays:
  * size_or_cut[S], viol[S], obj[S] (int64) and best[1] (int32). */

@@ -22,6 +22,8 @@ QQA_E_ARG, QQA_E_GRAPH, QQA_E_NOMEM, QQA_E_ADMISSION = -1, -2, -3, -4
 QQA_E_DEVICE, QQA_E_UNKNOWN_REQ, QQA_E_CANCELLED = -5, -6, -7
 QQA_MIS, QQA_MAXCUT = 0, 1
 QQA_STEP_ADAMW, QQA_STEP_LANGEVIN = 0, 1
+QQA_ENGINE_AUTO, QQA_ENGINE_STREAM, QQA_ENGINE_PERSISTENT, QQA_ENGINE_LDS_BLOCK, QQA_ENGINE_BATCH = -1, 0, 1, 2, 3
+ENGINES = {"auto": -1, "stream": 0, "persistent": 1, "lds_block": 2, "batch": 3}
 
 PROBLEMS = {"mis": QQA_MIS, "maxcut": QQA_MAXCUT, QQA_MIS: QQA_MIS, QQA_MAXCUT: QQA_MAXCUT}
 
@@ -49,7 +51,8 @@ class qqa_result(C.Structure):
                 ("best_size_or_cut", C.c_int64), ("best_violations", C.c_int64),
                 ("replica_objective", C.c_void_p), ("replica_size_or_cut", C.c_void_p),
                 ("replica_violations", C.c_void_p), ("best_x", C.c_void_p), ("queue_ms", C.c_double),
-                ("device_ms", C.c_double), ("step_loop_ms", C.c_double), ("latency_ms", C.c_double)]
+                ("device_ms", C.c_double), ("step_loop_ms", C.c_double), ("latency_ms", C.c_double),
+                ("engine", C.c_int32)]
 
 
 class qqa_dev_graph(C.Structure):
@@ -91,6 +94,8 @@ def lib():
             "qqa_dev_init": (C.c_int, [u64, i32, i32, vp, vp, vp, vp]),
             "qqa_dev_step": (C.c_int, [vp, i32, vp, i32, i32, i32, u64, vp, vp, vp, vp, i32, vp]),
             "qqa_set_replica_layout": (C.c_int, [vp, i32, i32]),
+            "qqa_set_engine": (C.c_int, [vp, i32]),
+            "qqa_dev_run": (C.c_int, [vp, i32, vp, i32, i32, i32, i32, u64, vp, vp, vp, vp, i32, i32, vp]),
             "qqa_autotune": (C.c_int, [vp, i64, i32, i32, vp]),
             "qqa_dev_eval": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
         }
@@ -190,6 +195,14 @@ def qqa_dev_step(g: DevGraph, problem, sched: qqa_schedule | None, S, t, K, seed
                                          _stream(stream)))
 
 
+def qqa_dev_run(g: DevGraph, problem, sched: qqa_schedule | None, S, t0, t1, K, seed, P0, P1, m, v,
+                engine="auto", lanes_per_row=0, stream=None):
+    e = ENGINES[engine] if isinstance(engine, str) else engine
+    return _dev_check(lib().qqa_dev_run(C.byref(g.struct), PROBLEMS[problem], None if sched is None else C.byref(sched),
+                                        S, t0, t1, K, seed, _ptr(P0), _ptr(P1), _ptr(m), _ptr(v), e, lanes_per_row,
+                                        _stream(stream)))
+
+
 def qqa_dev_eval(g: DevGraph, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best, stream=None):
     return _dev_check(lib().qqa_dev_eval(C.byref(g.struct), PROBLEMS[problem], penalty_lambda, S, _ptr(P),
                                          _ptr(size_or_cut), _ptr(viol), _ptr(obj), _ptr(best), _stream(stream)))
@@ -253,6 +266,9 @@ class Context:
         gid = C.c_int64()
         self._check(lib().qqa_graph_upload(self._c, C.byref(st), PROBLEMS[problem], C.byref(gid)))
         return gid.value
+
+    def set_engine(self, policy):
+        self._check(lib().qqa_set_engine(self._c, ENGINES[policy] if isinstance(policy, str) else policy))
 
     def set_replica_layout(self, S: int, lanes_per_row: int):
         self._check(lib().qqa_set_replica_layout(self._c, S, lanes_per_row))
@@ -333,4 +349,5 @@ class Context:
         return Result(best_replica=res.best_replica, feasible=bool(res.feasible), best_objective=res.best_objective,
                       best_size_or_cut=res.best_size_or_cut, best_violations=res.best_violations, obj=objs,
                       size_or_cut=size, viol=viol, best_x=x, queue_ms=res.queue_ms, device_ms=res.device_ms,
-                      step_loop_ms=res.step_loop_ms, latency_ms=res.latency_ms)
+                      step_loop_ms=res.step_loop_ms, latency_ms=res.latency_ms,
+                      engine={v: k for k, v in ENGINES.items()}.get(res.engine, res.engine))

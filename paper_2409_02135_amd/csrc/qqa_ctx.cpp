@@ -25,14 +25,18 @@ size_t request_footprint(int n, int S, int rule) {
   return state + out_bytes(n, S) + 2 * stride * sizeof(unsigned long long) + 4096;
 }
 
-size_t out_bytes(int n, int S) { return 3 * (size_t)S * sizeof(int64_t) + 8 + (size_t)n; }
+// result record: size_or_cut[S], viol[S], obj[S] (int64), best (int32) + pad, barrier
+// words (2 x uint32), x[n] (uint8)
+size_t out_bytes(int n, int S) { return 3 * (size_t)S * sizeof(int64_t) + 16 + (size_t)n; }
+
+unsigned* out_bar(char* base, int S) { return reinterpret_cast<unsigned*>(base + 3 * (size_t)S * sizeof(int64_t) + 8); }
 
 void out_views(char* base, int n, int S, int64_t** a, int64_t** b, int64_t** o, int32_t** best, uint8_t** x) {
   *a = reinterpret_cast<int64_t*>(base);
   *b = *a + S;
   *o = *b + S;
   *best = reinterpret_cast<int32_t*>(*o + S);
-  *x = reinterpret_cast<uint8_t*>(base + 3 * (size_t)S * sizeof(int64_t) + 8);
+  *x = reinterpret_cast<uint8_t*>(base + 3 * (size_t)S * sizeof(int64_t) + 16);
   (void)n;
 }
 
@@ -145,6 +149,10 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
   r->hub_partial = nullptr;
   c->dpool.put(r->out_dev, r->out_size);
   c->hpool.put(r->out_host, r->out_size);
+  c->dpool.put(r->table_dev, r->table_bytes);
+  c->hpool.put(r->table_host, r->table_bytes);
+  r->table_dev = nullptr;
+  r->table_host = nullptr;
   r->P[0] = r->P[1] = r->m = r->v = nullptr;
   r->acc = nullptr;
   r->out_dev = r->out_host = nullptr;
@@ -233,24 +241,64 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   r->lanes_per_row = c->layout_for(S);
   r->footprint = request_footprint(g.n, S, r->sched.rule) + (size_t)g.nchunks * r->shape.stride * sizeof(float);
   if (r->footprint + g.bytes > c->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the HBM budget");
+  {
+    StepParams probe = request_step_params(r.get(), g);
+    const int allow = c->engine_policy < 0 ? 3 : (c->engine_policy == QQA_ENGINE_LDS_BLOCK ? 1 :
+                                                  (c->engine_policy == QQA_ENGINE_PERSISTENT ? 2 : 0));
+    r->engine = allow ? persistent_plan(probe, g.nchunks > 0, allow, &r->rows_per_group, &r->grid) : kEngineStream;
+    if (r->engine != kEngineStream) {
+      r->table_bytes = (size_t)steps * sizeof(float4);
+      r->footprint += r->table_bytes;
+    }
+  }
   if (c->in_use + r->footprint > c->budget)
     return set_err(c, QQA_E_NOMEM, "HBM budget held by earlier requests; poll them first");
   int rc = alloc_request_buffers(c, r.get(), &c->err, g.nchunks);
   if (rc) return rc;
+  hipError_t e = hipSuccess;
+  if (r->table_bytes) {
+    e = c->dpool.get(r->table_bytes, (void**)&r->table_dev);
+    if (e == hipSuccess) e = c->hpool.get(r->table_bytes, (void**)&r->table_host);
+    if (e != hipSuccess) {
+      release_request_buffers(c, r.get());
+      return set_err(c, QQA_E_NOMEM, std::string("request buffers: ") + hipGetErrorString(e));
+    }
+    StepParams q{};
+    for (int t = 0; t < steps; ++t) {
+      fill_step_scalars(q, r->sched, t, steps);
+      r->table_host[t] = make_float4(q.ce, q.inv_bc1, q.inv_bc2, 0.f);
+    }
+  }
   c->in_use += r->footprint;
   g.refs++;
   r->t_submit = Clock::now();
 
-  hipError_t e = hipEventRecord(r->ev[0], c->stream);
+  e = hipEventRecord(r->ev[0], c->stream);
   if (e == hipSuccess) e = launch_init(seed, g.n, S, r->P[0], r->m, r->v, c->stream);
   if (e == hipSuccess) e = hipEventRecord(r->ev[1], c->stream);
   StepParams p = request_step_params(r.get(), g);
-  for (int t = 0; t < steps && e == hipSuccess; ++t) {
-    p.P_in = r->P[t & 1];
-    p.P_out = r->P[(t + 1) & 1];
-    fill_step_scalars(p, r->sched, t, steps);
-    if (g.nchunks) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
-    if (e == hipSuccess) e = launch_step(p, c->stream);
+  if (r->engine == kEngineStream) {
+    for (int t = 0; t < steps && e == hipSuccess; ++t) {
+      p.P_in = r->P[t & 1];
+      p.P_out = r->P[(t + 1) & 1];
+      fill_step_scalars(p, r->sched, t, steps);
+      if (g.nchunks) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
+      if (e == hipSuccess) e = launch_step(p, c->stream);
+    }
+  } else {
+    unsigned* bar = out_bar(r->out_dev, S);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(r->table_dev, r->table_host, r->table_bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_fill_u64(reinterpret_cast<unsigned long long*>(bar), 1, c->stream);
+    PersistParams pp{};
+    pp.a = p;
+    pp.P[0] = r->P[0];
+    pp.P[1] = r->P[1];
+    pp.table = r->table_dev;
+    pp.t0 = 0;
+    pp.t1 = steps;
+    pp.bar = bar;
+    if (e == hipSuccess) e = launch_persistent(pp, r->engine, r->rows_per_group, r->grid, c->stream);
   }
   if (e == hipSuccess) e = hipEventRecord(r->ev[2], c->stream);
   if (e == hipSuccess) e = enqueue_finish(c, r.get(), g, r->P[steps & 1]);
@@ -365,6 +413,13 @@ int qqa_solve_resident(qqa_ctx* c, qqa_graph_id g, qqa_problem problem, const qq
   return submit_plain(c, g, false, problem, sched, S, steps, seed, out_id);
 }
 
+int qqa_set_engine(qqa_ctx* c, qqa_engine policy) {
+  if (!c) return QQA_E_ARG;
+  if (policy < QQA_ENGINE_AUTO || policy > QQA_ENGINE_LDS_BLOCK) return set_err(c, QQA_E_ARG, "unknown engine policy");
+  c->engine_policy = policy;
+  return QQA_OK;
+}
+
 int qqa_set_replica_layout(qqa_ctx* c, int32_t S, int32_t lanes_per_row) {
   if (!c) return QQA_E_ARG;
   if (S <= 0 || S > kMaxReplicas) return set_err(c, QQA_E_ARG, "S must be in [1, 4096]");
@@ -457,8 +512,11 @@ int qqa_poll(qqa_ctx* c, qqa_req id, qqa_result* out, int32_t timeout_us) {
   int rc = QQA_OK;
   if (r->cancelled) {
     rc = set_err(c, QQA_E_CANCELLED, "request was cancelled");
+  } else if (r->engine != kEngineStream && r->engine != 3 && out_bar(r->out_host, r->S)[1] != 0u) {
+    rc = set_err(c, QQA_E_DEVICE, "persistent engine: grid barrier timed out");
   } else if (out) {
     fill_result(r, out);
+    out->engine = r->engine;
     float ms = 0.f;
     out->queue_ms = r->queue_ms;
     out->device_ms = hipEventElapsedTime(&ms, r->ev[0], r->ev[3]) == hipSuccess ? ms : -1.0;

@@ -44,6 +44,11 @@ struct Request {
   uint64_t seed = 0;
   ReplicaShape shape{};
   int lanes_per_row = 0;
+  int engine = 0;               // PersistEngine of the update loop (3: batch slots)
+  int rows_per_group = 0, grid = 0;
+  float4* table_dev = nullptr;  // per-update scalars (persistent engines)
+  float4* table_host = nullptr;
+  size_t table_bytes = 0;
   size_t footprint = 0;
   float* P[2] = {nullptr, nullptr};
   float* m = nullptr;
@@ -81,6 +86,7 @@ struct qqa_ctx {
   int64_t next_req = 1;
   std::unique_ptr<qqa::Server> server;
   std::unordered_map<int, int> layout;  // S -> lanes per row (absent: default)
+  int engine_policy = -1;                // qqa_engine: -1 auto, 0 stream only
   int layout_for(int S) const {
     auto it = layout.find(S);
     return it == layout.end() ? 0 : it->second;
@@ -94,6 +100,8 @@ namespace qqa {
 size_t request_footprint(int n, int S, int rule);
 size_t out_bytes(int n, int S);
 void out_views(char* base, int n, int S, int64_t** a, int64_t** b, int64_t** o, int32_t** best, uint8_t** x);
+// barrier words of a persistent launch inside a result record: [0] arrivals, [1] abort
+unsigned* out_bar(char* base, int S);
 int upload_graph(qqa_ctx* c, const qqa_graph& g, int problem, DevGraph* out, std::string* why);
 void free_graph(DevGraph& d);
 void graph_unref(qqa_ctx* c, int64_t gid);

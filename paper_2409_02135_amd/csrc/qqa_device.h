@@ -73,22 +73,26 @@ __device__ __forceinline__ float ipow_odd(float z, int e) {
   return r;
 }
 
+// Neighbour rows loaded per iteration of the coupling loop (independent loads in flight).
+constexpr int kGatherUnroll = 4;
+
 // acc += sum over edges e in [e_begin, e_end) of w_e * f(p_col(e)), in edge order, with
-// f(p) = p (MIS) or 2p - 1 (max-cut); four neighbour rows are loaded per iteration.
+// f(p) = p (MIS) or 2p - 1 (max-cut); kGatherUnroll neighbour rows are loaded per iteration.
 template <int LPR, int QPL, bool FULL>
 __device__ __forceinline__ void gather_coupling(const StepParams& a, const int e_begin, const int e_end, const int gl,
                                                 const int nq, const bool maxcut, float4 (&acc)[QPL]) {
-  for (int e0 = e_begin; e0 < e_end; e0 += 4) {
-    int j[4];
-    float w[4];
+  constexpr int U = kGatherUnroll;
+  for (int e0 = e_begin; e0 < e_end; e0 += U) {
+    int j[U];
+    float w[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int e = e0 + u;
       j[u] = e < e_end ? a.col[e] : -1;
       w[u] = e < e_end ? (a.w ? a.w[e] : 1.f) : 0.f;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       if (j[u] < 0) continue;
       const float* pj = a.P_in + (size_t)j[u] * a.stride;
 #pragma unroll
@@ -113,41 +117,42 @@ __device__ __forceinline__ void gather_coupling(const StepParams& a, const int e
 }
 
 // FULL: S == 4 * LPR * QPL, every lane owns whole, valid quads (no replica masks).
-template <int LPR, int QPL, bool FULL>
-__device__ __forceinline__ void update_row(const StepParams& a, const int row, const int gl) {
-  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
-  const bool maxcut = a.problem == kMAXCUT;
-  const bool adam = a.rule == kADAMW;
-  const size_t base = (size_t)row * a.stride;
 
-  // own row first, so its loads overlap the neighbour gathers below
-  float4 p[QPL], mm[QPL], vv[QPL];
+// A row's own replica values (p, and the AdamW moments when used) for lane gl.
+template <int LPR, int QPL, bool FULL>
+__device__ __forceinline__ void load_row(const StepParams& a, const float* P, const int row, const int gl,
+                                         float4 (&p)[QPL], float4 (&mm)[QPL], float4 (&vv)[QPL]) {
+  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
+  const size_t base = (size_t)row * a.stride;
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int q = gl + LPR * k;
     p[k] = mm[k] = vv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (FULL || q < nq) {
-      p[k] = *reinterpret_cast<const float4*>(a.P_in + base + 4 * q);
-      if (adam) {
+      p[k] = *reinterpret_cast<const float4*>(P + base + 4 * q);
+      if (a.rule == kADAMW) {
         mm[k] = *reinterpret_cast<const float4*>(a.m + base + 4 * q);
         vv[k] = *reinterpret_cast<const float4*>(a.v + base + 4 * q);
       }
     }
   }
+}
 
-  // (1) coupling product C_i = sum_j A_ij p_j (MIS) or sum_j A_ij (2 p_j - 1) (max-cut),
-  //     accumulated in CSR order so that the rounding sequence depends on the graph only
-  float4 acc[QPL];
+// Coupling product of one row: C_i = sum_j A_ij p_j (MIS) or sum_j A_ij (2 p_j - 1)
+// (max-cut), accumulated in CSR order (or chunk order for split rows) so that the
+// rounding sequence depends on the graph only.
+template <int LPR, int QPL, bool FULL>
+__device__ __forceinline__ void row_coupling(const StepParams& a, const int row, const int gl, float4 (&acc)[QPL]) {
+  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
 #pragma unroll
   for (int k = 0; k < QPL; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
   if (a.coupling) {
 #pragma unroll
     for (int k = 0; k < QPL; ++k) {
       const int q = gl + LPR * k;
-      if (FULL || q < nq) acc[k] = *reinterpret_cast<const float4*>(a.coupling + base + 4 * q);
+      if (FULL || q < nq) acc[k] = *reinterpret_cast<const float4*>(a.coupling + (size_t)row * a.stride + 4 * q);
     }
   } else if (a.hub_first && a.hub_first[row] >= 0) {
-    // split row: partial sums of its chunks, added in chunk order
     const int first = a.hub_first[row];
     const int nch = (a.row_ptr[row + 1] - a.row_ptr[row] + kHubChunk - 1) / kHubChunk;
     for (int c = 0; c < nch; ++c) {
@@ -165,10 +170,21 @@ __device__ __forceinline__ void update_row(const StepParams& a, const int row, c
       }
     }
   } else {
-    gather_coupling<LPR, QPL, FULL>(a, a.row_ptr[row], a.row_ptr[row + 1], gl, nq, maxcut, acc);
+    gather_coupling<LPR, QPL, FULL>(a, a.row_ptr[row], a.row_ptr[row + 1], gl, nq, a.problem == kMAXCUT, acc);
   }
+}
 
-  // (2) replica statistics mu_i, sigma_i (two passes, population STD)
+// Everything after the coupling product: replica statistics mu_i, sigma_i (two passes,
+// population STD), gradient, AdamW or plain step, noise, clamp.  Writes the new values
+// of lane gl's replicas to po / mo / vo (padding replicas 0).
+template <int LPR, int QPL, bool FULL>
+__device__ __forceinline__ void finish_row(const StepParams& a, const int row, const int gl, const float4 (&p)[QPL],
+                                           const float4 (&mm)[QPL], const float4 (&vv)[QPL],
+                                           const float4 (&acc)[QPL], float4 (&po)[QPL], float4 (&mo)[QPL],
+                                           float4 (&vo)[QPL]) {
+  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
+  const bool maxcut = a.problem == kMAXCUT;
+  const bool adam = a.rule == kADAMW;
   float sum = 0.f;
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
@@ -194,13 +210,12 @@ __device__ __forceinline__ void update_row(const StepParams& a, const int row, c
   const float sigma = __builtin_amdgcn_sqrtf(sq * a.inv_S);
   const float cg = sigma > 0.f ? -a.comm_alpha * __builtin_amdgcn_rcpf(sigma) : 0.f;
 
-  // (3) gradient, step, noise, clamp
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int q = gl + LPR * k;
+    po[k] = mo[k] = vo[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (!FULL && q >= nq) continue;
     const float4 xi = normals4(philox4x32_10((uint32_t)row, (uint32_t)q, a.k, kStreamNoise, a.key0, a.key1));
-    float4 po, mo, vo;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const float pc = comp(p[k], c);
@@ -222,16 +237,39 @@ __device__ __forceinline__ void update_row(const StepParams& a, const int row, c
       pn = fmaf(a.noise_scale, comp(xi, c), pn);
       pn = fminf(fmaxf(pn, 0.f), 1.f);
       const bool valid = FULL || 4 * q + c < a.S;
-      set_comp(po, c, valid ? pn : 0.f);
-      set_comp(mo, c, valid ? mn : 0.f);
-      set_comp(vo, c, valid ? vn : 0.f);
-    }
-    *reinterpret_cast<float4*>(a.P_out + base + 4 * q) = po;
-    if (adam) {
-      *reinterpret_cast<float4*>(a.m + base + 4 * q) = mo;
-      *reinterpret_cast<float4*>(a.v + base + 4 * q) = vo;
+      set_comp(po[k], c, valid ? pn : 0.f);
+      set_comp(mo[k], c, valid ? mn : 0.f);
+      set_comp(vo[k], c, valid ? vn : 0.f);
     }
   }
+}
+
+template <int LPR, int QPL, bool FULL>
+__device__ __forceinline__ void store_row(const StepParams& a, float* P, const int row, const int gl,
+                                          const float4 (&po)[QPL], const float4 (&mo)[QPL], const float4 (&vo)[QPL],
+                                          const bool moments) {
+  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
+  const size_t base = (size_t)row * a.stride;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int q = gl + LPR * k;
+    if (!FULL && q >= nq) continue;
+    *reinterpret_cast<float4*>(P + base + 4 * q) = po[k];
+    if (moments && a.rule == kADAMW) {
+      *reinterpret_cast<float4*>(a.m + base + 4 * q) = mo[k];
+      *reinterpret_cast<float4*>(a.v + base + 4 * q) = vo[k];
+    }
+  }
+}
+
+// One update of one row, state streamed from and to memory.
+template <int LPR, int QPL, bool FULL>
+__device__ __forceinline__ void update_row(const StepParams& a, const int row, const int gl) {
+  float4 p[QPL], mm[QPL], vv[QPL], acc[QPL], po[QPL], mo[QPL], vo[QPL];
+  load_row<LPR, QPL, FULL>(a, a.P_in, row, gl, p, mm, vv);  // issued before the gathers
+  row_coupling<LPR, QPL, FULL>(a, row, gl, acc);
+  finish_row<LPR, QPL, FULL>(a, row, gl, p, mm, vv, acc, po, mo, vo);
+  store_row<LPR, QPL, FULL>(a, a.P_out, row, gl, po, mo, vo, true);
 }
 
 }  // namespace qqa

@@ -18,7 +18,7 @@ constexpr int kBlock = 256;
 // Rows with more than kHubDegree neighbours are split into chunks of kHubChunk edges whose
 // partial coupling sums are computed by their own lane groups (hub_partial_kernel).
 constexpr int kHubDegree = 64;
-constexpr int kHubChunk = 32;
+constexpr int kHubChunk = 16;
 
 // How the S replicas of one variable map onto lanes: a row is served by `lpr` adjacent
 // lanes (a power of two, at most one wavefront), each lane owns `qpl` float4 quads.
@@ -126,6 +126,26 @@ hipError_t launch_clock_advance(int32_t* clock, int by, hipStream_t st);
 // finalize (objectives + best replica), extract x of the best replica.
 hipError_t launch_slot_eval(const SlotDesc* slots, const int32_t* slot_ids, int nslots, const WorkItem* items,
                             int nitems, int S, int lanes_per_row, hipStream_t st);
+
+// ---- persistent engines ----------------------------------------------------------------
+// One launch runs updates [t0, t1) of one instance.  Every lane group owns rows_per_group
+// consecutive rows for the whole launch and keeps their p, m, v in registers; only the new
+// p of each update goes to memory, for the neighbours to read.  The multi-block engine
+// separates updates with a grid barrier (cooperative launch, bounded spin: on time-out it
+// raises bar[1] and every block returns); the single-block engine keeps P itself in LDS.
+struct PersistParams {
+  StepParams a;                 // static fields; per-update fields come from `table`
+  float* P[2];                  // P[t0 & 1] holds the state before update t0
+  const float4* table;          // per update t: {ce, inv_bc1, inv_bc2, 0}
+  int32_t t0, t1;
+  unsigned* bar;                // [0] arrivals (zero before the launch), [1] abort flag
+};
+enum PersistEngine { kEngineStream = 0, kEnginePersistent = 1, kEngineLdsBlock = 2 };
+// Which engine can run this instance (FULL layouts with one quad per lane, no split
+// rows); `allow` is a mask (1: one workgroup with P in LDS, 2: many workgroups with state
+// in registers).  Fills rows per group and the grid for the chosen one.
+int persistent_plan(const StepParams& a, bool has_hubs, int allow, int* rows_per_group, int* grid);
+hipError_t launch_persistent(const PersistParams& pp, int engine, int rows_per_group, int grid, hipStream_t st);
 
 hipError_t launch_philox(uint64_t seed, int n, int nquads, uint32_t k, uint32_t stream_id, uint32_t* out,
                          hipStream_t st);

@@ -344,6 +344,113 @@ int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule
   return QQA_OK;
 }
 
+int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule* sched, int32_t S, int32_t t0,
+                int32_t t1, int32_t K, uint64_t seed, float* P0, float* P1, float* m, float* v, int32_t engine,
+                int32_t lanes_per_row, void* stream) {
+  int rc = dev_graph_check(g);
+  if (rc) return rc;
+  if (problem != QQA_MIS && problem != QQA_MAXCUT) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
+  if (S <= 0 || S > kMaxReplicas) return fail(&g_dev_error, QQA_E_ARG, "S must be in [1, 4096]");
+  if (K <= 0 || t0 < 0 || t1 < t0 || t1 > K) return fail(&g_dev_error, QQA_E_ARG, "need 0 <= t0 <= t1 <= K");
+  qqa_schedule s;
+  if (sched) s = *sched; else qqa_schedule_default(&s, problem, g->n);
+  std::string why;
+  if (!schedule_valid(s, &why)) return fail(&g_dev_error, QQA_E_ARG, why);
+  if (g->n > 0 && (!P0 || !P1 || P0 == P1)) return fail(&g_dev_error, QQA_E_ARG, "need two distinct P buffers");
+  if (s.rule == QQA_STEP_ADAMW && g->n > 0 && (!m || !v)) return fail(&g_dev_error, QQA_E_ARG, "AdamW needs m and v");
+  if (lanes_per_row < 0 || lanes_per_row > 64 || !layout_supported(S, lanes_per_row))
+    return fail(&g_dev_error, QQA_E_ARG, "unsupported replica layout");
+  if (g->n == 0 || t0 == t1) return QQA_OK;
+  hipStream_t st = (hipStream_t)stream;
+  StepParams p{};
+  p.row_ptr = g->row_ptr;
+  p.col = g->col_idx;
+  p.w = problem == QQA_MAXCUT ? g->weight : nullptr;
+  p.m = m;
+  p.v = v;
+  p.n = g->n;
+  fill_static_scalars(p, s, problem, S, seed);
+  p.lanes_per_row = lanes_per_row;
+  std::vector<int32_t> rp(g->n + 1);
+  DEV_CHECK(hipMemcpyAsync(rp.data(), g->row_ptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  DEV_CHECK(hipStreamSynchronize(st));
+  std::vector<HubChunk> chunks;
+  std::vector<int32_t> hub_first;
+  build_hub_plan(rp.data(), g->n, &chunks, &hub_first);
+  int rpg = 0, grid = 0;
+  int use = kEngineStream;
+  if (engine != kEngineStream) {
+    // allow mask: 1 = one workgroup with P in LDS, 2 = many workgroups with registers
+    const int allow = engine < 0 ? 3 : (engine == kEngineLdsBlock ? 1 : (engine == kEnginePersistent ? 2 : 0));
+    if (!allow) return fail(&g_dev_error, QQA_E_ARG, "unknown engine");
+    use = persistent_plan(p, !chunks.empty(), allow, &rpg, &grid);
+    if (engine >= 0 && use != engine) return fail(&g_dev_error, QQA_E_ARG, "engine cannot run this instance");
+  }
+  float* P[2] = {P0, P1};
+  if (use == kEngineStream) {
+    HubChunk* d_chunks = nullptr;
+    int32_t* d_first = nullptr;
+    float* d_part = nullptr;
+    if (!chunks.empty()) {
+      DEV_CHECK(hipMallocAsync((void**)&d_chunks, chunks.size() * sizeof(HubChunk), st));
+      DEV_CHECK(hipMallocAsync((void**)&d_first, hub_first.size() * sizeof(int32_t), st));
+      DEV_CHECK(hipMallocAsync((void**)&d_part, chunks.size() * (size_t)p.stride * sizeof(float), st));
+      DEV_CHECK(hipMemcpyAsync(d_chunks, chunks.data(), chunks.size() * sizeof(HubChunk), hipMemcpyHostToDevice, st));
+      DEV_CHECK(hipMemcpyAsync(d_first, hub_first.data(), hub_first.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      p.hub_first = d_first;
+      p.hub_partial = d_part;
+    }
+    hipError_t e = hipSuccess;
+    for (int t = t0; t < t1 && e == hipSuccess; ++t) {
+      p.P_in = P[t & 1];
+      p.P_out = P[(t + 1) & 1];
+      fill_step_scalars(p, s, t, K);
+      if (!chunks.empty()) e = launch_hub_partials(p, d_chunks, (int)chunks.size(), st);
+      if (e == hipSuccess) e = launch_step(p, st);
+    }
+    if (!chunks.empty()) {
+      (void)hipFreeAsync(d_chunks, st);
+      (void)hipFreeAsync(d_first, st);
+      (void)hipFreeAsync(d_part, st);
+      DEV_CHECK(hipStreamSynchronize(st));
+    }
+    DEV_CHECK(e);
+    return QQA_OK;
+  }
+  // persistent engines: per-update table and barrier words
+  std::vector<float4> table((size_t)K);
+  for (int t = 0; t < K; ++t) {
+    StepParams q{};
+    fill_step_scalars(q, s, t, K);
+    table[t] = make_float4(q.ce, q.inv_bc1, q.inv_bc2, 0.f);
+  }
+  float4* d_table = nullptr;
+  unsigned* d_bar = nullptr;
+  DEV_CHECK(hipMallocAsync((void**)&d_table, table.size() * sizeof(float4), st));
+  DEV_CHECK(hipMallocAsync((void**)&d_bar, 256, st));
+  DEV_CHECK(hipMemcpyAsync(d_table, table.data(), table.size() * sizeof(float4), hipMemcpyHostToDevice, st));
+  DEV_CHECK(launch_fill_u64(reinterpret_cast<unsigned long long*>(d_bar), 1, st));
+  PersistParams pp{};
+  pp.a = p;
+  pp.P[0] = P0;
+  pp.P[1] = P1;
+  pp.table = d_table;
+  pp.t0 = t0;
+  pp.t1 = t1;
+  pp.bar = d_bar;
+  hipError_t e = launch_persistent(pp, use, rpg, grid, st);
+  unsigned bar[2] = {0, 0};
+  hipError_t e2 = hipMemcpyAsync(bar, d_bar, sizeof(bar), hipMemcpyDeviceToHost, st);
+  hipError_t e3 = hipStreamSynchronize(st);
+  (void)hipFreeAsync(d_table, st);
+  (void)hipFreeAsync(d_bar, st);
+  DEV_CHECK(e);
+  DEV_CHECK(e2);
+  DEV_CHECK(e3);
+  if (bar[1] != 0u) return fail(&g_dev_error, QQA_E_DEVICE, "persistent engine: grid barrier timed out");
+  return QQA_OK;
+}
+
 int qqa_dev_eval(const qqa_dev_graph* g, qqa_problem problem, int32_t penalty_lambda, int32_t S, const float* P,
                  int64_t* size_or_cut, int64_t* viol, int64_t* obj, int32_t* best, void* stream) {
   if (!g || g->n < 0) return fail(&g_dev_error, QQA_E_ARG, "graph is NULL or n < 0");

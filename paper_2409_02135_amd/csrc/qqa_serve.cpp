@@ -318,6 +318,7 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     r->seed = I.seed;
     r->shape = replica_shape(I.S);
     r->lanes_per_row = I.lanes;
+    r->engine = 3;
     r->out_host = run->host_out + I.out_off;
     r->out_size = I.L.out_size;
     for (int k = 0; k < 4; ++k) r->ev[k] = run->ev[k];
