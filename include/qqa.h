@@ -183,9 +183,10 @@ int qqa_set_replica_layout(qqa_ctx *c, int32_t S, int32_t lanes_per_row);
 int qqa_autotune(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, int32_t S, int32_t *lanes_per_row);
 
 /* Engine policy of a context for single solves: QQA_ENGINE_AUTO (default) runs an instance
- * on LDS_BLOCK or PERSISTENT when it qualifies (one quad per lane in a full-width layout,
- * no rows split into chunks, state fits on chip), else STREAM; QQA_ENGINE_STREAM always
- * streams. */
+ * on LDS_BLOCK when it qualifies (one quad per lane in a full-width layout, no rows split
+ * into chunks, P fits in one workgroup's LDS), else STREAM; QQA_ENGINE_PERSISTENT runs the
+ * register-resident engine when the instance fits on chip (else STREAM);
+ * QQA_ENGINE_LDS_BLOCK / QQA_ENGINE_STREAM force those engines where possible. */
 int qqa_set_engine(qqa_ctx *c, qqa_engine policy);
 
 /* Wait up to timeout_us (0 = do not wait, < 0 = forever) for a request.  Returns QQA_OK

@@ -243,8 +243,10 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   if (r->footprint + g.bytes > c->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the HBM budget");
   {
     StepParams probe = request_step_params(r.get(), g);
-    const int allow = c->engine_policy < 0 ? 3 : (c->engine_policy == QQA_ENGINE_LDS_BLOCK ? 1 :
-                                                  (c->engine_policy == QQA_ENGINE_PERSISTENT ? 2 : 0));
+    // auto: one workgroup with P in LDS when the instance fits, else one launch per update
+    // (measured faster on this GPU than the register-resident engine for larger instances)
+    const int allow = c->engine_policy < 0 ? 1 : (c->engine_policy == QQA_ENGINE_LDS_BLOCK ? 1 :
+                                                 (c->engine_policy == QQA_ENGINE_PERSISTENT ? 2 : 0));
     r->engine = allow ? persistent_plan(probe, g.nchunks > 0, allow, &r->rows_per_group, &r->grid) : kEngineStream;
     if (r->engine != kEngineStream) {
       r->table_bytes = (size_t)steps * sizeof(float4);

@@ -73,12 +73,31 @@ __device__ __forceinline__ float ipow_odd(float z, int e) {
   return r;
 }
 
+// Device-coherent float4 access for state that other workgroups of a running kernel read:
+// two 64-bit agent-scope relaxed atomic accesses, which the compiler emits as L2-bypassing
+// (write-through) memory instructions, so no cache write-back or invalidation is needed to
+// share the values across the chip.
+__device__ __forceinline__ float4 load_coherent(const float* p) {
+  const unsigned long long lo =
+      __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long hi =
+      __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p) + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return make_float4(__uint_as_float((unsigned)lo), __uint_as_float((unsigned)(lo >> 32)), __uint_as_float((unsigned)hi),
+                     __uint_as_float((unsigned)(hi >> 32)));
+}
+__device__ __forceinline__ void store_coherent(float* p, const float4 v) {
+  const unsigned long long lo = (unsigned long long)__float_as_uint(v.x) | ((unsigned long long)__float_as_uint(v.y) << 32);
+  const unsigned long long hi = (unsigned long long)__float_as_uint(v.z) | ((unsigned long long)__float_as_uint(v.w) << 32);
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p) + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Neighbour rows loaded per iteration of the coupling loop (independent loads in flight).
 constexpr int kGatherUnroll = 4;
 
 // acc += sum over edges e in [e_begin, e_end) of w_e * f(p_col(e)), in edge order, with
 // f(p) = p (MIS) or 2p - 1 (max-cut); kGatherUnroll neighbour rows are loaded per iteration.
-template <int LPR, int QPL, bool FULL>
+template <int LPR, int QPL, bool FULL, bool COHERENT = false>
 __device__ __forceinline__ void gather_coupling(const StepParams& a, const int e_begin, const int e_end, const int gl,
                                                 const int nq, const bool maxcut, float4 (&acc)[QPL]) {
   constexpr int U = kGatherUnroll;
@@ -99,7 +118,7 @@ __device__ __forceinline__ void gather_coupling(const StepParams& a, const int e
       for (int k = 0; k < QPL; ++k) {
         const int q = gl + LPR * k;
         if (FULL || q < nq) {
-          float4 x = *reinterpret_cast<const float4*>(pj + 4 * q);
+          float4 x = COHERENT ? load_coherent(pj + 4 * q) : *reinterpret_cast<const float4*>(pj + 4 * q);
           if (maxcut) {
             x.x = 2.f * x.x - 1.f;
             x.y = 2.f * x.y - 1.f;
@@ -141,7 +160,7 @@ __device__ __forceinline__ void load_row(const StepParams& a, const float* P, co
 // Coupling product of one row: C_i = sum_j A_ij p_j (MIS) or sum_j A_ij (2 p_j - 1)
 // (max-cut), accumulated in CSR order (or chunk order for split rows) so that the
 // rounding sequence depends on the graph only.
-template <int LPR, int QPL, bool FULL>
+template <int LPR, int QPL, bool FULL, bool COHERENT = false>
 __device__ __forceinline__ void row_coupling(const StepParams& a, const int row, const int gl, float4 (&acc)[QPL]) {
   const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
 #pragma unroll
@@ -170,7 +189,8 @@ __device__ __forceinline__ void row_coupling(const StepParams& a, const int row,
       }
     }
   } else {
-    gather_coupling<LPR, QPL, FULL>(a, a.row_ptr[row], a.row_ptr[row + 1], gl, nq, a.problem == kMAXCUT, acc);
+    gather_coupling<LPR, QPL, FULL, COHERENT>(a, a.row_ptr[row], a.row_ptr[row + 1], gl, nq, a.problem == kMAXCUT,
+                                              acc);
   }
 }
 
@@ -244,7 +264,7 @@ __device__ __forceinline__ void finish_row(const StepParams& a, const int row, c
   }
 }
 
-template <int LPR, int QPL, bool FULL>
+template <int LPR, int QPL, bool FULL, bool COHERENT = false>
 __device__ __forceinline__ void store_row(const StepParams& a, float* P, const int row, const int gl,
                                           const float4 (&po)[QPL], const float4 (&mo)[QPL], const float4 (&vo)[QPL],
                                           const bool moments) {
@@ -254,7 +274,8 @@ __device__ __forceinline__ void store_row(const StepParams& a, float* P, const i
   for (int k = 0; k < QPL; ++k) {
     const int q = gl + LPR * k;
     if (!FULL && q >= nq) continue;
-    *reinterpret_cast<float4*>(P + base + 4 * q) = po[k];
+    if (COHERENT) store_coherent(P + base + 4 * q, po[k]);
+    else *reinterpret_cast<float4*>(P + base + 4 * q) = po[k];
     if (moments && a.rule == kADAMW) {
       *reinterpret_cast<float4*>(a.m + base + 4 * q) = mo[k];
       *reinterpret_cast<float4*>(a.v + base + 4 * q) = vo[k];

@@ -13,14 +13,15 @@ constexpr unsigned kSpinLimit = 1u << 22;  // about seconds of polling: a barrie
 constexpr int kLdsBlock = 1024;
 
 // Grid-wide barrier: every block arrives once per update; `target` counts arrivals since
-// the launch.  Release/acquire fences at agent scope publish this block's stores of P and
-// make the other blocks' visible.  Returns false when the barrier aborted.
+// the launch.  The state other blocks read (P) is written and read with device-coherent
+// accesses, so the barrier only has to order completion: each wave waits for its stores
+// to complete before the workgroup arrives.  Returns false when the barrier aborted.
 __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned target) {
   __shared__ int ok;
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's coherent stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
     int good = 1;
-    __threadfence();
     atomicAdd(&bar[0], 1u);
     unsigned spins = 0;
     while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -29,9 +30,8 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned target) {
         good = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
-    __threadfence();
     ok = good;
   }
   __syncthreads();
@@ -46,7 +46,7 @@ __device__ __forceinline__ void per_update(const PersistParams& pp, int t, StepP
   a->k = (uint32_t)t + 1u;
 }
 
-template <int LPR, int RPG>
+template <int LPR, int RPG, bool COHERENT>
 __device__ __forceinline__ void run_rows(StepParams& a, const int row0, const int gl, float4 (&p)[RPG][1],
                                          float4 (&mm)[RPG][1], float4 (&vv)[RPG][1]) {
 #pragma unroll
@@ -54,9 +54,9 @@ __device__ __forceinline__ void run_rows(StepParams& a, const int row0, const in
     const int row = row0 + r;
     if (row >= a.n) continue;
     float4 acc[1], po[1], mo[1], vo[1];
-    row_coupling<LPR, 1, true>(a, row, gl, acc);
+    row_coupling<LPR, 1, true, COHERENT>(a, row, gl, acc);
     finish_row<LPR, 1, true>(a, row, gl, p[r], mm[r], vv[r], acc, po, mo, vo);
-    store_row<LPR, 1, true>(a, a.P_out, row, gl, po, mo, vo, false);
+    store_row<LPR, 1, true, COHERENT>(a, a.P_out, row, gl, po, mo, vo, false);
     p[r][0] = po[0];
     mm[r][0] = mo[0];
     vv[r][0] = vo[0];
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistParams pp) {
     a.P_in = pp.P[t & 1];
     a.P_out = pp.P[(t + 1) & 1];
     per_update(pp, t, &a);
-    run_rows<LPR, RPG>(a, row0, gl, p, mm, vv);
+    run_rows<LPR, RPG, true>(a, row0, gl, p, mm, vv);
     if (!grid_sync(pp.bar, (unsigned)(t - pp.t0 + 1) * gridDim.x)) return;
   }
   store_moments<LPR, RPG>(a, row0, gl, mm, vv);
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kLdsBlock) void lds_block_kernel(PersistParams pp) 
     a.P_in = sP[t & 1];
     a.P_out = sP[(t + 1) & 1];
     per_update(pp, t, &a);
-    run_rows<LPR, RPG>(a, row0, gl, p, mm, vv);
+    run_rows<LPR, RPG, false>(a, row0, gl, p, mm, vv);
     __syncthreads();
   }
   const float4* fin = reinterpret_cast<const float4*>(sP[pp.t1 & 1]);
