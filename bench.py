@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--lanes", type=int, default=-1,
                     help="replica layout (lanes per row); -1 = autotune before timing, 0 = default")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB elementwise copy three times (reference for HBM byte counters)")
     ap.add_argument("--updates", type=int, default=0,
                     help="override the updates per solve (short runs under hardware counters)")
     args = ap.parse_args()
@@ -155,6 +157,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        src = torch.rand(512 * 1024 * 1024 // 4, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+        print("copy calibration: 3 x (read 512 MiB, write 512 MiB)", flush=True)
+        return
     import paper_2409_02135_amd as q
 
     family, n, d, problem, S, K = WORKLOADS[args.workload]
