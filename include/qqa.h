@@ -196,18 +196,27 @@ int qqa_poll(qqa_ctx *c, qqa_req id, qqa_result *out, int32_t timeout_us);
 int qqa_cancel(qqa_ctx *c, qqa_req id);
 
 /* ---------------------------------------------------------------------------------
- * Continuous-batching server.  Requests submitted with qqa_serve_submit are admitted
- * into device-resident slots while their HBM footprint fits the budget and a slot is
- * free; every device iteration advances all admitted slots by one update (each at its
- * own update index) in one launch per replica-width class, so requests that arrive
- * while others run overlap on the device.  Finished slots are rounded, evaluated and
- * released, and waiting requests are admitted, between iterations.  Results are
- * identical to the same solve run alone.  Collect with qqa_poll.
+ * Continuous-batching server.  A server thread advances all admitted requests together:
+ * every update is one launch per replica-layout class covering every admitted request,
+ * each at its own update index, so requests that arrive while others run overlap on
+ * the device.  It works in rounds of 16 updates; at each round boundary it retires
+ * finished requests (rounded, evaluated and copied back during the previous round) and
+ * admits queued requests first-come-first-served while a slot is free and the request's
+ * HBM footprint (state, graph, schedule table, result) fits the server budget (the
+ * context budget not in use when the server started).  A served result is identical to
+ * the same solve run alone.  Replica layouts set on the context before qqa_serve_start
+ * apply.  Collect results with qqa_poll (queue_ms = submit -> admission, latency_ms =
+ * submit -> result).  Dense graphs are not served.
+ *   qqa_serve_start: max_slots concurrent requests on the device.
+ *   qqa_serve_submit: validates and copies the host graph (the caller may free it on
+ *     return) and queues the request; QQA_E_ADMISSION if it can never fit.
+ *   qqa_serve_stop: returns after every queued and admitted request has finished;
+ *     results stay available to qqa_poll.  A context runs at most one server at a time.
  * --------------------------------------------------------------------------------- */
 int qqa_serve_start(qqa_ctx *c, int32_t max_slots);
 int qqa_serve_submit(qqa_ctx *c, const qqa_graph *g, qqa_problem problem, const qqa_schedule *sched,
                      int32_t S, int32_t steps, uint64_t seed, qqa_req *out_id);
-int qqa_serve_stop(qqa_ctx *c);  /* drains admitted and queued requests, then stops */
+int qqa_serve_stop(qqa_ctx *c);
 
 /* ---------------------------------------------------------------------------------
  * Device-level entry points: one stage of the path on caller-owned device buffers,

@@ -41,8 +41,15 @@ void out_views(char* base, int n, int S, int64_t** a, int64_t** b, int64_t** o, 
 }
 
 int upload_graph(qqa_ctx* c, const qqa_graph& g, int problem, DevGraph* out, std::string* why) {
-  int rc = validate_graph(g, problem, why);
-  if (rc) return rc;
+  return upload_graph_on(c->stream, g, problem, out, why, true);
+}
+
+int upload_graph_on(hipStream_t stream, const qqa_graph& g, int problem, DevGraph* out, std::string* why,
+                    bool validate) {
+  if (validate) {
+    int rc = validate_graph(g, problem, why);
+    if (rc) return rc;
+  }
   DevGraph d;
   d.n = g.n;
   d.problem = problem;
@@ -50,7 +57,7 @@ int upload_graph(qqa_ctx* c, const qqa_graph& g, int problem, DevGraph* out, std
     hipError_t e = hipMalloc(dst, bytes ? bytes : 4);
     if (e != hipSuccess) return e;
     d.bytes += bytes;
-    return bytes ? hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, c->stream) : hipSuccess;
+    return bytes ? hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, stream) : hipSuccess;
   };
   hipError_t e = hipSuccess;
   if (g.dense) {
@@ -72,9 +79,9 @@ int upload_graph(qqa_ctx* c, const qqa_graph& g, int problem, DevGraph* out, std
       e = dev_copy((void**)&d.chunks, chunks.data(), chunks.size() * sizeof(HubChunk));
       if (e == hipSuccess) e = dev_copy((void**)&d.hub_first, hub_first.data(), hub_first.size() * sizeof(int32_t));
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host arrays may go away on return
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host arrays may go away on return
   }
-  if (e == hipSuccess && g.dense) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && g.dense) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     free_graph(d);
     return fail(why, e == hipErrorOutOfMemory ? QQA_E_NOMEM : QQA_E_DEVICE,
@@ -343,7 +350,7 @@ int qqa_create(qqa_ctx** out, int device, size_t hbm_budget_bytes, void* hip_str
 void qqa_destroy(qqa_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
-  qqa_serve_stop(c);
+  server_shutdown(c);
   (void)hipStreamSynchronize(c->stream);
   for (auto& kv : c->reqs) release_request_buffers(c, kv.second.get());
   c->reqs.clear();

@@ -103,6 +103,8 @@ void out_views(char* base, int n, int S, int64_t** a, int64_t** b, int64_t** o, 
 // barrier words of a persistent launch inside a result record: [0] arrivals, [1] abort
 unsigned* out_bar(char* base, int S);
 int upload_graph(qqa_ctx* c, const qqa_graph& g, int problem, DevGraph* out, std::string* why);
+int upload_graph_on(hipStream_t stream, const qqa_graph& g, int problem, DevGraph* out, std::string* why,
+                    bool validate);
 void free_graph(DevGraph& d);
 void graph_unref(qqa_ctx* c, int64_t gid);
 int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks);
@@ -115,5 +117,6 @@ int set_err(qqa_ctx* c, int code, const std::string& msg);
 // continuous-batching server hooks (qqa_serve.cpp)
 int serve_poll(qqa_ctx* c, int64_t id, qqa_result* out, int32_t timeout_us);
 int serve_cancel(qqa_ctx* c, int64_t id);
+void server_shutdown(qqa_ctx* c);  // drain, then free everything the server holds
 
 }  // namespace qqa

@@ -1,0 +1,92 @@
+"""The continuous-batching server: requests submitted while others run are admitted as
+slots and memory free up, every result equals the same solve run alone (bit for bit), a
+tight HBM budget makes requests queue rather than fail, and oversize requests, cancellation
+and draining behave as documented."""
+
+import time
+
+import numpy as np
+import pytest
+
+import qqa_inputs as qi
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def qqa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_02135_amd as q
+    q.lib()
+    return q
+
+
+def mixed_requests(count, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n = int(rng.integers(100, 4000))
+        if k % 2:
+            g, p = qi.pm1_weights(qi.barabasi_albert(n, 4, k), k), "maxcut"
+        else:
+            g, p = qi.erdos_renyi(n, float(rng.uniform(3, 20)), k), "mis"
+        out.append((g, p, [16, 32, 128, 7][k % 4], int(rng.integers(20, 90)), 500 + k))
+    return out
+
+
+def test_served_results_equal_alone_and_overlap():
+    q = qqa()
+    reqs = mixed_requests(18)
+    ctx = q.Context(0)
+    ctx.serve_start(6)
+    ids = []
+    for i, (g, p, S, K, seed) in enumerate(reqs):
+        ids.append(ctx.serve_submit(g, p, S, K, seed))
+        if i % 5 == 4:
+            time.sleep(0.01)  # later requests arrive while earlier ones run
+    served = [ctx.poll(i) for i in ids]
+    ctx.serve_stop()
+    for (g, p, S, K, seed), r in zip(reqs, served):
+        alone = ctx.poll(ctx.solve(g, p, S, K, seed))
+        assert np.array_equal(r["obj"], alone["obj"]), (g["n"], p, S, K)
+        assert np.array_equal(r["best_x"], alone["best_x"])
+        assert r["engine"] == "batch" and r["latency_ms"] >= r["queue_ms"] >= 0
+    # with 6 slots for 18 requests some had to wait for a slot
+    assert max(r["queue_ms"] for r in served) > 0
+    ctx.close()
+
+
+def test_tight_budget_queues_and_oversize_is_rejected():
+    q = qqa()
+    small = mixed_requests(6, seed=1)
+    ctx = q.Context(0, hbm_budget=24 << 20)
+    ctx.serve_start(64)
+    ids = [ctx.serve_submit(g, p, S, K, seed) for g, p, S, K, seed in small]
+    res = [ctx.poll(i) for i in ids]
+    for (g, p, S, K, seed), r in zip(small, res):
+        assert r["best_objective"] == r["obj"][r["best_replica"]]
+    big = qi.erdos_renyi(60000, 5.0, 0)
+    with pytest.raises(q.QQAError) as e:
+        ctx.serve_submit(big, "mis", 256, 10, 0)
+    assert e.value.code == q.QQA_E_ADMISSION
+    ctx.serve_stop()
+    ctx.close()
+
+
+def test_cancel_and_drain():
+    q = qqa()
+    ctx = q.Context(0)
+    ctx.serve_start(1)
+    g = qi.erdos_renyi(3000, 5.0, 2)
+    first = ctx.serve_submit(g, "mis", 64, 400, 1)
+    queued = ctx.serve_submit(g, "mis", 64, 400, 2)  # waits for the single slot
+    ctx.cancel(queued)
+    with pytest.raises(q.QQAError) as e:
+        ctx.poll(queued)
+    assert e.value.code == q.QQA_E_CANCELLED
+    later = ctx.serve_submit(g, "mis", 64, 50, 3)
+    ctx.serve_stop()  # returns once everything submitted has finished
+    assert ctx.poll(first, timeout_us=0) is not None
+    assert ctx.poll(later, timeout_us=0) is not None
+    ctx.close()
