@@ -120,6 +120,62 @@ def batched_vs_plain(q, count=512, S=32, K=2000, seed=0):
             "plain_latency_ms": {"p50": float(np.percentile(lat_p, 50)), "p99": float(np.percentile(lat_p, 99))}}
 
 
+def graph_pool(count, seed=0, n_range=(1e3, 1e5)):
+    """A pool of request graphs shaped like the served mix: ER (mean degree ~ U[3,20]) or BA
+    (m = 4), n log-uniform in n_range, each with +-1 weights for max-cut use."""
+    import qqa_inputs as qi
+    rng = np.random.default_rng(seed)
+    pool = []
+    for k in range(count):
+        n = int(round(10 ** rng.uniform(np.log10(n_range[0]), np.log10(n_range[1]))))
+        fam = "er" if k % 2 == 0 else "ba"
+        g = qi.erdos_renyi(n, float(rng.uniform(3.0, 20.0)), 1000 + k) if fam == "er" else \
+            qi.barabasi_albert(n, 4, 1000 + k)
+        pool.append({"family": fam, "mis": g, "maxcut": qi.pm1_weights(g, 2000 + k)})
+    return pool
+
+
+def served(q, rate, arrival_window, pool, seed=0, max_slots=256):
+    """Requests arrive as a Poisson stream at `rate`/s during `arrival_window` s: MIS or +-1
+    max-cut (1/2 each) on a graph from the pool, S in {32, 128}, 1000..3000 updates.  The
+    server admits them as slots and memory free up; all are run to completion."""
+    import torch
+    rng = np.random.default_rng(seed)
+    t, arrivals = 0.0, []
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= arrival_window:
+            break
+        gi = int(rng.integers(len(pool)))
+        prob = "mis" if rng.random() < 0.5 else "maxcut"
+        arrivals.append((t, gi, prob, int(rng.choice([32, 128])), int(rng.integers(1000, 3001)),
+                         int(rng.integers(2 ** 31))))
+    ctx = q.Context(0)
+    ctx.serve_start(max_slots)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ids, work = [], []
+    for (ta, gi, prob, S, K, sd) in arrivals:
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        g = pool[gi][prob]
+        ids.append(ctx.serve_submit(g, prob, S, K, sd))
+        work.append(float(g["n"]) * S * K)
+    res = [ctx.poll(i, want_x=False) for i in ids]
+    makespan = time.perf_counter() - t0
+    ctx.serve_stop()
+    ctx.close()
+    lat = np.array([r["latency_ms"] for r in res])
+    qms = np.array([r["queue_ms"] for r in res])
+    return {"rate_per_s": rate, "arrival_window_s": arrival_window, "requests": len(res),
+            "offered_updates_per_s": sum(work) / arrival_window,
+            "sustained_updates_per_s": sum(work) / makespan, "makespan_s": makespan,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "queue_ms": {"p50": float(np.percentile(qms, 50)), "p99": float(np.percentile(qms, 99))},
+            "feasible_fraction": float(np.mean([r["feasible"] for r in res]))}
+
+
 def cpu_baseline(g, problem, S, K, updates=20):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload: the first
     `updates` updates of the schedule from the same start, one thread."""
@@ -144,6 +200,9 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served request-stream measurement")
+    ap.add_argument("--serve-window", type=float, default=2.0,
+                    help="arrival window (s) of the served stream at the specified rate of 200 requests/s")
     ap.add_argument("--lanes", type=int, default=-1,
                     help="replica layout (lanes per row); -1 = autotune before timing, 0 = default")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -227,6 +286,16 @@ def main():
     ctx.close()
     if not args.no_batch:
         out["batched_vs_plain"] = batched_vs_plain(q)
+    if not args.no_serve:
+        pool = graph_pool(24)
+        spec = served(q, 200.0, args.serve_window, pool, seed=1)
+        # a second stream at about 70 % of the capacity the first one sustained
+        mean_work = spec["offered_updates_per_s"] / 200.0
+        rate70 = max(1.0, 0.7 * spec["sustained_updates_per_s"] / mean_work)
+        low = served(q, rate70, 8.0, pool, seed=2)
+        out["served"] = {"workload": "Poisson stream of MIS / +-1 max-cut requests on ER (mean degree U[3,20]) "
+                                     "and BA (m=4) graphs, n log-uniform in [1e3,1e5], S in {32,128}, "
+                                     "1000-3000 updates", "at_200_per_s": spec, "at_70pct_capacity": low}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, problem, S, K)
     print(json.dumps(out), flush=True)
