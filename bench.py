@@ -25,18 +25,23 @@ import numpy as np  # noqa: E402
 
 METRIC = "replica-var updates/s (N·S·steps/s); p50/p99 solve latency, batched vs plain"
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 
 WORKLOADS = {
     # name: (family, n, degree parameter, problem, S, updates)
     "mis_er_n20000_d5_S256_K3000": ("er", 20000, 5.0, "mis", 256, 3000),
     "maxcut_ba_n100000_m4_pm1_S128_K3000": ("ba", 100000, 4, "maxcut", 128, 3000),
     "mis_rrg_n256_d3_S16_K2000": ("rrg", 256, 3, "mis", 16, 2000),
+    # dense symmetric Gaussian couplings (Sherrington-Kirkpatrick-like max-cut)
+    "maxcut_dense_n4096_gauss_S256_K3000": ("dense", 4096, 0, "maxcut", 256, 3000),
 }
 DEFAULT = "mis_er_n20000_d5_S256_K3000"
 
 
 def make_graph(family, n, d, problem, seed=0):
     import qqa_inputs as qi
+    if family == "dense":
+        return {"n": n, "dense": qi.dense_gaussian(n, seed)}
     if family == "er":
         g = qi.erdos_renyi(n, d, seed)
     elif family == "ba":
@@ -55,6 +60,26 @@ def algorithmic_bytes_per_update_launch(n, nnz, S, stride, weighted):
     state = 24 * n * S
     csr = 4 * (n + 1) + 4 * nnz + (4 * nnz if weighted else 0)
     return state + csr
+
+
+def dense_coupling_us(q, W, n, S, problem, launches=20):
+    """Average duration of one launch of the matrix-core coupling product at the solve's
+    shape, from HIP events on the stream the kernels are launched on."""
+    import torch
+    stride = q.qqa_replica_stride(S)
+    Wd = torch.as_tensor(W, device="cuda")
+    P = torch.rand(n, stride, device="cuda")
+    C = torch.empty_like(P)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        q.qqa_dev_dense_coupling(Wd, P, C, n, S, problem, st)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(launches):
+        q.qqa_dev_dense_coupling(Wd, P, C, n, S, problem, st)
+    b.record(st)
+    b.synchronize()
+    return a.elapsed_time(b) * 1e3 / launches
 
 
 def traffic_from_profiles(kernel_src_hash):
@@ -184,8 +209,9 @@ def cpu_baseline(g, problem, S, K, updates=20):
                        gamma_min=-2.0 if problem == "mis" else (-20.0 if g["n"] >= 1000 else -5.0)).as_float32()
     P = oracle.init(0, g["n"], S)
     z = np.zeros_like(P)
+    og = oracle.graph(W=g["dense"]) if "dense" in g else g
     t0 = time.perf_counter()
-    oracle.run(pr, g, 0, updates, K, 0, P, z, z)
+    oracle.run(pr, og, 0, updates, K, 0, P, z, z)
     dt = time.perf_counter() - t0
     return {"value": g["n"] * S * updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{updates} of {K} updates of the same instance from the same start, single-threaded FP64 C",
@@ -230,10 +256,15 @@ def main():
     if args.updates > 0:
         K = args.updates
     g = make_graph(family, n, d, problem)
-    nnz = int(g["col"].size)
+    dense = family == "dense"
+    nnz = n * (n - 1) if dense else int(g["col"].size)
     ctx = q.Context(0)
-    gid = ctx.upload(g, problem)
-    lanes = ctx.autotune(gid, problem, S) if args.lanes < 0 else args.lanes
+    if dense:
+        gid = ctx.upload(None, problem, dense=g["dense"])
+        lanes = max(args.lanes, 0)  # the layout only concerns the fused update here
+    else:
+        gid = ctx.upload(g, problem)
+        lanes = ctx.autotune(gid, problem, S) if args.lanes < 0 else args.lanes
     ctx.set_replica_layout(S, lanes)
     print(f"# workload {args.workload}: n={n} nnz={nnz} S={S} updates={K} lanes_per_row={lanes}",
           file=sys.stderr, flush=True)
@@ -254,9 +285,22 @@ def main():
     loop_ms = np.array([r["step_loop_ms"] for r in results])
     step_us = float(np.mean(loop_ms)) * 1e3 / K  # average duration of one update launch
     stride = q.qqa_replica_stride(S)
-    abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
-    achieved = abytes / (step_us * 1e-6) / 1e9
-    traffic = traffic_from_profiles(device_source_hash())
+    if dense:
+        # dominant kernel: the FP32 matrix-core product, 2 n^2 S flops per launch
+        mm_us = dense_coupling_us(q, g["dense"], n, S, problem)
+        flops = 2.0 * n * n * S
+        achieved = flops / (mm_us * 1e-6) / 1e12
+        roofline = {"bound": "mfma", "kernel": "dense_coupling_kernel", "achieved": achieved,
+                    "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                    "traffic": None, "avg_launch_us": mm_us, "algorithmic_flops_per_launch": flops,
+                    "update_loop_us_per_update": step_us}
+    else:
+        abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
+        achieved = abytes / (step_us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "kernel": "step_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": traffic_from_profiles(device_source_hash()),
+                    "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes}
 
     out = {
         "metric": METRIC,
@@ -276,9 +320,7 @@ def main():
                    "lanes_per_row": lanes, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(dev_ms, 50)), "p99": float(np.percentile(dev_ms, 99)),
                        "basis": "device time per solve (events on the solver stream)"},
-        "roofline": {"bound": "hbm", "kernel": "step_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes},
+        "roofline": roofline,
         "quality": {"best_objective_mean": float(np.mean([r["best_objective"] for r in results])),
                     "feasible_all": bool(all(r["feasible"] for r in results))},
     }
@@ -297,7 +339,7 @@ def main():
                                      "and BA (m=4) graphs, n log-uniform in [1e3,1e5], S in {32,128}, "
                                      "1000-3000 updates", "at_200_per_s": spec, "at_70pct_capacity": low}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, problem, S, K)
+        out["cpu_baseline"] = cpu_baseline(g, problem, S, K, updates=2 if dense else 20)
     print(json.dumps(out), flush=True)
 
 

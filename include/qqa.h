@@ -244,11 +244,18 @@ int qqa_dev_noise(uint64_t seed, int32_t n, int32_t S, uint32_t k, float *xi, vo
 /* Initial state: P[i*stride + s] ~ U(0,1) from `seed`; m = v = 0 (m, v may be NULL). */
 int qqa_dev_init(uint64_t seed, int32_t n, int32_t S, float *P, float *m, float *v, void *stream);
 
+/* Dense coupling product on the matrix cores (FP32 MFMA, FP32 accumulation):
+ * C[i*stride + s] = sum_k W[i*n + k] f(P[k*stride + s]), f(p) = 2p - 1 (QQA_MAXCUT) or p
+ * (QQA_MIS), for a symmetric n x n W (device).  P, C: device n x stride. */
+int qqa_dev_dense_coupling(const float *W, const float *P, float *C, int32_t n, int32_t S, qqa_problem problem,
+                           void *stream);
+
 /* One update t (0-based, AdamW step count t+1) of a K-update schedule:
  * reads P_in, writes P_out (must not alias P_in: neighbours read P_in), updates m, v in
  * place.  lanes_per_row selects the replica layout (0 = default; see
- * qqa_set_replica_layout).  Rows of more than 64 neighbours are split into 32-edge chunks
- * whose partial sums are added in chunk order, as in every solve. */
+ * qqa_set_replica_layout).  Rows of more than 64 neighbours are split into 16-edge chunks
+ * whose partial sums are added in chunk order, as in every solve.  A dense graph takes the
+ * coupling product from qqa_dev_dense_coupling's kernel. */
 int qqa_dev_step(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule *sched, int32_t S,
                  int32_t t, int32_t K, uint64_t seed, const float *P_in, float *P_out, float *m,
                  float *v, int32_t lanes_per_row, void *stream);

@@ -98,6 +98,7 @@ def lib():
             "qqa_dev_run": (C.c_int, [vp, i32, vp, i32, i32, i32, i32, u64, vp, vp, vp, vp, i32, i32, vp]),
             "qqa_autotune": (C.c_int, [vp, i64, i32, i32, vp]),
             "qqa_dev_eval": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
+            "qqa_dev_dense_coupling": (C.c_int, [vp, vp, vp, i32, i32, i32, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -201,6 +202,10 @@ def qqa_dev_run(g: DevGraph, problem, sched: qqa_schedule | None, S, t0, t1, K, 
     return _dev_check(lib().qqa_dev_run(C.byref(g.struct), PROBLEMS[problem], None if sched is None else C.byref(sched),
                                         S, t0, t1, K, seed, _ptr(P0), _ptr(P1), _ptr(m), _ptr(v), e, lanes_per_row,
                                         _stream(stream)))
+
+
+def qqa_dev_dense_coupling(W, P, C, n, S, problem, stream=None):
+    return _dev_check(lib().qqa_dev_dense_coupling(_ptr(W), _ptr(P), _ptr(C), n, S, PROBLEMS[problem], _stream(stream)))
 
 
 def qqa_dev_eval(g: DevGraph, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best, stream=None):

@@ -127,6 +127,12 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
   get((void**)&r->acc, 2 * (size_t)r->shape.stride * sizeof(unsigned long long));
   r->hub_bytes = (size_t)nchunks * r->shape.stride * sizeof(float);
   if (nchunks) get((void**)&r->hub_partial, r->hub_bytes);
+  r->coupling_bytes = 0;
+  auto git = c->graphs.find(r->graph);
+  if (git != c->graphs.end() && git->second.dense) {
+    r->coupling_bytes = state;
+    get((void**)&r->coupling, r->coupling_bytes);
+  }
   r->out_size = out_bytes(r->n, r->S);
   get((void**)&r->out_dev, r->out_size);
   if (e == hipSuccess) e = c->hpool.get(r->out_size, (void**)&r->out_host);
@@ -154,6 +160,8 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
   c->dpool.put(r->acc, 2 * (size_t)r->shape.stride * sizeof(unsigned long long));
   c->dpool.put(r->hub_partial, r->hub_bytes);
   r->hub_partial = nullptr;
+  c->dpool.put(r->coupling, r->coupling_bytes);
+  r->coupling = nullptr;
   c->dpool.put(r->out_dev, r->out_size);
   c->hpool.put(r->out_host, r->out_size);
   c->dpool.put(r->table_dev, r->table_bytes);
@@ -175,9 +183,9 @@ StepParams request_step_params(const Request* r, const DevGraph& g) {
   p.row_ptr = g.row_ptr;
   p.col = g.col;
   p.w = r->problem == QQA_MAXCUT ? g.w : nullptr;
-  p.coupling = nullptr;
   p.hub_first = g.hub_first;
   p.hub_partial = r->hub_partial;
+  p.coupling = g.dense ? r->coupling : nullptr;
   p.m = r->m;
   p.v = r->v;
   p.n = r->n;
@@ -231,7 +239,6 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   if (git == c->graphs.end()) return set_err(c, QQA_E_ARG, "unknown graph id");
   DevGraph& g = git->second;
   if (g.problem != problem) return set_err(c, QQA_E_ARG, "graph was uploaded for another problem type");
-  if (g.dense) return set_err(c, QQA_E_ARG, "dense coupling graphs are not supported by this solve path");
   auto r = std::make_unique<Request>();
   r->id = c->next_req++;
   r->graph = gid;
@@ -246,13 +253,16 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   r->n = g.n;
   r->shape = replica_shape(S);
   r->lanes_per_row = c->layout_for(S);
-  r->footprint = request_footprint(g.n, S, r->sched.rule) + (size_t)g.nchunks * r->shape.stride * sizeof(float);
+  r->footprint = request_footprint(g.n, S, r->sched.rule) + (size_t)g.nchunks * r->shape.stride * sizeof(float) +
+                 (g.dense ? (size_t)g.n * r->shape.stride * sizeof(float) : 0);
   if (r->footprint + g.bytes > c->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the HBM budget");
   {
     StepParams probe = request_step_params(r.get(), g);
     // auto: one workgroup with P in LDS when the instance fits, else one launch per update
-    // (measured faster on this GPU than the register-resident engine for larger instances)
-    const int allow = c->engine_policy < 0 ? 1 : (c->engine_policy == QQA_ENGINE_LDS_BLOCK ? 1 :
+    // (measured faster on this GPU than the register-resident engine for larger instances).
+    // Dense graphs always stream: their coupling product is a separate matrix-core launch
+    // before every update, which no persistent engine performs.
+    const int allow = g.dense ? 0 : c->engine_policy < 0 ? 1 : (c->engine_policy == QQA_ENGINE_LDS_BLOCK ? 1 :
                                                  (c->engine_policy == QQA_ENGINE_PERSISTENT ? 2 : 0));
     r->engine = allow ? persistent_plan(probe, g.nchunks > 0, allow, &r->rows_per_group, &r->grid) : kEngineStream;
     if (r->engine != kEngineStream) {
@@ -291,6 +301,7 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
       p.P_in = r->P[t & 1];
       p.P_out = r->P[(t + 1) & 1];
       fill_step_scalars(p, r->sched, t, steps);
+      if (g.dense) e = launch_dense_coupling(g.dense, p.P_in, r->coupling, g.n, p.stride, problem, c->stream);
       if (g.nchunks) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
       if (e == hipSuccess) e = launch_step(p, c->stream);
     }

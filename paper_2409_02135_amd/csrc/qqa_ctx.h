@@ -56,6 +56,8 @@ struct Request {
   unsigned long long* acc = nullptr;
   float* hub_partial = nullptr;  // nchunks x stride
   size_t hub_bytes = 0;
+  float* coupling = nullptr;     // dense graphs: n x stride coupling product
+  size_t coupling_bytes = 0;
   char* out_dev = nullptr;
   char* out_host = nullptr;
   size_t out_size = 0;

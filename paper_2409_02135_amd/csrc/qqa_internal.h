@@ -147,6 +147,11 @@ enum PersistEngine { kEngineStream = 0, kEnginePersistent = 1, kEngineLdsBlock =
 int persistent_plan(const StepParams& a, bool has_hubs, int allow, int* rows_per_group, int* grid);
 hipError_t launch_persistent(const PersistParams& pp, int engine, int rows_per_group, int grid, hipStream_t st);
 
+// Dense coupling product C = W f(P) on the matrix cores (W symmetric n x n, P and C
+// n x stride; f(p) = 2p - 1 for max-cut, p for MIS).
+hipError_t launch_dense_coupling(const float* W, const float* P, float* C, int n, int stride, int problem,
+                                 hipStream_t st);
+
 hipError_t launch_philox(uint64_t seed, int n, int nquads, uint32_t k, uint32_t stream_id, uint32_t* out,
                          hipStream_t st);
 hipError_t launch_noise(uint64_t seed, int n, int S, uint32_t k, float* xi, hipStream_t st);

@@ -274,7 +274,7 @@ int qqa_dev_init(uint64_t seed, int32_t n, int32_t S, float* P, float* m, float*
 
 static int dev_graph_check(const qqa_dev_graph* g) {
   if (!g || g->n < 0) return fail(&g_dev_error, QQA_E_ARG, "graph is NULL or n < 0");
-  if (g->dense) return fail(&g_dev_error, QQA_E_ARG, "dense coupling is handled by the dense path");
+  if (g->dense) return QQA_OK;
   if (g->n > 0 && !g->row_ptr) return fail(&g_dev_error, QQA_E_ARG, "row_ptr missing");
   if (g->nnz > 0 && !g->col_idx) return fail(&g_dev_error, QQA_E_ARG, "col_idx missing");
   return QQA_OK;
@@ -312,6 +312,19 @@ int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule
   fill_step_scalars(p, s, t, K);
   p.lanes_per_row = lanes_per_row;
   if (g->n == 0) return QQA_OK;
+  if (g->dense) {
+    float* C = nullptr;
+    DEV_CHECK(hipMallocAsync((void**)&C, (size_t)g->n * p.stride * sizeof(float), st));
+    p.row_ptr = nullptr;
+    p.col = nullptr;
+    p.w = nullptr;
+    p.coupling = C;
+    hipError_t e = launch_dense_coupling(g->dense, P_in, C, g->n, p.stride, problem, st);
+    if (e == hipSuccess) e = launch_step(p, st);
+    (void)hipFreeAsync(C, st);
+    DEV_CHECK(e);
+    return QQA_OK;
+  }
   // the same row split the solver uses: read the row pointers back to plan it
   std::vector<int32_t> rp(g->n + 1);
   DEV_CHECK(hipMemcpyAsync(rp.data(), g->row_ptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -362,6 +375,30 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
     return fail(&g_dev_error, QQA_E_ARG, "unsupported replica layout");
   if (g->n == 0 || t0 == t1) return QQA_OK;
   hipStream_t st = (hipStream_t)stream;
+  if (g->dense) {
+    if (engine > 0) return fail(&g_dev_error, QQA_E_ARG, "dense coupling runs on the streaming engine");
+    StepParams p{};
+    p.m = m;
+    p.v = v;
+    p.n = g->n;
+    fill_static_scalars(p, s, problem, S, seed);
+    p.lanes_per_row = lanes_per_row;
+    float* C = nullptr;
+    DEV_CHECK(hipMallocAsync((void**)&C, (size_t)g->n * p.stride * sizeof(float), st));
+    p.coupling = C;
+    float* P[2] = {P0, P1};
+    hipError_t e = hipSuccess;
+    for (int t = t0; t < t1 && e == hipSuccess; ++t) {
+      p.P_in = P[t & 1];
+      p.P_out = P[(t + 1) & 1];
+      fill_step_scalars(p, s, t, K);
+      e = launch_dense_coupling(g->dense, p.P_in, C, g->n, p.stride, problem, st);
+      if (e == hipSuccess) e = launch_step(p, st);
+    }
+    (void)hipFreeAsync(C, st);
+    DEV_CHECK(e);
+    return QQA_OK;
+  }
   StepParams p{};
   p.row_ptr = g->row_ptr;
   p.col = g->col_idx;
@@ -448,6 +485,15 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
   DEV_CHECK(e2);
   DEV_CHECK(e3);
   if (bar[1] != 0u) return fail(&g_dev_error, QQA_E_DEVICE, "persistent engine: grid barrier timed out");
+  return QQA_OK;
+}
+
+int qqa_dev_dense_coupling(const float* W, const float* P, float* C, int32_t n, int32_t S, qqa_problem problem,
+                           void* stream) {
+  if (n < 0 || S <= 0 || S > kMaxReplicas || (n > 0 && (!W || !P || !C)))
+    return fail(&g_dev_error, QQA_E_ARG, "bad dense coupling arguments");
+  if (problem != QQA_MIS && problem != QQA_MAXCUT) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
+  DEV_CHECK(launch_dense_coupling(W, P, C, n, replica_shape(S).stride, problem, (hipStream_t)stream));
   return QQA_OK;
 }
 

@@ -18,12 +18,15 @@ WORKLOADS = {
     "rrg256_d3_mis_S16_K2000": ("rrg", 256, 3, 0, "mis", 16, 2000),
     "er2000_d5_mis_S256_K1000": ("er", 2000, 5.0, 0, "mis", 256, 1000),
     "ba2000_m4_pm1_maxcut_S128_K1000": ("ba", 2000, 4, 0, "maxcut", 128, 1000),
+    "dense256_gauss_maxcut_S32_K500": ("dense", 256, 0, 0, "maxcut", 32, 500),
 }
 SEEDS = list(range(10))
 
 
 def make_graph(kind, n, d, gseed, problem):
     import qqa_inputs as qi
+    if kind == "dense":
+        return qi.dense_gaussian(n, gseed)
     if kind == "rrg":
         g = qi.random_regular(n, d, gseed)
     elif kind == "er":
@@ -41,6 +44,8 @@ def one(args):
     import oracle
     kind, n, d, gseed, problem, S, K = WORKLOADS[name]
     g = make_graph(kind, n, d, gseed, problem)
+    if kind == "dense":
+        g = oracle.graph(W=g)
     pr = oracle.Params(problem=0 if problem == "mis" else 1,
                        gamma_min=-2.0 if problem == "mis" else (-20.0 if n >= 1000 else -5.0)).as_float32()
     r = oracle.solve(pr, g, S, K, seed)

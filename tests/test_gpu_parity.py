@@ -69,7 +69,7 @@ def padded(a: np.ndarray, stride: int) -> np.ndarray:
 def run_gpu_step(q, g, problem, sched, S, t, K, seed, P, m, v, lanes_per_row=0):
     stride = q.qqa_replica_stride(S)
     d = dev()
-    G = q.DevGraph(g)
+    G = q.DevGraph(dense=g["dense"]) if "dense" in g else q.DevGraph(g)
     Pi = torch.as_tensor(padded(P, stride), device=d)
     Po = torch.full_like(Pi, -7.0)
     mt = torch.as_tensor(padded(m, stride), device=d)
@@ -126,7 +126,8 @@ def check_step(label, gpu, ref, S, adam, beta1, beta2, sens=None, comm_alpha=0.1
 def compare_step(label, q, orc, g, problem, sched, S, t, K, seed, P, m, v, lanes_per_row=0):
     """Run one update on the GPU and in the oracle from the same float32 state; check it."""
     gpu = run_gpu_step(q, g, problem, sched, S, t, K, seed, P, m, v, lanes_per_row)
-    ref = orc.step(oracle_params(orc, q, sched, problem), g, t, K, seed, P, m, v)
+    og = orc.graph(W=g["dense"]) if "dense" in g else g
+    ref = orc.step(oracle_params(orc, q, sched, problem), og, t, K, seed, P, m, v)
     adam = sched.rule == 0
     sens = step_sensitivity(ref, m.astype(np.float64), v.astype(np.float64), t, sched, adam)
     return check_step(label, gpu, ref, S, adam, sched.beta1, sched.beta2, sens, float(np.float32(sched.comm_alpha)))
