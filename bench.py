@@ -74,6 +74,9 @@ def dense_coupling_us(q, W, n, S, problem, launches=20):
     for _ in range(3):
         q.qqa_dev_dense_coupling(Wd, P, C, n, S, problem, st)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # hold the stream on the device while every launch is enqueued, so that the events
+    # bracket back-to-back kernels and not the host's launch rate
+    torch.cuda._sleep(20_000_000)
     a.record(st)
     for _ in range(launches):
         q.qqa_dev_dense_coupling(Wd, P, C, n, S, problem, st)
@@ -82,27 +85,31 @@ def dense_coupling_us(q, W, n, S, problem, launches=20):
     return a.elapsed_time(b) * 1e3 / launches
 
 
-def traffic_from_profiles(kernel_src_hash):
-    """Measured HBM bytes per launch of the update kernel, from the committed rocprofv3
-    counter summary, if it was taken with the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
-    try:
-        rec = json.load(open(path))
-    except (OSError, ValueError):
-        return None
-    if rec.get("kernel_source_sha256") != kernel_src_hash:
-        return None
-    return rec.get("bytes_per_launch")
-
-
 DEVICE_SOURCES = ["qqa_device.h", "qqa_kernels.hip"]
+DENSE_SOURCES = ["qqa_dense.hip"]
+
+
+def source_hash(sources):
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(ROOT, "paper_2409_02135_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def device_source_hash():
-    h = hashlib.sha256()
-    for f in DEVICE_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2409_02135_amd", "csrc", f), "rb").read())
-    return h.hexdigest()
+    return source_hash(DEVICE_SOURCES)
+
+
+def traffic_from_profiles(record, sources):
+    """Measured HBM bytes per launch of a kernel, from a committed rocprofv3 counter
+    summary, if it was taken with the current kernel source; else None."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", record)))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != source_hash(sources):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def batched_vs_plain(q, count=512, S=32, K=2000, seed=0):
@@ -286,21 +293,25 @@ def main():
     step_us = float(np.mean(loop_ms)) * 1e3 / K  # average duration of one update launch
     stride = q.qqa_replica_stride(S)
     if dense:
-        # dominant kernel: the FP32 matrix-core product, 2 n^2 S flops per launch
-        mm_us = dense_coupling_us(q, g["dense"], n, S, problem)
+        # dominant kernel: the FP32 matrix-core product, 2 n^2 S flops per launch, timed by
+        # the library with events on sampled launches inside the timed solves
+        mm_us = float(np.mean([r["kernel_us"] for r in results]))
         flops = 2.0 * n * n * S
         achieved = flops / (mm_us * 1e-6) / 1e12
         roofline = {"bound": "mfma", "kernel": "dense_coupling_kernel", "achieved": achieved,
                     "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-                    "traffic": None, "avg_launch_us": mm_us, "algorithmic_flops_per_launch": flops,
-                    "update_loop_us_per_update": step_us}
+                    "traffic": traffic_from_profiles("dense_coupling_kernel_traffic.json", DENSE_SOURCES),
+                    "avg_launch_us": mm_us, "algorithmic_flops_per_launch": flops,
+                    "update_loop_us_per_update": step_us,
+                    "uniform_random_state_us": dense_coupling_us(q, g["dense"], n, S, problem)}
     else:
         abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
         achieved = abytes / (step_us * 1e-6) / 1e9
         roofline = {"bound": "hbm", "kernel": "step_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": traffic_from_profiles(device_source_hash()),
-                    "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes}
+                    "traffic": traffic_from_profiles("step_kernel_traffic.json", DEVICE_SOURCES),
+                    "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes,
+                    "sampled_launch_us": float(np.mean([r["kernel_us"] for r in results]))}
 
     out = {
         "metric": METRIC,

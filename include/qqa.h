@@ -123,6 +123,10 @@ typedef struct {
     double step_loop_ms;         /* device time of the K-update loop */
     double latency_ms;           /* submit -> result ready (host clock) */
     int32_t engine;              /* qqa_engine that ran the update loop */
+    double kernel_us;            /* streaming engine: mean device duration of the dominant
+                                  * launch of an update (the coupling product for dense
+                                  * graphs, the update kernel otherwise), timed with events on
+                                  * up to 32 launches spread over the schedule; -1 otherwise */
 } qqa_result;
 
 /* How the update loop runs.  STREAM: one launch per update, state streamed through

@@ -52,7 +52,7 @@ class qqa_result(C.Structure):
                 ("replica_objective", C.c_void_p), ("replica_size_or_cut", C.c_void_p),
                 ("replica_violations", C.c_void_p), ("best_x", C.c_void_p), ("queue_ms", C.c_double),
                 ("device_ms", C.c_double), ("step_loop_ms", C.c_double), ("latency_ms", C.c_double),
-                ("engine", C.c_int32)]
+                ("engine", C.c_int32), ("kernel_us", C.c_double)]
 
 
 class qqa_dev_graph(C.Structure):
@@ -354,5 +354,5 @@ class Context:
         return Result(best_replica=res.best_replica, feasible=bool(res.feasible), best_objective=res.best_objective,
                       best_size_or_cut=res.best_size_or_cut, best_violations=res.best_violations, obj=objs,
                       size_or_cut=size, viol=viol, best_x=x, queue_ms=res.queue_ms, device_ms=res.device_ms,
-                      step_loop_ms=res.step_loop_ms, latency_ms=res.latency_ms,
+                      step_loop_ms=res.step_loop_ms, latency_ms=res.latency_ms, kernel_us=res.kernel_us,
                       engine={v: k for k, v in ENGINES.items()}.get(res.engine, res.engine))

@@ -137,6 +137,13 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
   get((void**)&r->out_dev, r->out_size);
   if (e == hipSuccess) e = c->hpool.get(r->out_size, (void**)&r->out_host);
   for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&r->ev[i]);
+  if (r->engine == kEngineStream && r->K > 0) {
+    // sampled updates t with t % every == every / 2, at most kProbes of them
+    r->probe_every = std::max(1, (r->K + kProbes - 1) / kProbes);
+    const int samples = (r->K - r->probe_every / 2 + r->probe_every - 1) / r->probe_every;
+    r->probe.assign(2 * (size_t)samples, nullptr);
+    for (size_t i = 0; i < r->probe.size() && e == hipSuccess; ++i) e = hipEventCreate(&r->probe[i]);
+  }
   if (e != hipSuccess) {
     release_request_buffers(c, r);
     return fail(why, e == hipErrorOutOfMemory ? QQA_E_NOMEM : QQA_E_DEVICE,
@@ -176,6 +183,9 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
       (void)hipEventDestroy(r->ev[i]);
       r->ev[i] = nullptr;
     }
+  for (hipEvent_t& ev : r->probe)
+    if (ev) (void)hipEventDestroy(ev);
+  r->probe.clear();
 }
 
 StepParams request_step_params(const Request* r, const DevGraph& g) {
@@ -297,13 +307,22 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   if (e == hipSuccess) e = hipEventRecord(r->ev[1], c->stream);
   StepParams p = request_step_params(r.get(), g);
   if (r->engine == kEngineStream) {
+    const int every = r->probe_every;
     for (int t = 0; t < steps && e == hipSuccess; ++t) {
       p.P_in = r->P[t & 1];
       p.P_out = r->P[(t + 1) & 1];
       fill_step_scalars(p, r->sched, t, steps);
-      if (g.dense) e = launch_dense_coupling(g.dense, p.P_in, r->coupling, g.n, p.stride, problem, c->stream);
-      if (g.nchunks) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
+      const size_t pi = 2 * (size_t)(t / every);
+      const bool probe = t % every == every / 2 && pi + 1 < r->probe.size();
+      if (g.dense) {
+        if (probe) e = hipEventRecord(r->probe[pi], c->stream);
+        if (e == hipSuccess) e = launch_dense_coupling(g.dense, p.P_in, r->coupling, g.n, p.stride, problem, c->stream);
+        if (probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
+      }
+      if (g.nchunks && e == hipSuccess) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
+      if (!g.dense && probe && e == hipSuccess) e = hipEventRecord(r->probe[pi], c->stream);
       if (e == hipSuccess) e = launch_step(p, c->stream);
+      if (!g.dense && probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
     }
   } else {
     unsigned* bar = out_bar(r->out_dev, S);
@@ -542,6 +561,14 @@ int qqa_poll(qqa_ctx* c, qqa_req id, qqa_result* out, int32_t timeout_us) {
     out->device_ms = hipEventElapsedTime(&ms, r->ev[0], r->ev[3]) == hipSuccess ? ms : -1.0;
     out->step_loop_ms = hipEventElapsedTime(&ms, r->ev[1], r->ev[2]) == hipSuccess ? ms : -1.0;
     out->latency_ms = std::chrono::duration<double, std::milli>(t_done - r->t_submit).count();
+    out->kernel_us = -1.0;
+    if (!r->probe.empty()) {
+      double sum = 0.0;
+      bool ok = true;
+      for (size_t i = 0; i + 1 < r->probe.size(); i += 2)
+        ok = ok && hipEventElapsedTime(&ms, r->probe[i], r->probe[i + 1]) == hipSuccess && (sum += ms, true);
+      if (ok) out->kernel_us = sum * 1e3 / (double)(r->probe.size() / 2);
+    }
   }
   release_request_buffers(c, r);
   c->in_use -= r->footprint;
@@ -567,6 +594,7 @@ int qqa_cancel(qqa_ctx* c, qqa_req id) {
 namespace qqa {
 
 void fill_result(const Request* r, qqa_result* out) {
+  out->kernel_us = -1.0;
   int64_t *a, *b, *o;
   int32_t* best;
   uint8_t* x;

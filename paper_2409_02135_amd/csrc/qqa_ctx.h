@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cstdint>
 #include <memory>
+#include <vector>
 #include <string>
 #include <unordered_map>
 
@@ -30,6 +31,9 @@ struct DevGraph {
   int refs = 0;
   bool release_pending = false;
 };
+
+// launches of the dominant kernel timed per streaming request
+constexpr int kProbes = 32;
 
 struct Request {
   enum State { kQueued = 0, kRunning = 1, kDone = 2 };
@@ -62,6 +66,9 @@ struct Request {
   char* out_host = nullptr;
   size_t out_size = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // start, loop start, loop end, done
+  // streaming engine: event pairs around the dominant launch of sampled updates
+  std::vector<hipEvent_t> probe;
+  int probe_every = 0;
   std::chrono::steady_clock::time_point t_submit, t_admit;
   // set when the buffers and events belong to a shared owner (a batch or the server);
   // releasing the request then only drops its reference
