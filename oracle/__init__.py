@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qqa_oracle.c")
 _LIB = os.path.join(_HERE, "libqqa_oracle.so")
 
-MIS, MAXCUT = 0, 1
+MIS, MAXCUT, MAXCLIQUE = 0, 1, 2
 ADAMW, LANGEVIN = 0, 1
 STREAM_INIT, STREAM_NOISE = 0, 1
 

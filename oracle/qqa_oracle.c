@@ -24,10 +24,12 @@
  *
  * Parity status (tests/test_oracle_*.py pin each function against something other
  * than itself):
- *   orc_eval        exact: brute force over every x of small graphs, textbook optima
+ *   orc_eval        exact: brute force over every x of small graphs (maximum independent
+ *                   sets, maximum cuts, maximum cliques), textbook optima
  *   orc_energy      exact at binary points (equals the discrete objective), closed
  *                   forms at P = 1/2 and for the STD maximiser (appendix proposition)
- *   orc_grad        central finite differences of orc_energy, row sums of the STD term
+ *   orc_grad        central finite differences of orc_energy, row sums of the STD term;
+ *                   max clique also against the MIS gradient on the complement graph
  *   orc_step        AdamW first-step closed form, projected-gradient fixed point of a
  *                   regular graph (closed-form root), Langevin noise moments
  *   orc_philox*     parity unpinned against the published known-answer vectors (not
@@ -40,7 +42,7 @@
 #include <string.h>
 
 /* ---- problem / step-rule codes ----------------------------------------------------- */
-enum { ORC_MIS = 0, ORC_MAXCUT = 1 };
+enum { ORC_MIS = 0, ORC_MAXCUT = 1, ORC_MAXCLIQUE = 2 };
 enum { ORC_ADAMW = 0, ORC_LANGEVIN = 1 };
 enum { ORC_STREAM_INIT = 0, ORC_STREAM_NOISE = 1 };
 
@@ -53,8 +55,8 @@ typedef struct {
     int32_t entropy_alpha;       /* alpha of the alpha-entropy (Eq. 7), even */
     int32_t rule;                /* ORC_ADAMW or ORC_LANGEVIN */
     double beta1, beta2, adam_eps;
-    double lambda;               /* MIS penalty coefficient */
-    int32_t problem;             /* ORC_MIS or ORC_MAXCUT */
+    double lambda;               /* MIS / max-clique penalty coefficient */
+    int32_t problem;             /* ORC_MIS, ORC_MAXCUT or ORC_MAXCLIQUE */
     int32_t pad_;
 } orc_params;
 
@@ -180,13 +182,41 @@ static double ipow(double x, int e) {
 static double edge_weight(const orc_graph *g, int64_t e) { return g->weight ? g->weight[e] : 1.0; }
 
 /* ---- energy (for finite differences and closed-form pins) ----------------------------- */
+/* p^T A p of replica s (each ordered pair (i, j) with A_ij != 0 once) */
+static double quad_form(const orc_graph *g, int32_t S, const double *P, int32_t s) {
+    const int32_t n = g->n;
+    double quad = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double pi = P[(size_t)i * S + s];
+        if (g->dense) {
+            for (int32_t j = 0; j < n; ++j) quad += pi * g->W[(size_t)i * n + j] * P[(size_t)j * S + s];
+        } else {
+            for (int64_t e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e)
+                quad += pi * edge_weight(g, e) * P[(size_t)g->col[e] * S + s];
+        }
+    }
+    return quad;
+}
+
+/* 1^T p of replica s */
+static double column_sum(int32_t n, int32_t S, const double *P, int32_t s) {
+    double t = 0.0;
+    for (int32_t i = 0; i < n; ++i) t += P[(size_t)i * S + s];
+    return t;
+}
+
 /* Relaxed objective l^(p) of one replica (continuous relaxation of the penalised loss,
    energies of the appendix "Energy Function of Benchmark Problems"):
-     MIS:    -sum_i p_i + lambda * p^T A p / 2          (c = 1)
-     MaxCut: -sum_{(i,j) in E} A_ij (1 - (2p_i - 1)(2p_j - 1)) / 2                    */
+     MIS:       -sum_i p_i + lambda * p^T A p / 2          (c = 1)
+     MaxCut:    -sum_{(i,j) in E} A_ij (1 - (2p_i - 1)(2p_j - 1)) / 2
+     MaxClique: -sum_i p_i + lambda/2 * ( 1^T p (1^T p - 1) - p^T A p )   (c = 1)          */
 static double relaxed_objective(const orc_params *pr, const orc_graph *g, int32_t S, const double *P, int32_t s) {
     const int32_t n = g->n;
     double l = 0.0;
+    if (pr->problem == ORC_MAXCLIQUE) {
+        const double T = column_sum(n, S, P, s);
+        return -T + pr->lambda / 2.0 * (T * (T - 1.0) - quad_form(g, S, P, s));
+    }
     if (pr->problem == ORC_MIS) {
         double quad = 0.0;
         for (int32_t i = 0; i < n; ++i) {
@@ -250,29 +280,35 @@ double orc_energy(const orc_params *pr, const orc_graph *g, int32_t S, const dou
 
 /* ---- gradient of R^ with respect to P -------------------------------------------------- */
 /* gf: gradient of the relaxed objective
-         MIS     -1 + lambda * sum_j A_ij p_j
-         MaxCut  sum_j A_ij (2 p_j - 1)
+         MIS        -1 + lambda * sum_j A_ij p_j
+         MaxCut     sum_j A_ij (2 p_j - 1)
+         MaxClique  -1 + lambda * (1^T p - 1/2 - sum_j A_ij p_j)   (1^T p over the replica's column)
    ge: gradient of gamma s(p): -2 alpha gamma (2p - 1)^(alpha - 1)
    gc: gradient of -S alpha_c STD_i: -alpha_c (p - mu_i) / sigma_i, taken as 0 when sigma_i = 0
    sigma (optional, n): sigma_i                                                            */
 void orc_grad(const orc_params *pr, const orc_graph *g, int32_t S, const double *P, double gamma,
               double *gf, double *ge, double *gc, double *sigma) {
     const int32_t n = g->n;
+    const int maxcut = pr->problem == ORC_MAXCUT;
+    double *colsum = (double *)malloc((size_t)(S > 0 ? S : 1) * sizeof(double));
+    for (int32_t s = 0; s < S; ++s) colsum[s] = column_sum(n, S, P, s);
     for (int32_t i = 0; i < n; ++i) {
         for (int32_t s = 0; s < S; ++s) {
             double c = 0.0;
             if (g->dense) {
                 for (int32_t j = 0; j < n; ++j) {
                     double pj = P[(size_t)j * S + s];
-                    c += g->W[(size_t)i * n + j] * (pr->problem == ORC_MIS ? pj : 2.0 * pj - 1.0);
+                    c += g->W[(size_t)i * n + j] * (maxcut ? 2.0 * pj - 1.0 : pj);
                 }
             } else {
                 for (int64_t e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e) {
                     double pj = P[(size_t)g->col[e] * S + s];
-                    c += edge_weight(g, e) * (pr->problem == ORC_MIS ? pj : 2.0 * pj - 1.0);
+                    c += edge_weight(g, e) * (maxcut ? 2.0 * pj - 1.0 : pj);
                 }
             }
-            gf[(size_t)i * S + s] = pr->problem == ORC_MIS ? -1.0 + pr->lambda * c : c;
+            if (pr->problem == ORC_MIS) gf[(size_t)i * S + s] = -1.0 + pr->lambda * c;
+            else if (maxcut) gf[(size_t)i * S + s] = c;
+            else gf[(size_t)i * S + s] = -1.0 + pr->lambda * (colsum[s] - 0.5 - c);
             double z = 2.0 * P[(size_t)i * S + s] - 1.0;
             ge[(size_t)i * S + s] = -2.0 * (double)pr->entropy_alpha * gamma * ipow(z, pr->entropy_alpha - 1);
         }
@@ -285,26 +321,32 @@ void orc_grad(const orc_params *pr, const orc_graph *g, int32_t S, const double 
         for (int32_t s = 0; s < S; ++s)
             gc[(size_t)i * S + s] = sd > 0.0 ? -pr->comm_alpha * (row[s] - mu) / sd : 0.0;
     }
+    free(colsum);
 }
 
 /* Sum of the magnitudes of every term that makes up the objective gradient gf of replica
-   s at variable i: 1 + lambda sum_j |A_ij p_j| (MIS) or sum_j |A_ij (2 p_j - 1)| (max-cut).
+   s at variable i: 1 + lambda sum_j |A_ij p_j| (MIS), sum_j |A_ij (2 p_j - 1)| (max-cut),
+   1 + lambda (sum_j |p_j| + 1/2 + sum_j |A_ij p_j|) (max clique).
    A diagnostic for comparisons: it sets the scale of the rounding error of any
    finite-precision evaluation of gf. */
 static double objective_term_magnitude(const orc_params *pr, const orc_graph *g, int32_t S, const double *P,
                                        int32_t i, int32_t s) {
     const int32_t n = g->n;
-    double acc = pr->problem == ORC_MIS ? 1.0 : 0.0;
-    const double scale = pr->problem == ORC_MIS ? pr->lambda : 1.0;
+    double acc = pr->problem == ORC_MAXCUT ? 0.0 : 1.0;
+    const double scale = pr->problem == ORC_MAXCUT ? 1.0 : pr->lambda;
+    if (pr->problem == ORC_MAXCLIQUE) {
+        for (int32_t j = 0; j < n; ++j) acc += scale * fabs(P[(size_t)j * S + s]);
+        acc += scale * 0.5;
+    }
     if (g->dense) {
         for (int32_t j = 0; j < n; ++j) {
             double pj = P[(size_t)j * S + s];
-            acc += scale * fabs(g->W[(size_t)i * n + j] * (pr->problem == ORC_MIS ? pj : 2.0 * pj - 1.0));
+            acc += scale * fabs(g->W[(size_t)i * n + j] * (pr->problem == ORC_MAXCUT ? 2.0 * pj - 1.0 : pj));
         }
     } else {
         for (int64_t e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e) {
             double pj = P[(size_t)g->col[e] * S + s];
-            acc += scale * fabs(edge_weight(g, e) * (pr->problem == ORC_MIS ? pj : 2.0 * pj - 1.0));
+            acc += scale * fabs(edge_weight(g, e) * (pr->problem == ORC_MAXCUT ? 2.0 * pj - 1.0 : pj));
         }
     }
     return acc;
@@ -384,6 +426,9 @@ void orc_run(const orc_params *pr, const orc_graph *g, int32_t S, int32_t t0, in
    x_i = Theta(p_i - 1/2) with Theta(0) = 0, i.e. x = [p > 1/2].
    MIS:    size = sum_i x_i, viol = #{(i,j) in E : x_i = x_j = 1}, l = -size + lambda*viol
    MaxCut: cut  = sum_{(i,j) in E} w_ij [x_i != x_j] counted in units of 2^-16, l = -cut
+   MaxClique: size = sum_i x_i, viol = #{i < j : x_i = x_j = 1, (i,j) not in E}
+           = size (size - 1) / 2 - #{(i,j) in E : x_i = x_j = 1},  l = -size + lambda*viol
+           (the appendix energy at binary x: its bracket counts each such pair twice)
    Integer arithmetic throughout; weights must be integer multiples of 2^-16.
    best = replica minimising (viol > 0, l, s) lexicographically.  Returns 0, or -1 if a
    weight is off the 2^-16 grid.                                                          */
@@ -392,9 +437,10 @@ int orc_eval(int32_t problem, int64_t lambda, const orc_graph *g, int32_t S, con
     const int32_t n = g->n;
     for (int32_t s = 0; s < S; ++s) {
         int64_t a = 0, b = 0;
+        const int counts = problem == ORC_MIS || problem == ORC_MAXCLIQUE;
         for (int32_t i = 0; i < n; ++i) {
             int xi = P[(size_t)i * S + s] > 0.5;
-            if (problem == ORC_MIS) a += xi;
+            if (counts) a += xi;
             int32_t deg = g->dense ? n : (int32_t)(g->row_ptr[i + 1] - g->row_ptr[i]);
             for (int32_t u = 0; u < deg; ++u) {
                 int32_t j; double w;
@@ -402,7 +448,7 @@ int orc_eval(int32_t problem, int64_t lambda, const orc_graph *g, int32_t S, con
                 else { int64_t e = g->row_ptr[i] + u; j = g->col[e]; w = edge_weight(g, e); }
                 if (j <= i || w == 0.0) continue;
                 int xj = P[(size_t)j * S + s] > 0.5;
-                if (problem == ORC_MIS) {
+                if (counts) {
                     b += (xi && xj);
                 } else {
                     double qd = w * 65536.0;
@@ -413,8 +459,9 @@ int orc_eval(int32_t problem, int64_t lambda, const orc_graph *g, int32_t S, con
             }
         }
         size_or_cut[s] = a;
-        viol[s] = problem == ORC_MIS ? b : 0;
-        obj[s] = problem == ORC_MIS ? -a + lambda * b : -a;
+        if (problem == ORC_MAXCLIQUE) b = a * (a - 1) / 2 - b; /* selected pairs that are not edges */
+        viol[s] = counts ? b : 0;
+        obj[s] = counts ? -a + lambda * b : -a;
     }
     int32_t bi = 0;
     for (int32_t s = 1; s < S; ++s) {

@@ -11,7 +11,9 @@ datasets themselves are not available):
   * Erdos-Renyi G(n, p), the family of the ER-[700-800] / ER-[9000-11000] MIS sets;
   * Barabasi-Albert preferential attachment with m edges per new node, the BA max-cut
     family;
-  * complete graphs with Gaussian couplings quantised to a 2^-16 grid (dense max-cut).
+  * complete graphs with Gaussian couplings quantised to a 2^-16 grid (dense max-cut);
+  * Model RB constraint-satisfaction instances with a planted solution, as the
+    compatibility graphs whose cliques are consistent partial assignments (max clique).
 
 A graph is returned as a dict ``{"n", "row_ptr" (int64, n+1), "col" (int32, nnz),
 "weight" (float32, nnz, or None)}`` holding a symmetric CSR without self-loops or
@@ -224,6 +226,41 @@ def build_request_graph(req: dict) -> dict:
 
 
 # --- small graphs with textbook optima (for exact pins) ------------------------------
+
+def rb_model(n_vars: int, domain: int, r: float, p: float, seed) -> dict:
+    """Model RB (Xu and Li, 2000) with a planted solution (the forced-satisfiable variant of
+    Xu, Boussemart, Hemery and Lecoutre, 2007), returned as its compatibility graph.
+
+    n_vars variables share a domain of `domain` values; m = round(r n ln n) binary
+    constraints each pick two distinct variables at random (with repetition across
+    constraints) and forbid round(p domain^2) value pairs chosen uniformly without
+    replacement, never the pair of a planted assignment drawn first.  Graph: one node per
+    (variable, value), node id variable * domain + value; an edge joins two nodes of
+    different variables unless some constraint on that variable pair forbids their
+    values.  A clique holds at most one node per variable, and the planted assignment is
+    a clique of size n_vars, so the clique number is exactly n_vars."""
+    rng = _rng(seed)
+    d = int(domain)
+    N = n_vars * d
+    planted = rng.integers(0, d, n_vars)
+    adj = np.ones((N, N), dtype=bool)
+    for x in range(n_vars):
+        adj[x * d:(x + 1) * d, x * d:(x + 1) * d] = False  # one value per variable
+    m = int(round(r * n_vars * math.log(n_vars)))
+    t = int(round(p * d * d))
+    for _ in range(m):
+        x, y = rng.choice(n_vars, 2, replace=False)
+        allowed = np.ones(d * d, dtype=bool)
+        allowed[planted[x] * d + planted[y]] = False  # the planted pair stays compatible
+        pairs = rng.choice(np.nonzero(allowed)[0], t, replace=False)
+        a, b = pairs // d, pairs % d
+        adj[x * d + a, y * d + b] = False
+        adj[y * d + b, x * d + a] = False
+    iu, ju = np.nonzero(np.triu(adj, 1))
+    g = csr_from_edges(N, np.stack([iu, ju], axis=1))
+    g["planted_clique"] = np.arange(n_vars, dtype=np.int64) * d + planted
+    return g
+
 
 def cycle(n: int) -> dict:
     return csr_from_edges(n, np.array([(i, (i + 1) % n) for i in range(n)], dtype=np.int64))

@@ -85,3 +85,25 @@ def test_csr_from_edges_rejects(bad):
     e = np.array([[0, 0]]) if bad == "loop" else np.array([[0, 1], [1, 0]])
     with pytest.raises(ValueError):
         qi.csr_from_edges(3, e)
+
+
+def test_rb_model_structure():
+    """Model RB compatibility graph: symmetric CSR without self-loops, no edge between two
+    values of one variable, the planted assignment is a clique, so the clique number is
+    exactly the number of variables; seeded."""
+    import itertools
+    g = qi.rb_model(12, 6, 2.6, 0.25, 3)
+    n = g["n"]
+    assert n == 72
+    A = np.zeros((n, n), bool)
+    rows = np.repeat(np.arange(n), np.diff(g["row_ptr"]))
+    A[rows, g["col"]] = True
+    assert np.array_equal(A, A.T) and not A.diagonal().any()
+    var = np.arange(n) // 6
+    assert not (A & (var[:, None] == var[None, :])).any()
+    pc = g["planted_clique"]
+    assert len(set(var[pc])) == 12 and all(A[i, j] for i, j in itertools.combinations(pc, 2))
+    # constraints removed some cross-variable pairs
+    assert A.sum() < (n * n - 12 * 36)
+    h = qi.rb_model(12, 6, 2.6, 0.25, 3)
+    assert np.array_equal(h["col"], g["col"]) and np.array_equal(h["row_ptr"], g["row_ptr"])
