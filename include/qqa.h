@@ -49,7 +49,15 @@ extern "C" {
 #define QQA_E_UNKNOWN_REQ (-6) /* unknown or already collected request handle */
 #define QQA_E_CANCELLED (-7)   /* request was cancelled */
 
-typedef enum { QQA_MIS = 0, QQA_MAXCUT = 1 } qqa_problem;
+/* Problems (appendix "Energy Function of Benchmark Problems"), relaxed objective l^(p) of
+ * one replica, lambda = penalty_lambda:
+ *   QQA_MIS        -sum_i p_i + lambda p^T A p / 2
+ *   QQA_MAXCUT     -sum_{i<j} A_ij (1 - (2p_i - 1)(2p_j - 1)) / 2
+ *   QQA_MAXCLIQUE  -sum_i p_i + lambda/2 (1^T p (1^T p - 1) - p^T A p); its gradient
+ *                  needs the per-replica sum 1^T p over all variables in every update.
+ *                  Max clique runs on the streaming engine of plain solves only (not in
+ *                  batches or the server). */
+typedef enum { QQA_MIS = 0, QQA_MAXCUT = 1, QQA_MAXCLIQUE = 2 } qqa_problem;
 typedef enum { QQA_STEP_ADAMW = 0, QQA_STEP_LANGEVIN = 1 } qqa_step_rule;
 
 /* Hyper-parameters of one solve.  qqa_schedule_default() fills the paper's values:
@@ -105,14 +113,15 @@ int qqa_graph_validate(const qqa_graph *g, qqa_problem problem, char *why, size_
 
 /* Result of a finished request.  The caller owns the optional arrays (NULL = not
  * wanted) and qqa_poll fills them when it returns QQA_OK.
- * Objectives are exact integers: MIS l = -size + lambda * violations; max-cut
- * l = -cut with cut counted in units of 2^-16.  best_replica minimises
- * (violations > 0, l, replica index) lexicographically. */
+ * Objectives are exact integers: MIS l = -size + lambda * violations (selected adjacent
+ * pairs); max-cut l = -cut with cut counted in units of 2^-16; max clique
+ * l = -size + lambda * violations (selected pairs that are not adjacent).  best_replica
+ * minimises (violations > 0, l, replica index) lexicographically. */
 typedef struct {
     int32_t best_replica;
     int32_t feasible;            /* best replica has no violated constraint */
     int64_t best_objective;
-    int64_t best_size_or_cut;    /* MIS set size, or cut in units of 2^-16 */
+    int64_t best_size_or_cut;    /* MIS / clique set size, or cut in units of 2^-16 */
     int64_t best_violations;     /* MIS edges with both ends selected; 0 for max-cut */
     int64_t *replica_objective;  /* [S] or NULL */
     int64_t *replica_size_or_cut;/* [S] or NULL */
@@ -167,7 +176,8 @@ int qqa_solve_resident(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, const qq
  * batch is a single launch covering all instances (each at its own update index), the
  * update loop is replayed from a captured HIP graph.  Instances never interact: each
  * result equals that of the same solve submitted alone.  Graph ids come from
- * qqa_graph_upload.  Arrays have `count` entries; sched may be NULL (defaults). */
+ * qqa_graph_upload.  Arrays have `count` entries; sched may be NULL (defaults).  Dense
+ * graphs and max clique are solved one at a time (QQA_E_ARG here). */
 int qqa_solve_batch(qqa_ctx *c, int32_t count, const qqa_graph_id *graphs, const qqa_problem *problems,
                     const qqa_schedule *sched, const int32_t *S, const int32_t *steps,
                     const uint64_t *seeds, qqa_req *out_ids);
@@ -210,7 +220,7 @@ int qqa_cancel(qqa_ctx *c, qqa_req id);
  * context budget not in use when the server started).  A served result is identical to
  * the same solve run alone.  Replica layouts set on the context before qqa_serve_start
  * apply.  Collect results with qqa_poll (queue_ms = submit -> admission, latency_ms =
- * submit -> result).  Dense graphs are not served.
+ * submit -> result).  Dense graphs and max clique are not served (QQA_E_ARG).
  *   qqa_serve_start: max_slots concurrent requests on the device.
  *   qqa_serve_submit: validates and copies the host graph (the caller may free it on
  *     return) and queues the request; QQA_E_ADMISSION if it can never fit.
@@ -254,12 +264,19 @@ int qqa_dev_init(uint64_t seed, int32_t n, int32_t S, float *P, float *m, float 
 int qqa_dev_dense_coupling(const float *W, const float *P, float *C, int32_t n, int32_t S, qqa_problem problem,
                            void *stream);
 
+/* Per-replica sums of P for max clique, exact in 2^-32 fixed point:
+ * T[s] = sum_i round(P[i*stride + s] * 2^32) for s < stride (padding replicas included),
+ * for P with entries in [0, 1].  T: device, stride uint64, overwritten.  The integer sum
+ * does not depend on the order of additions, so T is bit-reproducible. */
+int qqa_dev_replica_sums(const float *P, int32_t n, int32_t S, uint64_t *T, void *stream);
+
 /* One update t (0-based, AdamW step count t+1) of a K-update schedule:
  * reads P_in, writes P_out (must not alias P_in: neighbours read P_in), updates m, v in
  * place.  lanes_per_row selects the replica layout (0 = default; see
  * qqa_set_replica_layout).  Rows of more than 64 neighbours are split into 16-edge chunks
  * whose partial sums are added in chunk order, as in every solve.  A dense graph takes the
- * coupling product from qqa_dev_dense_coupling's kernel. */
+ * coupling product from qqa_dev_dense_coupling's kernel.  Max clique computes the
+ * per-replica sums of P_in (qqa_dev_replica_sums) before the update. */
 int qqa_dev_step(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule *sched, int32_t S,
                  int32_t t, int32_t K, uint64_t seed, const float *P_in, float *P_out, float *m,
                  float *v, int32_t lanes_per_row, void *stream);

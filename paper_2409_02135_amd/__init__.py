@@ -20,12 +20,13 @@ LIB_PATH = os.path.join(_PKG, "libqqa.so")
 QQA_OK, QQA_PENDING = 0, 1
 QQA_E_ARG, QQA_E_GRAPH, QQA_E_NOMEM, QQA_E_ADMISSION = -1, -2, -3, -4
 QQA_E_DEVICE, QQA_E_UNKNOWN_REQ, QQA_E_CANCELLED = -5, -6, -7
-QQA_MIS, QQA_MAXCUT = 0, 1
+QQA_MIS, QQA_MAXCUT, QQA_MAXCLIQUE = 0, 1, 2
 QQA_STEP_ADAMW, QQA_STEP_LANGEVIN = 0, 1
 QQA_ENGINE_AUTO, QQA_ENGINE_STREAM, QQA_ENGINE_PERSISTENT, QQA_ENGINE_LDS_BLOCK, QQA_ENGINE_BATCH = -1, 0, 1, 2, 3
 ENGINES = {"auto": -1, "stream": 0, "persistent": 1, "lds_block": 2, "batch": 3}
 
-PROBLEMS = {"mis": QQA_MIS, "maxcut": QQA_MAXCUT, QQA_MIS: QQA_MIS, QQA_MAXCUT: QQA_MAXCUT}
+PROBLEMS = {"mis": QQA_MIS, "maxcut": QQA_MAXCUT, "maxclique": QQA_MAXCLIQUE,
+            QQA_MIS: QQA_MIS, QQA_MAXCUT: QQA_MAXCUT, QQA_MAXCLIQUE: QQA_MAXCLIQUE}
 
 
 class QQAError(RuntimeError):
@@ -99,6 +100,7 @@ def lib():
             "qqa_autotune": (C.c_int, [vp, i64, i32, i32, vp]),
             "qqa_dev_eval": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
             "qqa_dev_dense_coupling": (C.c_int, [vp, vp, vp, i32, i32, i32, vp]),
+            "qqa_dev_replica_sums": (C.c_int, [vp, i32, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -202,6 +204,11 @@ def qqa_dev_run(g: DevGraph, problem, sched: qqa_schedule | None, S, t0, t1, K, 
     return _dev_check(lib().qqa_dev_run(C.byref(g.struct), PROBLEMS[problem], None if sched is None else C.byref(sched),
                                         S, t0, t1, K, seed, _ptr(P0), _ptr(P1), _ptr(m), _ptr(v), e, lanes_per_row,
                                         _stream(stream)))
+
+
+def qqa_dev_replica_sums(P, n, S, T, stream=None):
+    """T (device uint64/int64 tensor of stride entries) = per-replica sums of P in 2^-32 units."""
+    return _dev_check(lib().qqa_dev_replica_sums(_ptr(P), n, S, _ptr(T), _stream(stream)))
 
 
 def qqa_dev_dense_coupling(W, P, C, n, S, problem, stream=None):

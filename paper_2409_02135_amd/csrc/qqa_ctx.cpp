@@ -19,10 +19,11 @@ using Clock = std::chrono::steady_clock;
 
 namespace qqa {
 
-size_t request_footprint(int n, int S, int rule) {
+size_t request_footprint(int n, int S, int rule, int problem) {
   const size_t stride = (size_t)replica_shape(S).stride;
   const size_t state = (size_t)n * stride * sizeof(float) * (rule == QQA_STEP_ADAMW ? 4 : 2);
-  return state + out_bytes(n, S) + 2 * stride * sizeof(unsigned long long) + 4096;
+  const size_t sums = problem == QQA_MAXCLIQUE ? stride * sizeof(unsigned long long) : 0;
+  return state + out_bytes(n, S) + 2 * stride * sizeof(unsigned long long) + sums + 4096;
 }
 
 // result record: size_or_cut[S], viol[S], obj[S] (int64), best (int32) + pad, barrier
@@ -127,6 +128,7 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
   get((void**)&r->acc, 2 * (size_t)r->shape.stride * sizeof(unsigned long long));
   r->hub_bytes = (size_t)nchunks * r->shape.stride * sizeof(float);
   if (nchunks) get((void**)&r->hub_partial, r->hub_bytes);
+  if (r->problem == QQA_MAXCLIQUE) get((void**)&r->colsum, (size_t)r->shape.stride * sizeof(unsigned long long));
   r->coupling_bytes = 0;
   auto git = c->graphs.find(r->graph);
   if (git != c->graphs.end() && git->second.dense) {
@@ -169,6 +171,8 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
   r->hub_partial = nullptr;
   c->dpool.put(r->coupling, r->coupling_bytes);
   r->coupling = nullptr;
+  if (r->colsum) c->dpool.put(r->colsum, (size_t)r->shape.stride * sizeof(unsigned long long));
+  r->colsum = nullptr;
   c->dpool.put(r->out_dev, r->out_size);
   c->hpool.put(r->out_host, r->out_size);
   c->dpool.put(r->table_dev, r->table_bytes);
@@ -195,6 +199,7 @@ StepParams request_step_params(const Request* r, const DevGraph& g) {
   p.w = r->problem == QQA_MAXCUT ? g.w : nullptr;
   p.hub_first = g.hub_first;
   p.hub_partial = r->hub_partial;
+  p.colsum = r->colsum;
   p.coupling = g.dense ? r->coupling : nullptr;
   p.m = r->m;
   p.v = r->v;
@@ -263,16 +268,17 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   r->n = g.n;
   r->shape = replica_shape(S);
   r->lanes_per_row = c->layout_for(S);
-  r->footprint = request_footprint(g.n, S, r->sched.rule) + (size_t)g.nchunks * r->shape.stride * sizeof(float) +
+  r->footprint = request_footprint(g.n, S, r->sched.rule, problem) + (size_t)g.nchunks * r->shape.stride * sizeof(float) +
                  (g.dense ? (size_t)g.n * r->shape.stride * sizeof(float) : 0);
   if (r->footprint + g.bytes > c->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the HBM budget");
   {
     StepParams probe = request_step_params(r.get(), g);
     // auto: one workgroup with P in LDS when the instance fits, else one launch per update
     // (measured faster on this GPU than the register-resident engine for larger instances).
-    // Dense graphs always stream: their coupling product is a separate matrix-core launch
-    // before every update, which no persistent engine performs.
-    const int allow = g.dense ? 0 : c->engine_policy < 0 ? 1 : (c->engine_policy == QQA_ENGINE_LDS_BLOCK ? 1 :
+    // Dense graphs and max clique always stream: the coupling product (matrix cores) and
+    // the per-replica sums are separate launches before every update, which no
+    // persistent engine performs.
+    const int allow = g.dense || problem == QQA_MAXCLIQUE ? 0 : c->engine_policy < 0 ? 1 : (c->engine_policy == QQA_ENGINE_LDS_BLOCK ? 1 :
                                                  (c->engine_policy == QQA_ENGINE_PERSISTENT ? 2 : 0));
     r->engine = allow ? persistent_plan(probe, g.nchunks > 0, allow, &r->rows_per_group, &r->grid) : kEngineStream;
     if (r->engine != kEngineStream) {
@@ -312,6 +318,11 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
       p.P_in = r->P[t & 1];
       p.P_out = r->P[(t + 1) & 1];
       fill_step_scalars(p, r->sched, t, steps);
+      if (r->colsum) {
+        p.colsum = r->colsum;
+        e = launch_colsum(p.P_in, g.n, p.stride, r->colsum, c->stream);
+        if (e != hipSuccess) break;
+      }
       const size_t pi = 2 * (size_t)(t / every);
       const bool probe = t % every == every / 2 && pi + 1 < r->probe.size();
       if (g.dense) {
@@ -396,7 +407,7 @@ const char* qqa_last_error(const qqa_ctx* c) { return c ? c->err.c_str() : "NULL
 
 int qqa_graph_upload(qqa_ctx* c, const qqa_graph* g, qqa_problem problem, qqa_graph_id* out) {
   if (!c || !g || !out) return c ? set_err(c, QQA_E_ARG, "NULL argument") : QQA_E_ARG;
-  if (problem != QQA_MIS && problem != QQA_MAXCUT) return set_err(c, QQA_E_ARG, "unknown problem");
+  if (!known_problem(problem)) return set_err(c, QQA_E_ARG, "unknown problem");
   (void)hipSetDevice(c->device);
   DevGraph d;
   int rc = upload_graph(c, *g, problem, &d, &c->err);
@@ -423,7 +434,7 @@ int qqa_graph_release(qqa_ctx* c, qqa_graph_id id) {
 
 static int check_solve_args(qqa_ctx* c, qqa_problem problem, int32_t S, int32_t steps, qqa_req* out_id) {
   if (!out_id) return set_err(c, QQA_E_ARG, "out_id is NULL");
-  if (problem != QQA_MIS && problem != QQA_MAXCUT) return set_err(c, QQA_E_ARG, "unknown problem");
+  if (!known_problem(problem)) return set_err(c, QQA_E_ARG, "unknown problem");
   if (S <= 0 || S > kMaxReplicas) return set_err(c, QQA_E_ARG, "S must be in [1, 4096]");
   if (steps <= 0) return set_err(c, QQA_E_ARG, "steps must be positive");
   return QQA_OK;
@@ -483,7 +494,7 @@ int qqa_autotune(qqa_ctx* c, qqa_graph_id gid, qqa_problem problem, int32_t S, i
   r.S = S;
   r.n = g.n;
   r.shape = replica_shape(S);
-  const size_t fp = request_footprint(g.n, S, r.sched.rule) + (size_t)g.nchunks * r.shape.stride * sizeof(float);
+  const size_t fp = request_footprint(g.n, S, r.sched.rule, problem) + (size_t)g.nchunks * r.shape.stride * sizeof(float);
   if (c->in_use + fp > c->budget) return set_err(c, QQA_E_NOMEM, "no budget left for tuning state");
   int rc = alloc_request_buffers(c, &r, &c->err, g.nchunks);
   if (rc) return rc;
@@ -491,6 +502,8 @@ int qqa_autotune(qqa_ctx* c, qqa_graph_id gid, qqa_problem problem, int32_t S, i
   int best = 0;
   float best_ms = 1e30f;
   hipError_t e = launch_init(1, g.n, S, r.P[0], r.m, r.v, c->stream);
+  // max clique: valid per-replica sums for the timed updates (their values do not matter)
+  if (e == hipSuccess && r.colsum) e = launch_colsum(r.P[0], g.n, r.shape.stride, r.colsum, c->stream);
   int last_lpr = -1;
   for (int want = 1; want <= 64 && e == hipSuccess; want <<= 1) {
     const ReplicaShape sh = replica_shape(S, want);

@@ -61,6 +61,7 @@ struct Request {
   float* hub_partial = nullptr;  // nchunks x stride
   size_t hub_bytes = 0;
   float* coupling = nullptr;     // dense graphs: n x stride coupling product
+  unsigned long long* colsum = nullptr;  // max clique: per-replica sums of P (2^-32 fixed point)
   size_t coupling_bytes = 0;
   char* out_dev = nullptr;
   char* out_host = nullptr;
@@ -106,7 +107,7 @@ struct qqa_ctx {
 
 namespace qqa {
 
-size_t request_footprint(int n, int S, int rule);
+size_t request_footprint(int n, int S, int rule, int problem);
 size_t out_bytes(int n, int S);
 void out_views(char* base, int n, int S, int64_t** a, int64_t** b, int64_t** o, int32_t** best, uint8_t** x);
 // barrier words of a persistent launch inside a result record: [0] arrivals, [1] abort

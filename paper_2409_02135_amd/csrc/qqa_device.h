@@ -196,14 +196,17 @@ __device__ __forceinline__ void row_coupling(const StepParams& a, const int row,
 
 // Everything after the coupling product: replica statistics mu_i, sigma_i (two passes,
 // population STD), gradient, AdamW or plain step, noise, clamp.  Writes the new values
-// of lane gl's replicas to po / mo / vo (padding replicas 0).
-template <int LPR, int QPL, bool FULL>
+// of lane gl's replicas to po / mo / vo (padding replicas 0).  SUMS: the kernel may run
+// max clique (per-replica sums in a.colsum); kernels that never do leave it out and keep
+// their registers.
+template <int LPR, int QPL, bool FULL, bool SUMS = true>
 __device__ __forceinline__ void finish_row(const StepParams& a, const int row, const int gl, const float4 (&p)[QPL],
                                            const float4 (&mm)[QPL], const float4 (&vv)[QPL],
                                            const float4 (&acc)[QPL], float4 (&po)[QPL], float4 (&mo)[QPL],
                                            float4 (&vo)[QPL]) {
   const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
   const bool maxcut = a.problem == kMAXCUT;
+  const bool clique = SUMS && a.problem == kMAXCLIQUE;
   const bool adam = a.rule == kADAMW;
   float sum = 0.f;
 #pragma unroll
@@ -236,11 +239,17 @@ __device__ __forceinline__ void finish_row(const StepParams& a, const int row, c
     po[k] = mo[k] = vo[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (!FULL && q >= nq) continue;
     const float4 xi = normals4(philox4x32_10((uint32_t)row, (uint32_t)q, a.k, kStreamNoise, a.key0, a.key1));
+    float4 T = make_float4(0.f, 0.f, 0.f, 0.f);  // max clique: 1^T p of the quad's replicas
+    if (clique) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) set_comp(T, c, (float)((double)a.colsum[4 * q + c] * 0x1p-32));
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const float pc = comp(p[k], c);
       const float C = comp(acc[k], c);
-      const float gf = maxcut ? C : fmaf(a.lambda, C, -1.f);
+      // MIS: -1 + lambda C;  max-cut: C;  max clique: -1 + lambda (1^T p - 1/2 - C)
+      const float gf = maxcut ? C : fmaf(a.lambda, clique ? (comp(T, c) - 0.5f) - C : C, -1.f);
       const float z = 2.f * pc - 1.f;
       const float ge = a.ce * ipow_odd(z, a.alpha_e - 1);
       const float gc = cg * (pc - mu);
@@ -284,12 +293,12 @@ __device__ __forceinline__ void store_row(const StepParams& a, float* P, const i
 }
 
 // One update of one row, state streamed from and to memory.
-template <int LPR, int QPL, bool FULL>
+template <int LPR, int QPL, bool FULL, bool SUMS = true>
 __device__ __forceinline__ void update_row(const StepParams& a, const int row, const int gl) {
   float4 p[QPL], mm[QPL], vv[QPL], acc[QPL], po[QPL], mo[QPL], vo[QPL];
   load_row<LPR, QPL, FULL>(a, a.P_in, row, gl, p, mm, vv);  // issued before the gathers
   row_coupling<LPR, QPL, FULL>(a, row, gl, acc);
-  finish_row<LPR, QPL, FULL>(a, row, gl, p, mm, vv, acc, po, mo, vo);
+  finish_row<LPR, QPL, FULL, SUMS>(a, row, gl, p, mm, vv, acc, po, mo, vo);
   store_row<LPR, QPL, FULL>(a, a.P_out, row, gl, po, mo, vo, true);
 }
 

@@ -9,7 +9,7 @@
 
 namespace qqa {
 
-enum : int32_t { kMIS = 0, kMAXCUT = 1 };
+enum : int32_t { kMIS = 0, kMAXCUT = 1, kMAXCLIQUE = 2 };
 enum : int32_t { kADAMW = 0, kLANGEVIN = 1 };
 enum : uint32_t { kStreamInit = 0, kStreamNoise = 1 };
 
@@ -48,13 +48,15 @@ struct StepParams {
   const float* coupling;   // dense path: precomputed coupling product, n x stride, or nullptr
   const int32_t* hub_first;  // per row: first chunk of a split row, -1 otherwise (nullptr: no hubs)
   const float* hub_partial;  // per chunk: partial coupling sums, nchunks x stride
+  // max clique: per-replica sums 1^T p of P_in in 2^-32 fixed point ([stride]), else nullptr
+  const unsigned long long* colsum;
   const float* P_in;
   float* P_out;
   float* m;
   float* v;
   int32_t n, S, stride, problem, rule, alpha_e;
   int32_t lanes_per_row;   // replica layout (0 = default); selects the kernel instance
-  float lambda;            // MIS penalty
+  float lambda;            // MIS / max-clique penalty
   float lr, wd_factor;     // wd_factor = 1 - lr * weight_decay
   float comm_alpha;
   float beta1, omb1, beta2, omb2, eps;
@@ -149,6 +151,11 @@ hipError_t launch_persistent(const PersistParams& pp, int engine, int rows_per_g
 
 // Dense coupling product C = W f(P) on the matrix cores (W symmetric n x n, P and C
 // n x stride; f(p) = 2p - 1 for max-cut, p for MIS).
+// Per-replica sums T[s] = sum_i P[i][s] (max clique), accumulated exactly in 2^-32 fixed
+// point: each p is rounded once to a multiple of 2^-32, and the integer sums are independent
+// of the order of addition.  T (stride entries) is cleared by the launcher.
+hipError_t launch_colsum(const float* P, int n, int stride, unsigned long long* T, hipStream_t st);
+
 hipError_t launch_dense_coupling(const float* W, const float* P, float* C, int n, int stride, int problem,
                                  hipStream_t st);
 

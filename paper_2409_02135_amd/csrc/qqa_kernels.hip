@@ -7,6 +7,8 @@
 // wavefront for smaller S); each lane owns float4 quads of replicas, which makes every
 // neighbour-row gather a coalesced, 16-byte-per-lane load and gives one Philox call
 // (4 normals) per lane and quad.
+#include <algorithm>
+
 #include "qqa_device.h"
 
 namespace qqa {
@@ -66,14 +68,15 @@ __global__ __launch_bounds__(kBlock) void hub_partial_kernel(StepParams a, const
   }
 }
 
-template <int LPR, int QPL, bool FULL>
+// SUMS: the max-clique instance (reads the per-replica sums); the others do not carry it
+template <int LPR, int QPL, bool FULL, bool SUMS>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepParams a) {
   int row = (int)(((long long)blockIdx.x * kBlock + threadIdx.x) / LPR);
   // a whole wavefront serves one row when LPR = 64: make that explicit so the CSR reads
   // become scalar loads and neighbour addresses a scalar base plus the lane offset
   if (LPR == 64) row = __builtin_amdgcn_readfirstlane(row);
   if (row >= a.n) return;  // whole LPR-lane groups leave together
-  update_row<LPR, QPL, FULL>(a, row, threadIdx.x & (LPR - 1));
+  update_row<LPR, QPL, FULL, SUMS>(a, row, threadIdx.x & (LPR - 1));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -156,6 +159,16 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(EvalParams a) {
   }
 }
 
+// Violations and objective of replica s from the counts: MIS counts selected adjacent
+// pairs; max clique turns the count of selected adjacent pairs into the selected pairs
+// that are not adjacent, size (size - 1) / 2 - count; max-cut has none.
+__device__ __forceinline__ void derive(const EvalParams& a, int s, long long* A, long long* B, long long* o) {
+  *A = (long long)a.acc[s];
+  const long long cnt = (long long)a.acc[a.stride + s];
+  *B = a.problem == kMAXCLIQUE ? *A * (*A - 1) / 2 - cnt : cnt;
+  *o = a.problem == kMAXCUT ? -*A : -*A + a.lambda * *B;
+}
+
 // objectives and the lexicographic best replica (violations > 0, l, index)
 __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalParams a) {
   __shared__ int best_s[kBlock];
@@ -163,8 +176,8 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalParams a) {
   bool mi = false;
   long long mo = 0;
   for (int s = threadIdx.x; s < a.S; s += kBlock) {
-    const long long A = (long long)a.acc[s], B = (long long)a.acc[a.stride + s];
-    const long long o = a.problem == kMAXCUT ? -A : -A + a.lambda * B;
+    long long A, B, o;
+    derive(a, s, &A, &B, &o);
     a.size_or_cut[s] = A;
     a.viol[s] = B;
     a.obj[s] = o;
@@ -183,10 +196,9 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalParams a) {
       if (y >= 0) {
         bool take = x < 0;
         if (!take) {
-          const long long Bx = (long long)a.acc[a.stride + x], By = (long long)a.acc[a.stride + y];
-          const long long Ax = (long long)a.acc[x], Ay = (long long)a.acc[y];
-          const long long ox = a.problem == kMAXCUT ? -Ax : -Ax + a.lambda * Bx;
-          const long long oy = a.problem == kMAXCUT ? -Ay : -Ay + a.lambda * By;
+          long long Ax, Bx, ox, Ay, By, oy;
+          derive(a, x, &Ax, &Bx, &ox);
+          derive(a, y, &Ay, &By, &oy);
           const bool ix = Bx > 0, iy = By > 0;
           take = (iy < ix) || (iy == ix && (oy < ox || (oy == ox && y < x)));
         }
@@ -201,6 +213,37 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(EvalParams a) {
 __global__ void extract_kernel(const float* P, int n, int stride, const int32_t* best, uint8_t* x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = P[(size_t)i * stride + best[0]] > 0.5f ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Per-replica sums of P (max clique).  Block b sums rows [b * rows, (b + 1) * rows): each
+// thread takes one quad of replicas and every lanes-th row of the band, in 2^-32 fixed
+// point (p in [0, 1] times 2^32 is exact in double, then rounded once), so the block's
+// partial and the final total are exact integers whatever order the additions run in.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void colsum_kernel(const float* __restrict__ P, int n, int stride, int rows,
+                                                        unsigned long long* __restrict__ T) {
+  extern __shared__ unsigned long long colsum_sh[];  // [stride]
+  for (int c = threadIdx.x; c < stride; c += kBlock) colsum_sh[c] = 0ull;
+  __syncthreads();
+  const int nq = stride >> 2;
+  const int lanes = nq >= kBlock ? 1 : kBlock / nq;  // row lanes per quad
+  const int r0 = blockIdx.x * rows, r1 = min(n, r0 + rows);
+  for (int slot = threadIdx.x; slot < lanes * nq; slot += kBlock) {
+    const int q = slot % nq, rl = slot / nq;
+    unsigned long long acc[4] = {0ull, 0ull, 0ull, 0ull};
+    for (int r = r0 + rl; r < r1; r += lanes) {
+      const float4 v = *reinterpret_cast<const float4*>(P + (size_t)r * stride + 4 * q);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] += (unsigned long long)__double2ull_rn((double)comp(v, c) * 0x1p32);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (acc[c]) atomicAdd(&colsum_sh[4 * q + c], acc[c]);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < stride; c += kBlock)
+    if (colsum_sh[c]) atomicAdd(&T[c], colsum_sh[c]);
 }
 
 __global__ void fill_u64_kernel(unsigned long long* p, size_t count) {
@@ -280,10 +323,14 @@ hipError_t launch_init(uint64_t seed, int n, int S, float* P, float* m, float* v
 template <int LPR, int QPL>
 static void launch_step_t(const StepParams& p, hipStream_t st) {
   const dim3 grid(grid_for((long long)p.n * LPR)), block(kBlock);
-  if (p.S == 4 * LPR * QPL)
-    hipLaunchKernelGGL((step_kernel<LPR, QPL, true>), grid, block, 0, st, p);
-  else
-    hipLaunchKernelGGL((step_kernel<LPR, QPL, false>), grid, block, 0, st, p);
+  const bool full = p.S == 4 * LPR * QPL;
+  if (p.problem == kMAXCLIQUE) {
+    if (full) hipLaunchKernelGGL((step_kernel<LPR, QPL, true, true>), grid, block, 0, st, p);
+    else hipLaunchKernelGGL((step_kernel<LPR, QPL, false, true>), grid, block, 0, st, p);
+  } else {
+    if (full) hipLaunchKernelGGL((step_kernel<LPR, QPL, true, false>), grid, block, 0, st, p);
+    else hipLaunchKernelGGL((step_kernel<LPR, QPL, false, false>), grid, block, 0, st, p);
+  }
 }
 
 template <int LPR, int QPL>
@@ -321,6 +368,17 @@ hipError_t launch_step(const StepParams& p, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
+
+hipError_t launch_colsum(const float* P, int n, int stride, unsigned long long* T, hipStream_t st) {
+  hipError_t e = launch_fill_u64(T, (size_t)stride, st);
+  if (e != hipSuccess || n == 0) return e;
+  // a few hundred blocks: enough loads in flight to stream P, few integer atomics per column
+  const int blocks = std::max(1, std::min(256, (n + 7) / 8));
+  const int rows = (n + blocks - 1) / blocks;
+  hipLaunchKernelGGL(colsum_kernel, dim3((n + rows - 1) / rows), dim3(kBlock), (size_t)stride * sizeof(unsigned long long),
+                     st, P, n, stride, rows, T);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_u64(unsigned long long* p, size_t count, hipStream_t st) {
   if (count == 0) return hipSuccess;

@@ -115,8 +115,8 @@ int validate_graph(const qqa_graph& g, int problem, std::string* why) {
         const float a = g.dense[(size_t)i * n + j], b = g.dense[(size_t)j * n + i];
         if (a != b) return fail(why, QQA_E_GRAPH, "dense graph is not symmetric");
         if (!std::isfinite(a)) return fail(why, QQA_E_GRAPH, "dense graph has a non-finite weight");
-        if (problem == QQA_MIS && a != 0.f && a != 1.f)
-          return fail(why, QQA_E_GRAPH, "MIS dense adjacency must be 0/1");
+        if ((problem == QQA_MIS || problem == QQA_MAXCLIQUE) && a != 0.f && a != 1.f)
+          return fail(why, QQA_E_GRAPH, "MIS / max-clique dense adjacency must be 0/1");
         if (problem == QQA_MAXCUT && !on_grid(a))
           return fail(why, QQA_E_GRAPH, "max-cut weight not a multiple of 2^-16 with |w| < 128");
       }
@@ -280,12 +280,23 @@ static int dev_graph_check(const qqa_dev_graph* g) {
   return QQA_OK;
 }
 
+// max clique: per-replica sums of P_in for the update that reads it (stream-ordered buffer)
+static hipError_t colsum_for(StepParams& p, int problem, unsigned long long** T, hipStream_t st) {
+  if (problem != QQA_MAXCLIQUE) return hipSuccess;
+  if (!*T) {
+    hipError_t e = hipMallocAsync((void**)T, (size_t)p.stride * sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+  }
+  p.colsum = *T;
+  return launch_colsum(p.P_in, p.n, p.stride, *T, st);
+}
+
 int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule* sched, int32_t S, int32_t t,
                  int32_t K, uint64_t seed, const float* P_in, float* P_out, float* m, float* v,
                  int32_t lanes_per_row, void* stream) {
   int rc = dev_graph_check(g);
   if (rc) return rc;
-  if (problem != QQA_MIS && problem != QQA_MAXCUT) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
+  if (!known_problem(problem)) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
   if (S <= 0 || S > kMaxReplicas) return fail(&g_dev_error, QQA_E_ARG, "S must be in [1, 4096]");
   if (K <= 0 || t < 0 || t >= K) return fail(&g_dev_error, QQA_E_ARG, "need 0 <= t < K");
   qqa_schedule s;
@@ -312,6 +323,8 @@ int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule
   fill_step_scalars(p, s, t, K);
   p.lanes_per_row = lanes_per_row;
   if (g->n == 0) return QQA_OK;
+  unsigned long long* T = nullptr;
+  DEV_CHECK(colsum_for(p, problem, &T, st));
   if (g->dense) {
     float* C = nullptr;
     DEV_CHECK(hipMallocAsync((void**)&C, (size_t)g->n * p.stride * sizeof(float), st));
@@ -322,6 +335,7 @@ int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule
     hipError_t e = launch_dense_coupling(g->dense, P_in, C, g->n, p.stride, problem, st);
     if (e == hipSuccess) e = launch_step(p, st);
     (void)hipFreeAsync(C, st);
+    if (T) (void)hipFreeAsync(T, st);
     DEV_CHECK(e);
     return QQA_OK;
   }
@@ -346,6 +360,7 @@ int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule
     DEV_CHECK(launch_hub_partials(p, d_chunks, (int)chunks.size(), st));
   }
   hipError_t e = launch_step(p, st);
+  if (T) (void)hipFreeAsync(T, st);
   if (!chunks.empty()) {
     (void)hipFreeAsync(d_chunks, st);
     (void)hipFreeAsync(d_first, st);
@@ -362,7 +377,7 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
                 int32_t lanes_per_row, void* stream) {
   int rc = dev_graph_check(g);
   if (rc) return rc;
-  if (problem != QQA_MIS && problem != QQA_MAXCUT) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
+  if (!known_problem(problem)) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
   if (S <= 0 || S > kMaxReplicas) return fail(&g_dev_error, QQA_E_ARG, "S must be in [1, 4096]");
   if (K <= 0 || t0 < 0 || t1 < t0 || t1 > K) return fail(&g_dev_error, QQA_E_ARG, "need 0 <= t0 <= t1 <= K");
   qqa_schedule s;
@@ -375,6 +390,9 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
     return fail(&g_dev_error, QQA_E_ARG, "unsupported replica layout");
   if (g->n == 0 || t0 == t1) return QQA_OK;
   hipStream_t st = (hipStream_t)stream;
+  if (problem == QQA_MAXCLIQUE && engine > 0)
+    return fail(&g_dev_error, QQA_E_ARG, "max clique runs on the streaming engine");
+  unsigned long long* T = nullptr;
   if (g->dense) {
     if (engine > 0) return fail(&g_dev_error, QQA_E_ARG, "dense coupling runs on the streaming engine");
     StepParams p{};
@@ -392,10 +410,12 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
       p.P_in = P[t & 1];
       p.P_out = P[(t + 1) & 1];
       fill_step_scalars(p, s, t, K);
-      e = launch_dense_coupling(g->dense, p.P_in, C, g->n, p.stride, problem, st);
+      e = colsum_for(p, problem, &T, st);
+      if (e == hipSuccess) e = launch_dense_coupling(g->dense, p.P_in, C, g->n, p.stride, problem, st);
       if (e == hipSuccess) e = launch_step(p, st);
     }
     (void)hipFreeAsync(C, st);
+    if (T) (void)hipFreeAsync(T, st);
     DEV_CHECK(e);
     return QQA_OK;
   }
@@ -416,7 +436,7 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
   build_hub_plan(rp.data(), g->n, &chunks, &hub_first);
   int rpg = 0, grid = 0;
   int use = kEngineStream;
-  if (engine != kEngineStream) {
+  if (engine != kEngineStream && problem != QQA_MAXCLIQUE) {
     // allow mask: 1 = one workgroup with P in LDS, 2 = many workgroups with registers
     const int allow = engine < 0 ? 3 : (engine == kEngineLdsBlock ? 1 : (engine == kEnginePersistent ? 2 : 0));
     if (!allow) return fail(&g_dev_error, QQA_E_ARG, "unknown engine");
@@ -442,9 +462,11 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
       p.P_in = P[t & 1];
       p.P_out = P[(t + 1) & 1];
       fill_step_scalars(p, s, t, K);
-      if (!chunks.empty()) e = launch_hub_partials(p, d_chunks, (int)chunks.size(), st);
+      e = colsum_for(p, problem, &T, st);
+      if (e == hipSuccess && !chunks.empty()) e = launch_hub_partials(p, d_chunks, (int)chunks.size(), st);
       if (e == hipSuccess) e = launch_step(p, st);
     }
+    if (T) (void)hipFreeAsync(T, st);
     if (!chunks.empty()) {
       (void)hipFreeAsync(d_chunks, st);
       (void)hipFreeAsync(d_first, st);
@@ -492,8 +514,15 @@ int qqa_dev_dense_coupling(const float* W, const float* P, float* C, int32_t n, 
                            void* stream) {
   if (n < 0 || S <= 0 || S > kMaxReplicas || (n > 0 && (!W || !P || !C)))
     return fail(&g_dev_error, QQA_E_ARG, "bad dense coupling arguments");
-  if (problem != QQA_MIS && problem != QQA_MAXCUT) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
+  if (!known_problem(problem)) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
   DEV_CHECK(launch_dense_coupling(W, P, C, n, replica_shape(S).stride, problem, (hipStream_t)stream));
+  return QQA_OK;
+}
+
+int qqa_dev_replica_sums(const float* P, int32_t n, int32_t S, uint64_t* T, void* stream) {
+  if (n < 0 || S <= 0 || S > kMaxReplicas || !T || (n > 0 && !P))
+    return fail(&g_dev_error, QQA_E_ARG, "bad replica-sum arguments");
+  DEV_CHECK(launch_colsum(P, n, replica_shape(S).stride, reinterpret_cast<unsigned long long*>(T), (hipStream_t)stream));
   return QQA_OK;
 }
 
@@ -501,7 +530,7 @@ int qqa_dev_eval(const qqa_dev_graph* g, qqa_problem problem, int32_t penalty_la
                  int64_t* size_or_cut, int64_t* viol, int64_t* obj, int32_t* best, void* stream) {
   if (!g || g->n < 0) return fail(&g_dev_error, QQA_E_ARG, "graph is NULL or n < 0");
   if (!g->dense && g->n > 0 && !g->row_ptr) return fail(&g_dev_error, QQA_E_ARG, "row_ptr missing");
-  if (problem != QQA_MIS && problem != QQA_MAXCUT) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
+  if (!known_problem(problem)) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
   if (S <= 0 || S > kMaxReplicas) return fail(&g_dev_error, QQA_E_ARG, "S must be in [1, 4096]");
   if (!size_or_cut || !viol || !obj || !best || (g->n > 0 && !P)) return fail(&g_dev_error, QQA_E_ARG, "output missing");
   const ReplicaShape r = replica_shape(S);

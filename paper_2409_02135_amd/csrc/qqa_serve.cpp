@@ -154,7 +154,8 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     I.g = &git->second;
     I.gid = graphs[i];
     I.problem = problems[i];
-    if (I.problem != QQA_MIS && I.problem != QQA_MAXCUT) return set_err(c, QQA_E_ARG, "unknown problem");
+    if (!known_problem(I.problem)) return set_err(c, QQA_E_ARG, "unknown problem");
+    if (I.problem == QQA_MAXCLIQUE) return set_err(c, QQA_E_ARG, "max clique is solved one at a time");
     if (I.g->problem != I.problem) return set_err(c, QQA_E_ARG, "graph was uploaded for another problem type");
     if (I.g->dense) return set_err(c, QQA_E_ARG, "dense graphs are solved one at a time");
     I.S = S[i];

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void slot_step_kernel(const SlotDesc* slots
     int row = w.row0 + (int)threadIdx.x / LPR;
     if (LPR == 64) row = __builtin_amdgcn_readfirstlane(row);
     if (row >= a.n) continue;  // whole lane groups
-    update_row<LPR, QPL, FULL>(a, row, threadIdx.x & (LPR - 1));
+    update_row<LPR, QPL, FULL, false>(a, row, threadIdx.x & (LPR - 1));  // batches never run max clique
   }
 }
 

@@ -80,7 +80,8 @@ def run_gpu_step(q, g, problem, sched, S, t, K, seed, P, m, v, lanes_per_row=0):
 
 
 def oracle_params(orc, q, sched, problem):
-    return orc.Params(problem=0 if problem == "mis" else 1, gamma_min=sched.gamma_min, gamma_max=sched.gamma_max,
+    return orc.Params(problem={"mis": 0, "maxcut": 1, "maxclique": 2}[problem], gamma_min=sched.gamma_min,
+                      gamma_max=sched.gamma_max,
                       lr=sched.lr, weight_decay=sched.weight_decay, temperature=sched.temperature,
                       comm_alpha=sched.comm_alpha, entropy_alpha=sched.entropy_alpha, rule=sched.rule,
                       beta1=sched.beta1, beta2=sched.beta2, adam_eps=sched.adam_eps,
