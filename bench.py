@@ -34,6 +34,11 @@ WORKLOADS = {
     "mis_rrg_n256_d3_S16_K2000": ("rrg", 256, 3, "mis", 16, 2000),
     # dense symmetric Gaussian couplings (Sherrington-Kirkpatrick-like max-cut)
     "maxcut_dense_n4096_gauss_S256_K3000": ("dense", 4096, 0, "maxcut", 256, 3000),
+    # the MIS scaling study's shape: random 20-regular graph, one million variables, S = 1
+    "mis_rrg_n1000000_d20_S1_K3000": ("rrg_swap", 1000000, 20, "mis", 1, 3000),
+    # max clique on a Model RB instance (20 variables x 12 values, planted clique of 20),
+    # the paper's 1,000 parallel runs
+    "maxclique_rb20x12_S1000_K3000": ("rb", 240, (20, 12, 2.6, 0.25), "maxclique", 1000, 3000),
 }
 DEFAULT = "mis_er_n20000_d5_S256_K3000"
 
@@ -42,6 +47,10 @@ def make_graph(family, n, d, problem, seed=0):
     import qqa_inputs as qi
     if family == "dense":
         return {"n": n, "dense": qi.dense_gaussian(n, seed)}
+    if family == "rb":
+        return qi.rb_model(*d, seed)
+    if family == "rrg_swap":
+        return qi.random_regular_swapped(n, int(d), seed)
     if family == "er":
         g = qi.erdos_renyi(n, d, seed)
     elif family == "ba":
@@ -212,8 +221,9 @@ def cpu_baseline(g, problem, S, K, updates=20):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload: the first
     `updates` updates of the schedule from the same start, one thread."""
     import oracle
-    pr = oracle.Params(problem=0 if problem == "mis" else 1,
-                       gamma_min=-2.0 if problem == "mis" else (-20.0 if g["n"] >= 1000 else -5.0)).as_float32()
+    pr = oracle.Params(problem={"mis": 0, "maxcut": 1, "maxclique": 2}[problem],
+                       gamma_min=-20.0 if problem == "maxcut" and g["n"] >= 1000 else
+                       (-5.0 if problem == "maxcut" else -2.0)).as_float32()
     P = oracle.init(0, g["n"], S)
     z = np.zeros_like(P)
     og = oracle.graph(W=g["dense"]) if "dense" in g else g

@@ -89,6 +89,52 @@ def random_regular(n: int, d: int, seed) -> dict:
     raise RuntimeError("pairing model did not produce a simple graph")
 
 
+def random_regular_swapped(n: int, d: int, seed) -> dict:
+    """Random simple d-regular graph for large d: one pairing (configuration model), then
+    each self-loop or repeated edge is removed by a double-edge swap with a uniformly chosen
+    other edge, (u, v), (x, y) -> (u, x), (v, y), taken only when both new edges are new and
+    not loops.  Degrees stay exactly d; the distribution is close to uniform (the swaps act
+    on O(d^2) of the n d / 2 edges), which is what the large random-regular MIS instances
+    need."""
+    if (n * d) % 2 or d >= n:
+        raise ValueError("need n*d even and d < n")
+    rng = _rng(seed)
+    stubs = rng.permutation(np.repeat(np.arange(n, dtype=np.int64), d))
+    lo = np.minimum(stubs[0::2], stubs[1::2])
+    hi = np.maximum(stubs[0::2], stubs[1::2])
+    key = lo * n + hi
+    order = np.argsort(key, kind="stable")
+    dup = np.zeros(key.size, bool)
+    dup[order[1:]] = key[order[1:]] == key[order[:-1]]
+    bad_mask = (lo == hi) | dup
+    bad = np.nonzero(bad_mask)[0].tolist()
+    if bad:
+        present = set(np.unique(key[~bad_mask]).tolist())
+        pending = set(bad)
+        for e in bad:
+            u, v = int(lo[e]), int(hi[e])
+            for _ in range(10000):
+                f = int(rng.integers(key.size))
+                if f in pending:
+                    continue
+                x, y = int(lo[f]), int(hi[f])
+                if rng.random() < 0.5:
+                    x, y = y, x
+                k1 = min(u, x) * n + max(u, x)
+                k2 = min(v, y) * n + max(v, y)
+                if u == x or v == y or k1 == k2 or k1 in present or k2 in present:
+                    continue
+                present.discard(int(key[f]))
+                present.update((k1, k2))
+                lo[e], hi[e], key[e] = min(u, x), max(u, x), k1
+                lo[f], hi[f], key[f] = min(v, y), max(v, y), k2
+                break
+            else:
+                raise RuntimeError("no valid swap found")
+            pending.discard(e)
+    return csr_from_edges(n, np.stack([lo, hi], axis=1))
+
+
 def erdos_renyi(n: int, mean_degree: float, seed) -> dict:
     """G(n, p) with p = mean_degree / (n - 1).
 

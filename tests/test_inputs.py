@@ -107,3 +107,16 @@ def test_rb_model_structure():
     assert A.sum() < (n * n - 12 * 36)
     h = qi.rb_model(12, 6, 2.6, 0.25, 3)
     assert np.array_equal(h["col"], g["col"]) and np.array_equal(h["row_ptr"], g["row_ptr"])
+
+
+def test_random_regular_swapped_is_simple_and_regular():
+    for n, d, seed in ((500, 20, 0), (2000, 40, 1), (64, 7 + 1, 2)):
+        g = qi.random_regular_swapped(n, d, seed)
+        deg = np.diff(g["row_ptr"])
+        assert deg.min() == d and deg.max() == d
+        rows = np.repeat(np.arange(n), deg)
+        assert not np.any(rows == g["col"])
+        key = rows * n + g["col"]
+        assert np.unique(key).size == key.size
+        h = qi.random_regular_swapped(n, d, seed)
+        assert np.array_equal(h["col"], g["col"])
