@@ -501,6 +501,19 @@ int qqa_autotune(qqa_ctx* c, qqa_graph_id gid, qqa_problem problem, int32_t S, i
   const int warm = 3, timed = 12;
   int best = 0;
   float best_ms = 1e30f;
+  {
+    // an instance that one workgroup runs with P in LDS keeps the default layout: that
+    // engine is faster than any streaming layout and runs only whole-row layouts
+    r.lanes_per_row = replica_shape(S).lpr;
+    StepParams probe = request_step_params(&r, g);
+    int rpg = 0, grid = 0;
+    if (problem != QQA_MAXCLIQUE && persistent_plan(probe, g.nchunks > 0, 1, &rpg, &grid) == kEngineLdsBlock) {
+      release_request_buffers(c, &r);
+      c->layout[S] = 0;
+      if (lanes_per_row) *lanes_per_row = replica_shape(S).lpr;
+      return QQA_OK;
+    }
+  }
   hipError_t e = launch_init(1, g.n, S, r.P[0], r.m, r.v, c->stream);
   // max clique: valid per-replica sums for the timed updates (their values do not matter)
   if (e == hipSuccess && r.colsum) e = launch_colsum(r.P[0], g.n, r.shape.stride, r.colsum, c->stream);

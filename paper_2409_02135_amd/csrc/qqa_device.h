@@ -95,18 +95,26 @@ __device__ __forceinline__ void store_coherent(float* p, const float4 v) {
 // Neighbour rows loaded per iteration of the coupling loop (independent loads in flight).
 constexpr int kGatherUnroll = 4;
 
-// acc += sum over edges e in [e_begin, e_end) of w_e * f(p_col(e)), in edge order, with
-// f(p) = p (MIS) or 2p - 1 (max-cut); kGatherUnroll neighbour rows are loaded per iteration.
+// acc += sum over edges e in [e_begin, e_end) of w_e * f(p_col(e)), with f(p) = p (MIS or
+// max clique) or 2p - 1 (max-cut); kGatherUnroll neighbour rows are loaded per iteration.
+// Normally every lane of the group walks all edges in edge order for its own quads.  Edge
+// split: when the row has fewer quads than the group has lanes (nq divides LPR, one quad
+// per lane), the LPR / nq lane slices take every (LPR / nq)-th edge for quad gl % nq, and a
+// butterfly over the slices adds their partial sums, so every lane ends with its quad's
+// sum (identical bits in each slice).  Both orders are fixed by the layout alone.
 template <int LPR, int QPL, bool FULL, bool COHERENT = false>
 __device__ __forceinline__ void gather_coupling(const StepParams& a, const int e_begin, const int e_end, const int gl,
                                                 const int nq, const bool maxcut, float4 (&acc)[QPL]) {
   constexpr int U = kGatherUnroll;
-  for (int e0 = e_begin; e0 < e_end; e0 += U) {
+  const int slices = (!FULL && QPL == 1 && nq < LPR && LPR % nq == 0) ? LPR / nq : 1;
+  const int lane_q = slices > 1 ? gl % nq : gl;  // the quad this lane gathers
+  const int first = e_begin + (slices > 1 ? gl / nq : 0);
+  for (int e0 = first; e0 < e_end; e0 += U * slices) {
     int j[U];
     float w[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = e0 + u;
+      const int e = e0 + u * slices;
       j[u] = e < e_end ? a.col[e] : -1;
       w[u] = e < e_end ? (a.w ? a.w[e] : 1.f) : 0.f;
     }
@@ -116,7 +124,7 @@ __device__ __forceinline__ void gather_coupling(const StepParams& a, const int e
       const float* pj = a.P_in + (size_t)j[u] * a.stride;
 #pragma unroll
       for (int k = 0; k < QPL; ++k) {
-        const int q = gl + LPR * k;
+        const int q = lane_q + LPR * k;
         if (FULL || q < nq) {
           float4 x = COHERENT ? load_coherent(pj + 4 * q) : *reinterpret_cast<const float4*>(pj + 4 * q);
           if (maxcut) {
@@ -131,6 +139,16 @@ __device__ __forceinline__ void gather_coupling(const StepParams& a, const int e
           acc[k].w = fmaf(w[u], x.w, acc[k].w);
         }
       }
+    }
+  }
+  if (!FULL && QPL == 1 && slices > 1) {
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+      if (off < nq) break;  // lanes differing in the slice bits only
+      acc[0].x += __shfl_xor(acc[0].x, off, LPR);
+      acc[0].y += __shfl_xor(acc[0].y, off, LPR);
+      acc[0].z += __shfl_xor(acc[0].z, off, LPR);
+      acc[0].w += __shfl_xor(acc[0].w, off, LPR);
     }
   }
 }

@@ -265,7 +265,11 @@ ReplicaShape replica_shape(int S, int lanes_per_row) {
   int lpr = 1;
   if (lanes_per_row > 0) {
     while (lpr < lanes_per_row && lpr < 64) lpr <<= 1;
-    while (lpr > 1 && lpr / 2 >= r.nquads) lpr >>= 1;  // no group wider than the row needs
+    // a group wider than the row's quads splits the row's edges between lane slices, which
+    // needs the quad count to divide the group; otherwise no wider than the row needs
+    const bool pow2 = (r.nquads & (r.nquads - 1)) == 0;
+    if (!pow2)
+      while (lpr > 1 && lpr / 2 >= r.nquads) lpr >>= 1;
   } else {
     while (lpr < r.nquads && lpr < 64) lpr <<= 1;
   }

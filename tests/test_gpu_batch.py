@@ -74,3 +74,24 @@ def test_batch_rejects_bad_arguments(ctx):
         ctx.solve_batch([gid, 999], [100, 100], ["mis", "mis"], [16, 16], [10, 10], [0, 1])
     assert e.value.code == q.QQA_E_ARG
     ctx.release(gid)
+
+
+def test_batch_equals_alone_with_edge_split_layouts():
+    """Layouts with more lanes than a row has quads split each row's edges between lane
+    slices; the batch runs them with the same row functions, so results stay identical."""
+    import paper_2409_02135_amd as q
+    c = q.Context(0)
+    for S, lanes in ((1, 8), (4, 16), (32, 64)):
+        c.set_replica_layout(S, lanes)
+    inst = [(qi.erdos_renyi(900, 12.0, 21), 1, 200, 5), (qi.random_regular_swapped(600, 20, 22), 4, 150, 6),
+            (qi.erdos_renyi(1500, 6.0, 23), 32, 120, 7)]
+    gids = [c.upload(g, "mis") for g, *_ in inst]
+    ids = c.solve_batch(gids, [g["n"] for g, *_ in inst], ["mis"] * 3, [i[1] for i in inst], [i[2] for i in inst],
+                        [i[3] for i in inst])
+    batched = [c.poll(i) for i in ids]
+    for (g, S, K, seed), gid, b in zip(inst, gids, batched):
+        alone = c.poll(c.solve_resident(gid, g["n"], "mis", S, K, seed))
+        assert np.array_equal(b["obj"], alone["obj"]) and np.array_equal(b["best_x"], alone["best_x"]), S
+    for gid in gids:
+        c.release(gid)
+    c.close()

@@ -344,14 +344,15 @@ def test_step_parity_split_hub_rows(orc, S):
         compare_step(f"hub/{problem}/S{S}", q, orc, g, problem, sched, S, 5, 50, 3, P, m, v)
 
 
-@pytest.mark.parametrize("S", [16, 32, 128, 256, 1024])
+@pytest.mark.parametrize("S", [1, 3, 4, 8, 16, 32, 100, 128, 256, 1024])
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
 def test_step_parity_every_replica_layout(orc, S, lanes):
-    """Every (lanes per row, quads per lane) layout the autotuner may pick."""
+    """Every (lanes per row, quads per lane) layout the autotuner may pick, including the
+    edge-split layouts (more lanes than quads: lane slices share the row's edges)."""
     q = qqa()
     nq = (S + 3) // 4
-    if nq < lanes // 2:
-        pytest.skip("layout wider than the row")
+    if nq < lanes // 2 and (nq & (nq - 1)):
+        pytest.skip("layout wider than the row (edge split needs a power-of-two quad count)")
     qpl = 1
     while lanes * qpl < nq:
         qpl *= 2
