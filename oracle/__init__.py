@@ -111,6 +111,15 @@ def lib():
         L.orc_run.argtypes = [vp, vp, i32, i32, i32, i32, u64, vp, vp, vp]
         L.orc_eval.argtypes = [i32, i64, vp, i32, vp, vp, vp, vp, vp]
         L.orc_eval.restype = C.c_int
+        L.orc_cat_sigma.argtypes = [i32, i32, i32, vp, vp, vp]
+        L.orc_cat_entropy.argtypes = [i32, i32, i32, C.c_int, vp, i32]
+        L.orc_cat_entropy.restype = d
+        L.orc_cat_energy.argtypes = [vp, vp, i32, i32, vp, d]
+        L.orc_cat_energy.restype = d
+        L.orc_cat_grad.argtypes = [vp, vp, i32, i32, vp, d, vp, vp]
+        L.orc_cat_step.argtypes = [vp, vp, i32, i32, i32, i32, u64, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_cat_run.argtypes = [vp, vp, i32, i32, i32, i32, i32, u64, vp, vp, vp]
+        L.orc_cat_eval.argtypes = [vp, i32, i32, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -277,4 +286,94 @@ def solve(params: Params, g, S: int, K: int, seed: int) -> dict:
     P, m, v = run(params, G, 0, K, K, seed, P, m, v)
     res = evaluate(params.problem, int(round(params.lam)), G, P)
     res["P"] = P
+    return res
+
+
+# ---- categorical K-state variant (graph coloring) -------------------------------------------
+# V has shape (n, K, S): V[i, k, s] is the clamped weight of colour k for variable i in replica s.
+
+def _v3(V):
+    return np.ascontiguousarray(V, dtype=np.float64)
+
+
+def cat_sigma(V):
+    """(sigma, Z): Clamp-normalised probabilities and the row sums Z (n, S)."""
+    V = _v3(V)
+    n, K, S = V.shape
+    sg = np.zeros_like(V)
+    Z = np.zeros((n, S))
+    lib().orc_cat_sigma(n, K, S, _p(V), _p(sg), _p(Z))
+    return sg, Z
+
+
+def cat_entropy(sigma, alpha: int = 4) -> np.ndarray:
+    """s_K per replica."""
+    sg = _v3(sigma)
+    n, K, S = sg.shape
+    return np.array([lib().orc_cat_entropy(n, K, S, alpha, _p(sg), s) for s in range(S)])
+
+
+def cat_energy(params: Params, g, V, gamma_value: float) -> float:
+    G = _as_graph(g)
+    pr = params._c()
+    V = _v3(V)
+    return lib().orc_cat_energy(C.byref(pr), G.ptr(), V.shape[1], V.shape[2], _p(V), gamma_value)
+
+
+def cat_grad(params: Params, g, V, gamma_value: float):
+    """(dR/dV, gabs)."""
+    G = _as_graph(g)
+    pr = params._c()
+    V = _v3(V)
+    gV, ga = np.zeros_like(V), np.zeros_like(V)
+    lib().orc_cat_grad(C.byref(pr), G.ptr(), V.shape[1], V.shape[2], _p(V), gamma_value, _p(gV), _p(ga))
+    return gV, ga
+
+
+def cat_step(params: Params, g, t: int, Kt: int, seed: int, V, m, v) -> dict:
+    G = _as_graph(g)
+    pr = params._c()
+    V_in = _v3(V)
+    n, K, S = V_in.shape
+    m2, v2 = _v3(m).copy(), _v3(v).copy()
+    out = {k: np.zeros_like(V_in) for k in ("V", "pre_clamp", "g", "gabs")}
+    lib().orc_cat_step(C.byref(pr), G.ptr(), K, S, t, Kt, seed, _p(V_in), _p(out["V"]), _p(m2), _p(v2),
+                       _p(out["pre_clamp"]), _p(out["g"]), _p(out["gabs"]))
+    out["m"], out["v"] = m2, v2
+    return out
+
+
+def cat_init(seed: int, n: int, K: int, S: int) -> np.ndarray:
+    """U(0,1) start with Philox row index i*K + k."""
+    return init(seed, n * K, S).reshape(n, K, S)
+
+
+def cat_run(params: Params, g, t0: int, t1: int, Kt: int, seed: int, V, m, v):
+    G = _as_graph(g)
+    pr = params._c()
+    V2, m2, v2 = _v3(V).copy(), _v3(m).copy(), _v3(v).copy()
+    n, K, S = V2.shape
+    lib().orc_cat_run(C.byref(pr), G.ptr(), K, S, t0, t1, Kt, seed, _p(V2), _p(m2), _p(v2))
+    return V2, m2, v2
+
+
+def cat_eval(g, V) -> dict:
+    """colors (n, S) = argmax_k V (first maximum), conflicts (S,), best replica."""
+    G = _as_graph(g)
+    V = _v3(V)
+    n, K, S = V.shape
+    colors = np.zeros((n, S), np.int32)
+    conf = np.zeros(S, np.int64)
+    best = np.zeros(1, np.int32)
+    lib().orc_cat_eval(G.ptr(), K, S, _p(V), _p(colors), _p(conf), _p(best))
+    return {"colors": colors, "conflicts": conf, "best": int(best[0])}
+
+
+def cat_solve(params: Params, g, K: int, S: int, steps: int, seed: int) -> dict:
+    G = _as_graph(g)
+    V = cat_init(seed, G.n, K, S)
+    z = np.zeros_like(V)
+    V, _, _ = cat_run(params, G, 0, steps, steps, seed, V, z, z)
+    res = cat_eval(G, V)
+    res["V"] = V
     return res

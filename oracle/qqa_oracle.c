@@ -32,6 +32,11 @@
  *                   max clique also against the MIS gradient on the complement graph
  *   orc_step        AdamW first-step closed form, projected-gradient fixed point of a
  *                   regular graph (closed-form root), Langevin noise moments
+ *   orc_cat_*       categorical K-state variant (graph coloring): K = 2 reduction of the
+ *                   entropy to the binary alpha-entropy (appendix proposition), entropy
+ *                   extremes, energy at one-hot points = conflict count (brute force),
+ *                   central finite differences through the Clamp-normalisation, brute-force
+ *                   minimum conflicts and textbook chromatic numbers
  *   orc_philox*     parity unpinned against the published known-answer vectors (not
  *                   available here); pinned by bijectivity and by uniform/normal
  *                   goodness-of-fit statistics only
@@ -470,4 +475,200 @@ int orc_eval(int32_t problem, int64_t lambda, const orc_graph *g, int32_t S, con
     }
     *best = bi;
     return 0;
+}
+
+
+/* =====================================================================================
+ * Categorical K-state QQA (appendix "Generalization to discrete optimization problems" and
+ * "Transformation for general discrete variables"), for graph coloring.
+ *
+ * State per replica s: V in [0,1]^{N x K}, stored V[((i*K + k) * S) + s] (the (i, k) pairs
+ * as rows, replicas contiguous).  Probabilities sigma_ik = V_ik / Z_i, Z_i = sum_k V_ik
+ * (Clamp-normalisation; V is kept clamped, as p is in the binary method); a row with
+ * Z_i = 0 reads as uniform, sigma_ik = 1/K, with Z_i taken as 1 in the chain rule.
+ *
+ *   l(sigma)   = sum_{(i,j) in E, i<j} sum_k sigma_ik sigma_jk     (expected conflicts)
+ *   s_K(sigma) = sum_i { 1 - c sum_k (K sigma_ik - 1)^alpha },  c = 1 / ((K-1)((K-1)^(alpha-1) + 1))
+ *   R          = sum_s [ l + gamma s_K ] - S alpha_c sum_{i,k} STD_s[sigma_ik]
+ * g = dR/dsigma per element, and dR/dV_ik = (g_ik - sum_k' sigma_ik' g_ik') / Z_i.
+ * The update is the binary method's: AdamW on V with that gradient, + sqrt(2 eta T) xi,
+ * Clamp to [0,1].  Noise and start use the Philox stream with row index i*K + k.
+ * Rounding: x_i = argmax_k V_ik (first maximum); cost = #{(i,j) in E : x_i = x_j}.
+ * ===================================================================================== */
+
+static size_t cat_at(int32_t K, int32_t S, int32_t i, int32_t k, int32_t s) {
+    return ((size_t)i * K + k) * S + s;
+}
+
+/* sigma from V, and Z (n*S, with 0 kept as 0) */
+void orc_cat_sigma(int32_t n, int32_t K, int32_t S, const double *V, double *sigma, double *Z) {
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t s = 0; s < S; ++s) {
+            double z = 0.0;
+            for (int32_t k = 0; k < K; ++k) z += V[cat_at(K, S, i, k, s)];
+            if (Z) Z[(size_t)i * S + s] = z;
+            for (int32_t k = 0; k < K; ++k)
+                sigma[cat_at(K, S, i, k, s)] = z > 0.0 ? V[cat_at(K, S, i, k, s)] / z : 1.0 / (double)K;
+        }
+}
+
+static double cat_entropy_coef(int32_t K, int alpha) {
+    return 1.0 / ((double)(K - 1) * (ipow((double)(K - 1), alpha - 1) + 1.0));
+}
+
+/* s_K of one replica's sigma */
+double orc_cat_entropy(int32_t n, int32_t K, int32_t S, int alpha, const double *sigma, int32_t s) {
+    const double c = cat_entropy_coef(K, alpha);
+    double acc = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double t = 0.0;
+        for (int32_t k = 0; k < K; ++k) t += ipow((double)K * sigma[cat_at(K, S, i, k, s)] - 1.0, alpha);
+        acc += 1.0 - c * t;
+    }
+    return acc;
+}
+
+/* R of the categorical model (graph coloring objective) */
+double orc_cat_energy(const orc_params *pr, const orc_graph *g, int32_t K, int32_t S, const double *V, double gamma) {
+    const int32_t n = g->n;
+    const size_t NKS = (size_t)n * K * S;
+    double *sg = (double *)malloc(NKS * sizeof(double));
+    orc_cat_sigma(n, K, S, V, sg, NULL);
+    double R = 0.0;
+    for (int32_t s = 0; s < S; ++s) {
+        double l = 0.0;
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e) {
+                const int32_t j = g->col[e];
+                if (j <= i) continue;
+                for (int32_t k = 0; k < K; ++k) l += sg[cat_at(K, S, i, k, s)] * sg[cat_at(K, S, j, k, s)];
+            }
+        R += l + gamma * orc_cat_entropy(n, K, S, pr->entropy_alpha, sg, s);
+    }
+    double stdsum = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = 0; k < K; ++k) stdsum += replica_std(S, sg + cat_at(K, S, i, k, 0));
+    free(sg);
+    return R - (double)S * pr->comm_alpha * stdsum;
+}
+
+/* dR/dV (n*K*S); optional gabs = magnitude of every term of dR/dV before cancellation:
+   (a_ik + sum_k' sigma_ik' a_ik') / Z with a_ik = sum_j |sigma_jk| + |entropy term|
+   + alpha_c (|sigma| + |mu|) / std. */
+void orc_cat_grad(const orc_params *pr, const orc_graph *g, int32_t K, int32_t S, const double *V, double gamma,
+                  double *gV, double *gabs) {
+    const int32_t n = g->n;
+    const size_t NKS = (size_t)n * K * S;
+    double *sg = (double *)malloc(NKS * sizeof(double));
+    double *Z = (double *)malloc((size_t)n * S * sizeof(double));
+    double *G = (double *)malloc(NKS * sizeof(double));
+    double *A = (double *)malloc(NKS * sizeof(double));
+    orc_cat_sigma(n, K, S, V, sg, Z);
+    const double c = cat_entropy_coef(K, pr->entropy_alpha);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = 0; k < K; ++k) {
+            const double *row = sg + cat_at(K, S, i, k, 0);
+            double mu = 0.0;
+            for (int32_t s = 0; s < S; ++s) mu += row[s];
+            mu /= (double)S;
+            const double sd = replica_std(S, row);
+            for (int32_t s = 0; s < S; ++s) {
+                double cpl = 0.0, cabs = 0.0;
+                for (int64_t e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e) {
+                    const double x = sg[cat_at(K, S, g->col[e], k, s)];
+                    cpl += x;
+                    cabs += fabs(x);
+                }
+                const double z = (double)K * row[s] - 1.0;
+                const double ent = -gamma * c * (double)pr->entropy_alpha * (double)K * ipow(z, pr->entropy_alpha - 1);
+                const double com = sd > 0.0 ? -pr->comm_alpha * (row[s] - mu) / sd : 0.0;
+                G[cat_at(K, S, i, k, s)] = cpl + ent + com;
+                A[cat_at(K, S, i, k, s)] = cabs + fabs(ent) + (sd > 0.0 ? pr->comm_alpha * (fabs(row[s]) + fabs(mu)) / sd : 0.0);
+            }
+        }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t s = 0; s < S; ++s) {
+            double d = 0.0, da = 0.0;
+            for (int32_t k = 0; k < K; ++k) {
+                d += sg[cat_at(K, S, i, k, s)] * G[cat_at(K, S, i, k, s)];
+                da += sg[cat_at(K, S, i, k, s)] * A[cat_at(K, S, i, k, s)];
+            }
+            const double z = Z[(size_t)i * S + s] > 0.0 ? Z[(size_t)i * S + s] : 1.0;
+            for (int32_t k = 0; k < K; ++k) {
+                gV[cat_at(K, S, i, k, s)] = (G[cat_at(K, S, i, k, s)] - d) / z;
+                if (gabs) gabs[cat_at(K, S, i, k, s)] = (A[cat_at(K, S, i, k, s)] + da) / z;
+            }
+        }
+    free(sg); free(Z); free(G); free(A);
+}
+
+/* One categorical update t of a Kt-update schedule (same step rule as orc_step). */
+void orc_cat_step(const orc_params *pr, const orc_graph *g, int32_t K, int32_t S, int32_t t, int32_t Kt,
+                  uint64_t seed, const double *V_in, double *V_out, double *m, double *v,
+                  double *pre_clamp, double *gsum, double *gabs) {
+    const int32_t n = g->n;
+    const size_t NKS = (size_t)n * K * S;
+    const double gamma = orc_gamma(pr, t, Kt);
+    const uint32_t kk = (uint32_t)t + 1u;
+    double *gV = (double *)malloc(NKS * sizeof(double));
+    double *xi = (double *)malloc(NKS * sizeof(double));
+    orc_cat_grad(pr, g, K, S, V_in, gamma, gV, gabs);
+    orc_noise(seed, n * K, S, kk, xi); /* row index i*K + k */
+    const double bc1 = 1.0 - pow(pr->beta1, (double)kk);
+    const double bc2 = 1.0 - pow(pr->beta2, (double)kk);
+    const double noise_scale = sqrt(2.0 * pr->lr * pr->temperature);
+    for (size_t e = 0; e < NKS; ++e) {
+        const double grad = gV[e];
+        double p = V_in[e];
+        if (pr->rule == ORC_ADAMW) {
+            p = p - pr->lr * pr->weight_decay * p;
+            m[e] = pr->beta1 * m[e] + (1.0 - pr->beta1) * grad;
+            v[e] = pr->beta2 * v[e] + (1.0 - pr->beta2) * grad * grad;
+            p = p - pr->lr * (m[e] / bc1) / (sqrt(v[e] / bc2) + pr->adam_eps);
+        } else {
+            p = p - pr->lr * grad;
+        }
+        p = p + noise_scale * xi[e];
+        if (pre_clamp) pre_clamp[e] = p;
+        if (gsum) gsum[e] = grad;
+        V_out[e] = p < 0.0 ? 0.0 : (p > 1.0 ? 1.0 : p);
+    }
+    free(gV); free(xi);
+}
+
+void orc_cat_run(const orc_params *pr, const orc_graph *g, int32_t K, int32_t S, int32_t t0, int32_t t1, int32_t Kt,
+                 uint64_t seed, double *V, double *m, double *v) {
+    const size_t NKS = (size_t)g->n * K * S;
+    double *tmp = (double *)malloc(NKS * sizeof(double));
+    for (int32_t t = t0; t < t1; ++t) {
+        orc_cat_step(pr, g, K, S, t, Kt, seed, V, tmp, m, v, NULL, NULL, NULL);
+        memcpy(V, tmp, NKS * sizeof(double));
+    }
+    free(tmp);
+}
+
+/* Rounding and exact cost: colors[n*S] (x_i per replica), conflicts[S]; best = replica with
+   the fewest conflicts (lowest index among ties). */
+void orc_cat_eval(const orc_graph *g, int32_t K, int32_t S, const double *V, int32_t *colors, int64_t *conflicts,
+                  int32_t *best) {
+    const int32_t n = g->n;
+    for (int32_t s = 0; s < S; ++s) {
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t arg = 0;
+            for (int32_t k = 1; k < K; ++k)
+                if (V[cat_at(K, S, i, k, s)] > V[cat_at(K, S, i, arg, s)]) arg = k;
+            colors[(size_t)i * S + s] = arg;
+        }
+        int64_t c = 0;
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e) {
+                const int32_t j = g->col[e];
+                if (j > i && colors[(size_t)i * S + s] == colors[(size_t)j * S + s]) ++c;
+            }
+        conflicts[s] = c;
+    }
+    int32_t b = 0;
+    for (int32_t s = 1; s < S; ++s)
+        if (conflicts[s] < conflicts[b]) b = s;
+    *best = b;
 }

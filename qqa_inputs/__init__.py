@@ -13,7 +13,8 @@ datasets themselves are not available):
     family;
   * complete graphs with Gaussian couplings quantised to a 2^-16 grid (dense max-cut);
   * Model RB constraint-satisfaction instances with a planted solution, as the
-    compatibility graphs whose cliques are consistent partial assignments (max clique).
+    compatibility graphs whose cliques are consistent partial assignments (max clique);
+  * queens graphs (graph coloring).
 
 A graph is returned as a dict ``{"n", "row_ptr" (int64, n+1), "col" (int32, nnz),
 "weight" (float32, nnz, or None)}`` holding a symmetric CSR without self-loops or
@@ -306,6 +307,21 @@ def rb_model(n_vars: int, domain: int, r: float, p: float, seed) -> dict:
     g = csr_from_edges(N, np.stack([iu, ju], axis=1))
     g["planted_clique"] = np.arange(n_vars, dtype=np.int64) * d + planted
     return g
+
+
+def queens(rows: int, cols: int | None = None) -> dict:
+    """Queens graph of a rows x cols board (the coloring benchmark family): one node per
+    square, node id r * cols + c, adjacent when the squares share a row, a column or a
+    diagonal, i.e. a queen on one attacks the other."""
+    cols = rows if cols is None else cols
+    edges = []
+    for a in range(rows * cols):
+        ra, ca = divmod(a, cols)
+        for b in range(a + 1, rows * cols):
+            rb, cb = divmod(b, cols)
+            if ra == rb or ca == cb or abs(ra - rb) == abs(ca - cb):
+                edges.append((a, b))
+    return csr_from_edges(rows * cols, np.array(edges, dtype=np.int64).reshape(-1, 2))
 
 
 def cycle(n: int) -> dict:
