@@ -56,8 +56,14 @@ extern "C" {
  *   QQA_MAXCLIQUE  -sum_i p_i + lambda/2 (1^T p (1^T p - 1) - p^T A p); its gradient
  *                  needs the per-replica sum 1^T p over all variables in every update.
  *                  Max clique runs on the streaming engine of plain solves only (not in
- *                  batches or the server). */
-typedef enum { QQA_MIS = 0, QQA_MAXCUT = 1, QQA_MAXCLIQUE = 2 } qqa_problem;
+ *                  batches or the server).
+ *   QQA_COLORING   categorical K-state variant (appendix "Generalization to discrete
+ *                  optimization problems"): per replica V in [0,1]^(N x K), sigma_ik =
+ *                  V_ik / sum_k' V_ik' (uniform for an all-zero row), objective
+ *                  sum_{(i,j) in E} sum_k sigma_ik sigma_jk (expected conflicts), the
+ *                  categorical alpha-entropy s_K, the replica STD per (variable, colour).
+ *                  Solved with qqa_solve_coloring (it needs K); streaming engine only. */
+typedef enum { QQA_MIS = 0, QQA_MAXCUT = 1, QQA_MAXCLIQUE = 2, QQA_COLORING = 3 } qqa_problem;
 typedef enum { QQA_STEP_ADAMW = 0, QQA_STEP_LANGEVIN = 1 } qqa_step_rule;
 
 /* Hyper-parameters of one solve.  qqa_schedule_default() fills the paper's values:
@@ -115,8 +121,10 @@ int qqa_graph_validate(const qqa_graph *g, qqa_problem problem, char *why, size_
  * wanted) and qqa_poll fills them when it returns QQA_OK.
  * Objectives are exact integers: MIS l = -size + lambda * violations (selected adjacent
  * pairs); max-cut l = -cut with cut counted in units of 2^-16; max clique
- * l = -size + lambda * violations (selected pairs that are not adjacent).  best_replica
- * minimises (violations > 0, l, replica index) lexicographically. */
+ * l = -size + lambda * violations (selected pairs that are not adjacent); coloring
+ * l = size_or_cut = violations = edges whose ends share a colour (x_i = argmax_k V_ik, first
+ * maximum), best_x = the colours (< K).  best_replica minimises (violations > 0, l,
+ * replica index) lexicographically. */
 typedef struct {
     int32_t best_replica;
     int32_t feasible;            /* best replica has no violated constraint */
@@ -171,6 +179,17 @@ int qqa_solve(qqa_ctx *c, const qqa_graph *g, qqa_problem problem, const qqa_sch
               int32_t S, int32_t steps, uint64_t seed, qqa_req *out_id);
 int qqa_solve_resident(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, const qqa_schedule *sched,
                        int32_t S, int32_t steps, uint64_t seed, qqa_req *out_id);
+
+/* Graph coloring with `colors` colours (2..255) on a CSR graph: the categorical update
+ * (QQA_COLORING) for `steps` updates, then the colouring of every replica and its conflict
+ * count; qqa_poll returns it as for the other problems.  Device state is colors x the
+ * binary problems'.  qqa_solve_coloring_resident takes a graph uploaded with QQA_COLORING.
+ * QQA_E_ARG for colors outside [2, 255]; qqa_solve / qqa_solve_resident refuse
+ * QQA_COLORING. */
+int qqa_solve_coloring(qqa_ctx *c, const qqa_graph *g, int32_t colors, const qqa_schedule *sched,
+                       int32_t S, int32_t steps, uint64_t seed, qqa_req *out_id);
+int qqa_solve_coloring_resident(qqa_ctx *c, qqa_graph_id g, int32_t colors, const qqa_schedule *sched,
+                                int32_t S, int32_t steps, uint64_t seed, qqa_req *out_id);
 
 /* Submit `count` independent solves packed into one ragged batch: every update of the
  * batch is a single launch covering all instances (each at its own update index), the
@@ -289,6 +308,21 @@ int qqa_dev_step(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule
 int qqa_dev_run(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule *sched, int32_t S,
                 int32_t t0, int32_t t1, int32_t K, uint64_t seed, float *P0, float *P1, float *m, float *v,
                 int32_t engine, int32_t lanes_per_row, void *stream);
+
+/* One graph-coloring update t of a K-update schedule on caller buffers: V_in, V_out, m, v
+ * are device arrays of n * colors rows x stride floats (row i*colors + k holds colour k of
+ * variable i for every replica); V_out must not alias V_in; m, v updated in place.  The
+ * Clamp-normalised sigma of V_in is formed internally (stream-ordered scratch). */
+int qqa_dev_color_step(const qqa_dev_graph *g, int32_t colors, const qqa_schedule *sched, int32_t S,
+                       int32_t t, int32_t K, uint64_t seed, const float *V_in, float *V_out, float *m,
+                       float *v, int32_t lanes_per_row, void *stream);
+
+/* Colouring of every replica and its exact cost: X (device, n x stride bytes) receives
+ * x_i = argmax_k V_ik (first maximum) for replica s at X[i*stride + s]; conflicts[S]
+ * (device int64) the edges whose ends share a colour; best[1] (device int32) the replica
+ * with the fewest (lowest index among ties). */
+int qqa_dev_color_eval(const qqa_dev_graph *g, int32_t colors, int32_t S, const float *V, uint8_t *X,
+                       int64_t *conflicts, int32_t *best, void *stream);
 
 /* Round x = [P > 1/2] and evaluate every replica exactly.  Outputs are device arrays:
  * size_or_cut[S], viol[S], obj[S] (int64) and best[1] (int32). */

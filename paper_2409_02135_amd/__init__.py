@@ -20,13 +20,13 @@ LIB_PATH = os.path.join(_PKG, "libqqa.so")
 QQA_OK, QQA_PENDING = 0, 1
 QQA_E_ARG, QQA_E_GRAPH, QQA_E_NOMEM, QQA_E_ADMISSION = -1, -2, -3, -4
 QQA_E_DEVICE, QQA_E_UNKNOWN_REQ, QQA_E_CANCELLED = -5, -6, -7
-QQA_MIS, QQA_MAXCUT, QQA_MAXCLIQUE = 0, 1, 2
+QQA_MIS, QQA_MAXCUT, QQA_MAXCLIQUE, QQA_COLORING = 0, 1, 2, 3
 QQA_STEP_ADAMW, QQA_STEP_LANGEVIN = 0, 1
 QQA_ENGINE_AUTO, QQA_ENGINE_STREAM, QQA_ENGINE_PERSISTENT, QQA_ENGINE_LDS_BLOCK, QQA_ENGINE_BATCH = -1, 0, 1, 2, 3
 ENGINES = {"auto": -1, "stream": 0, "persistent": 1, "lds_block": 2, "batch": 3}
 
-PROBLEMS = {"mis": QQA_MIS, "maxcut": QQA_MAXCUT, "maxclique": QQA_MAXCLIQUE,
-            QQA_MIS: QQA_MIS, QQA_MAXCUT: QQA_MAXCUT, QQA_MAXCLIQUE: QQA_MAXCLIQUE}
+PROBLEMS = {"mis": QQA_MIS, "maxcut": QQA_MAXCUT, "maxclique": QQA_MAXCLIQUE, "coloring": QQA_COLORING,
+            QQA_MIS: QQA_MIS, QQA_MAXCUT: QQA_MAXCUT, QQA_MAXCLIQUE: QQA_MAXCLIQUE, QQA_COLORING: QQA_COLORING}
 
 
 class QQAError(RuntimeError):
@@ -101,6 +101,10 @@ def lib():
             "qqa_dev_eval": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
             "qqa_dev_dense_coupling": (C.c_int, [vp, vp, vp, i32, i32, i32, vp]),
             "qqa_dev_replica_sums": (C.c_int, [vp, i32, i32, vp, vp]),
+            "qqa_solve_coloring": (C.c_int, [vp, vp, i32, vp, i32, i32, u64, vp]),
+            "qqa_solve_coloring_resident": (C.c_int, [vp, i64, i32, vp, i32, i32, u64, vp]),
+            "qqa_dev_color_step": (C.c_int, [vp, i32, vp, i32, i32, i32, u64, vp, vp, vp, vp, i32, vp]),
+            "qqa_dev_color_eval": (C.c_int, [vp, i32, i32, vp, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -215,6 +219,18 @@ def qqa_dev_dense_coupling(W, P, C, n, S, problem, stream=None):
     return _dev_check(lib().qqa_dev_dense_coupling(_ptr(W), _ptr(P), _ptr(C), n, S, PROBLEMS[problem], _stream(stream)))
 
 
+def qqa_dev_color_step(g: DevGraph, colors, sched: qqa_schedule | None, S, t, K, seed, V_in, V_out, m, v,
+                       lanes_per_row=0, stream=None):
+    return _dev_check(lib().qqa_dev_color_step(C.byref(g.struct), colors, None if sched is None else C.byref(sched),
+                                               S, t, K, seed, _ptr(V_in), _ptr(V_out), _ptr(m), _ptr(v),
+                                               lanes_per_row, _stream(stream)))
+
+
+def qqa_dev_color_eval(g: DevGraph, colors, S, V, X, conflicts, best, stream=None):
+    return _dev_check(lib().qqa_dev_color_eval(C.byref(g.struct), colors, S, _ptr(V), _ptr(X), _ptr(conflicts),
+                                               _ptr(best), _stream(stream)))
+
+
 def qqa_dev_eval(g: DevGraph, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best, stream=None):
     return _dev_check(lib().qqa_dev_eval(C.byref(g.struct), PROBLEMS[problem], penalty_lambda, S, _ptr(P),
                                          _ptr(size_or_cut), _ptr(viol), _ptr(obj), _ptr(best), _stream(stream)))
@@ -303,6 +319,19 @@ class Context:
         self._check(lib().qqa_solve(self._c, C.byref(st), PROBLEMS[problem],
                                     None if sched is None else C.byref(sched), S, steps, seed, C.byref(rid)))
         return self._track(rid.value, st.n, S)
+
+    def solve_coloring(self, g: dict, colors: int, S, steps, seed, sched=None) -> int:
+        st, keep = host_graph(g)
+        rid = C.c_int64()
+        self._check(lib().qqa_solve_coloring(self._c, C.byref(st), colors, None if sched is None else C.byref(sched),
+                                             S, steps, seed, C.byref(rid)))
+        return self._track(rid.value, int(g["n"]), S)
+
+    def solve_coloring_resident(self, gid: int, n: int, colors: int, S, steps, seed, sched=None) -> int:
+        rid = C.c_int64()
+        self._check(lib().qqa_solve_coloring_resident(self._c, gid, colors, None if sched is None else C.byref(sched),
+                                                      S, steps, seed, C.byref(rid)))
+        return self._track(rid.value, n, S)
 
     def solve_resident(self, gid: int, n: int, problem, S, steps, seed, sched=None) -> int:
         rid = C.c_int64()

@@ -1,0 +1,296 @@
+// Categorical K-state QQA for graph coloring (the paper's generalisation to discrete
+// variables): state V in [0,1]^(N x K) per replica, sigma = Clamp-normalised rows
+// (sigma_ik = V_ik / Z_i, Z_i = sum_k V_ik; an all-zero row reads as uniform 1/K, with
+// Z_i taken as 1 in the chain rule), expected-conflict objective
+//   l(sigma) = sum_{(i,j) in E, i<j} sum_k sigma_ik sigma_jk,
+// categorical alpha-entropy s_K = sum_i {1 - c sum_k (K sigma_ik - 1)^alpha},
+// c = 1 / ((K-1)((K-1)^(alpha-1) + 1)), and the replica STD term per (variable, colour).
+//
+// Layout: the (variable i, colour k) pairs are rows r = i*K + k of the usual replica layout
+// (row-major, replicas contiguous, stride = S rounded up to 4), for V, m, v, sigma and the
+// objective gradient G = dR/dsigma.  One update is two launches:
+//   cat_grad_kernel    per row (i, k): sum_j A_ij sigma_jk (gathered through the graph's CSR
+//                      with the row pitch K * stride), + the entropy and STD terms -> G
+//   cat_update_kernel  per variable i: dR/dV_ik = (G_ik - sum_k' sigma_ik' G_ik') / Z_i,
+//                      AdamW, sqrt(2 eta T) xi (Philox row i*K + k), clamp -> V; then sigma
+//                      of the new V, in place.
+// Rounding: x_i = argmax_k V_ik (first maximum); cost = edges whose ends share a colour.
+#include "qqa_device.h"
+
+namespace qqa {
+
+// sigma from V for variable i, quad q (all K colours); padding replicas 0
+__global__ __launch_bounds__(kBlock) void cat_sigma_kernel(const float* __restrict__ V, float* __restrict__ sig,
+                                                           int n, int K, int stride, int S) {
+  const int nq = stride >> 2;
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (long long)n * nq) return;
+  const int i = (int)(t / nq), q = (int)(t % nq);
+  float4 Z = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int k = 0; k < K; ++k) {
+    const float4 x = *reinterpret_cast<const float4*>(V + ((size_t)i * K + k) * stride + 4 * q);
+    Z.x += x.x;
+    Z.y += x.y;
+    Z.z += x.z;
+    Z.w += x.w;
+  }
+  const float u = 1.f / (float)K;
+  for (int k = 0; k < K; ++k) {
+    const size_t off = ((size_t)i * K + k) * stride + 4 * q;
+    const float4 x = *reinterpret_cast<const float4*>(V + off);
+    float4 o;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float z = comp(Z, c);
+      set_comp(o, c, 4 * q + c < S ? (z > 0.f ? comp(x, c) / z : u) : 0.f);
+    }
+    *reinterpret_cast<float4*>(sig + off) = o;
+  }
+}
+
+// G_ik = sum_j A_ij sigma_jk + ce (K sigma_ik - 1)^(alpha-1) - alpha_c (sigma_ik - mu_ik) / std_ik
+// a.P_in = sigma, a.n = N * K rows, a.ce = -gamma c alpha K
+template <int LPR, int QPL, bool FULL>
+__global__ __launch_bounds__(kBlock) void cat_grad_kernel(StepParams a, int K, float* __restrict__ G) {
+  int r = (int)(((long long)blockIdx.x * kBlock + threadIdx.x) / LPR);
+  if (LPR == 64) r = __builtin_amdgcn_readfirstlane(r);
+  if (r >= a.n) return;  // whole lane groups leave together
+  const int gl = threadIdx.x & (LPR - 1);
+  const int i = r / K, k = r % K;
+  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
+  // neighbours' sigma of colour k: rows j*K + k, i.e. pitch K*stride from sigma + k*stride
+  StepParams b = a;
+  b.P_in = a.P_in + (size_t)k * a.stride;
+  b.stride = K * a.stride;
+  b.w = nullptr;
+  float4 acc[QPL];
+#pragma unroll
+  for (int q = 0; q < QPL; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  gather_coupling<LPR, QPL, FULL>(b, a.row_ptr[i], a.row_ptr[i + 1], gl, nq, false, acc);
+  float4 p[QPL];
+  float sum = 0.f;
+#pragma unroll
+  for (int kk = 0; kk < QPL; ++kk) {
+    const int q = gl + LPR * kk;
+    p[kk] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (FULL || q < nq) p[kk] = *reinterpret_cast<const float4*>(a.P_in + (size_t)r * a.stride + 4 * q);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (FULL || 4 * q + c < a.S) sum += comp(p[kk], c);
+  }
+  sum = group_sum<LPR>(sum);
+  const float mu = sum * a.inv_S;
+  float sq = 0.f;
+#pragma unroll
+  for (int kk = 0; kk < QPL; ++kk) {
+    const int q = gl + LPR * kk;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (FULL || 4 * q + c < a.S) {
+        const float d = comp(p[kk], c) - mu;
+        sq = fmaf(d, d, sq);
+      }
+  }
+  sq = group_sum<LPR>(sq);
+  const float sd = __builtin_amdgcn_sqrtf(sq * a.inv_S);
+  const float cg = sd > 0.f ? -a.comm_alpha * __builtin_amdgcn_rcpf(sd) : 0.f;
+  const float Kf = (float)K;
+#pragma unroll
+  for (int kk = 0; kk < QPL; ++kk) {
+    const int q = gl + LPR * kk;
+    if (!FULL && q >= nq) continue;
+    float4 o;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float s = comp(p[kk], c);
+      const float g = comp(acc[kk], c) + a.ce * ipow_odd(fmaf(Kf, s, -1.f), a.alpha_e - 1) + cg * (s - mu);
+      set_comp(o, c, (FULL || 4 * q + c < a.S) ? g : 0.f);
+    }
+    *reinterpret_cast<float4*>(G + (size_t)r * a.stride + 4 * q) = o;
+  }
+}
+
+// per variable i and replica quad q: the chain rule through the normalisation, the step, and
+// sigma of the new state.  a.P_in = V_in, a.P_out = V_out, a.m / a.v, a.n = N variables.
+__global__ __launch_bounds__(kBlock) void cat_update_kernel(StepParams a, int K, const float* __restrict__ G,
+                                                            float* __restrict__ sig) {
+  const int nq = a.stride >> 2;
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (long long)a.n * nq) return;
+  const int i = (int)(t / nq), q = (int)(t % nq);
+  const bool adam = a.rule == kADAMW;
+  float4 Z = make_float4(0.f, 0.f, 0.f, 0.f), D = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int k = 0; k < K; ++k) {
+    const size_t off = ((size_t)i * K + k) * a.stride + 4 * q;
+    const float4 x = *reinterpret_cast<const float4*>(a.P_in + off);
+    const float4 s = *reinterpret_cast<const float4*>(sig + off);
+    const float4 g = *reinterpret_cast<const float4*>(G + off);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      set_comp(Z, c, comp(Z, c) + comp(x, c));
+      set_comp(D, c, fmaf(comp(s, c), comp(g, c), comp(D, c)));
+    }
+  }
+  float4 Zo = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int k = 0; k < K; ++k) {
+    const size_t off = ((size_t)i * K + k) * a.stride + 4 * q;
+    const float4 x = *reinterpret_cast<const float4*>(a.P_in + off);
+    const float4 g = *reinterpret_cast<const float4*>(G + off);
+    float4 mm = make_float4(0.f, 0.f, 0.f, 0.f), vv = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (adam) {
+      mm = *reinterpret_cast<const float4*>(a.m + off);
+      vv = *reinterpret_cast<const float4*>(a.v + off);
+    }
+    const float4 xi =
+        normals4(philox4x32_10((uint32_t)(i * K + k), (uint32_t)q, a.k, kStreamNoise, a.key0, a.key1));
+    float4 po, mo, vo;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float z = comp(Z, c);
+      const float grad = (comp(g, c) - comp(D, c)) / (z > 0.f ? z : 1.f);
+      const float pc = comp(x, c);
+      float pn, mn = 0.f, vn = 0.f;
+      if (adam) {
+        mn = fmaf(a.beta1, comp(mm, c), a.omb1 * grad);
+        vn = fmaf(a.beta2, comp(vv, c), a.omb2 * (grad * grad));
+        const float den = __builtin_amdgcn_sqrtf(vn * a.inv_bc2) + a.eps;
+        pn = pc * a.wd_factor - a.lr * (mn * a.inv_bc1) * __builtin_amdgcn_rcpf(den);
+      } else {
+        pn = pc - a.lr * grad;
+      }
+      pn = fmaf(a.noise_scale, comp(xi, c), pn);
+      pn = fminf(fmaxf(pn, 0.f), 1.f);
+      const bool valid = 4 * q + c < a.S;
+      set_comp(po, c, valid ? pn : 0.f);
+      set_comp(mo, c, valid ? mn : 0.f);
+      set_comp(vo, c, valid ? vn : 0.f);
+      set_comp(Zo, c, comp(Zo, c) + (valid ? pn : 0.f));
+    }
+    *reinterpret_cast<float4*>(a.P_out + off) = po;
+    if (adam) {
+      *reinterpret_cast<float4*>(a.m + off) = mo;
+      *reinterpret_cast<float4*>(a.v + off) = vo;
+    }
+  }
+  // sigma of the new state (this thread wrote exactly these elements above)
+  const float u = 1.f / (float)K;
+  for (int k = 0; k < K; ++k) {
+    const size_t off = ((size_t)i * K + k) * a.stride + 4 * q;
+    const float4 x = *reinterpret_cast<const float4*>(a.P_out + off);
+    float4 o;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float z = comp(Zo, c);
+      set_comp(o, c, 4 * q + c < a.S ? (z > 0.f ? comp(x, c) / z : u) : 0.f);
+    }
+    *reinterpret_cast<float4*>(sig + off) = o;
+  }
+}
+
+// colours x_i = argmax_k V_ik (first maximum) per replica
+__global__ __launch_bounds__(kBlock) void cat_color_kernel(const float* __restrict__ V, uint8_t* __restrict__ X,
+                                                           int n, int K, int stride, int S) {
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (long long)n * S) return;
+  const int i = (int)(t / S), s = (int)(t % S);
+  int arg = 0;
+  float best = V[((size_t)i * K) * stride + s];
+  for (int k = 1; k < K; ++k) {
+    const float x = V[((size_t)i * K + k) * stride + s];
+    if (x > best) {
+      best = x;
+      arg = k;
+    }
+  }
+  X[(size_t)i * stride + s] = (uint8_t)arg;
+}
+
+// conflicts per replica: edges (i, j), j > i, whose ends share a colour; integer counts are
+// folded in LDS, then one atomic per replica per block (order-free)
+__global__ __launch_bounds__(kBlock) void cat_conflict_kernel(const int32_t* __restrict__ row_ptr,
+                                                              const int32_t* __restrict__ col,
+                                                              const uint8_t* __restrict__ X, int n, int stride, int S,
+                                                              unsigned long long* __restrict__ acc) {
+  extern __shared__ unsigned long long cat_sh[];  // [stride]
+  for (int s = threadIdx.x; s < stride; s += kBlock) cat_sh[s] = 0ull;
+  __syncthreads();
+  // block b covers rows b, b + gridDim.x, ...; threads over replicas
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    for (int s = threadIdx.x; s < S; s += kBlock) {
+      const uint8_t xi = X[(size_t)i * stride + s];
+      unsigned long long c = 0;
+      for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        const int j = col[e];
+        if (j > i && X[(size_t)j * stride + s] == xi) ++c;
+      }
+      if (c) atomicAdd(&cat_sh[s], c);
+    }
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < S; s += kBlock)
+    if (cat_sh[s]) atomicAdd(&acc[s], cat_sh[s]);
+}
+
+// the best replica's colouring
+__global__ __launch_bounds__(kBlock) void cat_extract_kernel(const uint8_t* __restrict__ X, int n, int stride,
+                                                             const int32_t* __restrict__ best, uint8_t* __restrict__ x) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = X[(size_t)i * stride + best[0]];
+}
+
+static unsigned blocks_for(long long threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+hipError_t launch_cat_sigma(const float* V, float* sig, int n, int K, int stride, int S, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cat_sigma_kernel, dim3(blocks_for((long long)n * (stride >> 2))), dim3(kBlock), 0, st, V, sig, n,
+                     K, stride, S);
+  return hipGetLastError();
+}
+
+template <int LPR, int QPL>
+static void launch_cat_grad_t(const StepParams& p, int K, float* G, hipStream_t st) {
+  const dim3 grid(blocks_for((long long)p.n * LPR)), block(kBlock);
+  if (p.S == 4 * LPR * QPL)
+    hipLaunchKernelGGL((cat_grad_kernel<LPR, QPL, true>), grid, block, 0, st, p, K, G);
+  else
+    hipLaunchKernelGGL((cat_grad_kernel<LPR, QPL, false>), grid, block, 0, st, p, K, G);
+}
+
+hipError_t launch_cat_grad(const StepParams& p, int K, float* G, hipStream_t st) {
+  if (p.n == 0) return hipSuccess;
+  const ReplicaShape r = replica_shape(p.S, p.lanes_per_row);
+#define X(L, Q)                        \
+  if (r.lpr == L && r.qpl == Q) {      \
+    launch_cat_grad_t<L, Q>(p, K, G, st); \
+    return hipGetLastError();          \
+  }
+  QQA_FOR_EACH_LAYOUT(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cat_update(const StepParams& p, int K, const float* G, float* sig, hipStream_t st) {
+  if (p.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cat_update_kernel, dim3(blocks_for((long long)p.n * (p.stride >> 2))), dim3(kBlock), 0, st, p, K,
+                     G, sig);
+  return hipGetLastError();
+}
+
+hipError_t launch_cat_eval(const int32_t* row_ptr, const int32_t* col, const float* V, uint8_t* X, int n, int K,
+                           int stride, int S, unsigned long long* acc, hipStream_t st) {
+  hipError_t e = launch_fill_u64(acc, 2 * (size_t)stride, st);
+  if (e != hipSuccess || n == 0) return e;
+  hipLaunchKernelGGL(cat_color_kernel, dim3(blocks_for((long long)n * S)), dim3(kBlock), 0, st, V, X, n, K, stride, S);
+  const int blocks = std::max(1, std::min(n, 1024));
+  hipLaunchKernelGGL(cat_conflict_kernel, dim3(blocks), dim3(kBlock), (size_t)stride * sizeof(unsigned long long), st,
+                     row_ptr, col, X, n, stride, S, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_cat_extract(const uint8_t* X, int n, int stride, const int32_t* best, uint8_t* x, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cat_extract_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, st, X, n, stride, best, x);
+  return hipGetLastError();
+}
+
+}  // namespace qqa

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -113,7 +114,7 @@ void graph_unref(qqa_ctx* c, int64_t gid) {
 }
 
 int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks) {
-  const size_t state = (size_t)r->n * r->shape.stride * sizeof(float);
+  const size_t state = (size_t)r->n * std::max(1, r->colors) * r->shape.stride * sizeof(float);
   const bool adam = r->sched.rule == QQA_STEP_ADAMW;
   hipError_t e = hipSuccess;
   auto get = [&](void** p, size_t b) {
@@ -129,6 +130,11 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
   r->hub_bytes = (size_t)nchunks * r->shape.stride * sizeof(float);
   if (nchunks) get((void**)&r->hub_partial, r->hub_bytes);
   if (r->problem == QQA_MAXCLIQUE) get((void**)&r->colsum, (size_t)r->shape.stride * sizeof(unsigned long long));
+  if (r->colors > 0) {
+    get((void**)&r->cat_sigma, state);
+    get((void**)&r->cat_grad, state);
+    get((void**)&r->cat_colors, (size_t)r->n * r->shape.stride);
+  }
   r->coupling_bytes = 0;
   auto git = c->graphs.find(r->graph);
   if (git != c->graphs.end() && git->second.dense) {
@@ -161,7 +167,7 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
     r->owner.reset();
     return;
   }
-  const size_t state = (size_t)r->n * r->shape.stride * sizeof(float);
+  const size_t state = (size_t)r->n * std::max(1, r->colors) * r->shape.stride * sizeof(float);
   c->dpool.put(r->P[0], state);
   c->dpool.put(r->P[1], state);
   c->dpool.put(r->m, state);
@@ -173,6 +179,11 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
   r->coupling = nullptr;
   if (r->colsum) c->dpool.put(r->colsum, (size_t)r->shape.stride * sizeof(unsigned long long));
   r->colsum = nullptr;
+  if (r->cat_sigma) c->dpool.put(r->cat_sigma, state);
+  if (r->cat_grad) c->dpool.put(r->cat_grad, state);
+  if (r->cat_colors) c->dpool.put(r->cat_colors, (size_t)r->n * r->shape.stride);
+  r->cat_sigma = r->cat_grad = nullptr;
+  r->cat_colors = nullptr;
   c->dpool.put(r->out_dev, r->out_size);
   c->hpool.put(r->out_host, r->out_size);
   c->dpool.put(r->table_dev, r->table_bytes);
@@ -366,6 +377,119 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   return QQA_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// graph coloring (categorical K-state variant): init, sigma, K x (gradient, update), finish
+// ---------------------------------------------------------------------------------------
+static double gamma_at(const qqa_schedule& s, int t, int K) {
+  if (K <= 1) return s.gamma_min;
+  return (double)s.gamma_min + ((double)s.gamma_max - (double)s.gamma_min) * (double)t / (double)(K - 1);
+}
+
+static int submit_coloring(qqa_ctx* c, int64_t gid, bool temp, int32_t colors, const qqa_schedule* sched, int32_t S,
+                           int32_t steps, uint64_t seed, qqa_req* out_id) {
+  auto git = c->graphs.find(gid);
+  if (git == c->graphs.end()) return set_err(c, QQA_E_ARG, "unknown graph id");
+  DevGraph& g = git->second;
+  if (g.problem != QQA_COLORING) return set_err(c, QQA_E_ARG, "graph was uploaded for another problem type");
+  auto r = std::make_unique<Request>();
+  r->id = c->next_req++;
+  r->graph = gid;
+  r->temp_graph = temp;
+  r->problem = QQA_COLORING;
+  r->colors = colors;
+  if (sched) r->sched = *sched; else qqa_schedule_default(&r->sched, QQA_COLORING, g.n);
+  std::string why;
+  if (!schedule_valid(r->sched, &why)) return set_err(c, QQA_E_ARG, why);
+  r->S = S;
+  r->K = steps;
+  r->seed = seed;
+  r->n = g.n;
+  r->shape = replica_shape(S);
+  r->lanes_per_row = c->layout_for(S);
+  r->engine = kEngineStream;
+  const size_t stride = r->shape.stride;
+  const size_t state = (size_t)g.n * colors * stride * sizeof(float);
+  r->footprint = state * (r->sched.rule == QQA_STEP_ADAMW ? 6 : 4) + (size_t)g.n * stride + out_bytes(g.n, S) +
+                 2 * stride * sizeof(unsigned long long) + 4096;
+  if (r->footprint + g.bytes > c->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the HBM budget");
+  if (c->in_use + r->footprint > c->budget)
+    return set_err(c, QQA_E_NOMEM, "HBM budget held by earlier requests; poll them first");
+  int rc = alloc_request_buffers(c, r.get(), &c->err, 0);
+  if (rc) return rc;
+  c->in_use += r->footprint;
+  g.refs++;
+  r->t_submit = Clock::now();
+
+  // the colour-k gradient uses the categorical entropy's coefficient c = 1/((K-1)((K-1)^(a-1)+1))
+  const int a_e = r->sched.entropy_alpha;
+  const double cK = 1.0 / ((double)(colors - 1) * (std::pow((double)(colors - 1), a_e - 1) + 1.0));
+  StepParams base = request_step_params(r.get(), g);
+  base.w = nullptr;
+  hipError_t e = hipEventRecord(r->ev[0], c->stream);
+  if (e == hipSuccess) e = launch_init(seed, g.n * colors, S, r->P[0], r->m, r->v, c->stream);
+  if (e == hipSuccess) e = launch_cat_sigma(r->P[0], r->cat_sigma, g.n, colors, (int)stride, S, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(r->ev[1], c->stream);
+  const int every = r->probe_every;
+  for (int t = 0; t < steps && e == hipSuccess; ++t) {
+    StepParams pg = base;
+    pg.n = g.n * colors;
+    pg.P_in = r->cat_sigma;
+    pg.ce = (float)(-gamma_at(r->sched, t, steps) * cK * (double)a_e * (double)colors);
+    StepParams pu = base;
+    pu.P_in = r->P[t & 1];
+    pu.P_out = r->P[(t + 1) & 1];
+    fill_step_scalars(pu, r->sched, t, steps);
+    const size_t pi = 2 * (size_t)(t / every);
+    const bool probe = t % every == every / 2 && pi + 1 < r->probe.size();
+    if (probe) e = hipEventRecord(r->probe[pi], c->stream);
+    if (e == hipSuccess) e = launch_cat_grad(pg, colors, r->cat_grad, c->stream);
+    if (probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
+    if (e == hipSuccess) e = launch_cat_update(pu, colors, r->cat_grad, r->cat_sigma, c->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(r->ev[2], c->stream);
+  if (e == hipSuccess) {
+    int64_t *a, *b, *o;
+    int32_t* best;
+    uint8_t* x;
+    out_views(r->out_dev, r->n, r->S, &a, &b, &o, &best, &x);
+    e = launch_cat_eval(g.row_ptr, g.col, r->P[steps & 1], r->cat_colors, g.n, colors, (int)stride, S, r->acc,
+                        c->stream);
+    EvalParams ep{};
+    ep.n = g.n;
+    ep.S = S;
+    ep.stride = (int)stride;
+    ep.problem = QQA_COLORING;
+    ep.acc = r->acc;
+    ep.size_or_cut = a;
+    ep.viol = b;
+    ep.obj = o;
+    ep.best = best;
+    if (e == hipSuccess) e = launch_finalize(ep, c->stream);
+    if (e == hipSuccess) e = launch_cat_extract(r->cat_colors, g.n, (int)stride, best, x, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->out_host, r->out_dev, r->out_size, hipMemcpyDeviceToHost, c->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(r->ev[3], c->stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(c->stream);
+    release_request_buffers(c, r.get());
+    c->in_use -= r->footprint;
+    graph_unref(c, gid);
+    return set_err(c, QQA_E_DEVICE, std::string("enqueue: ") + hipGetErrorString(e));
+  }
+  r->state = Request::kRunning;
+  *out_id = r->id;
+  c->reqs.emplace(r->id, std::move(r));
+  return QQA_OK;
+}
+
+static int check_coloring_args(qqa_ctx* c, int32_t colors, int32_t S, int32_t steps, qqa_req* out_id) {
+  if (!out_id) return set_err(c, QQA_E_ARG, "out_id is NULL");
+  if (colors < 2 || colors > 255) return set_err(c, QQA_E_ARG, "colours must be in [2, 255]");
+  if (S <= 0 || S > kMaxReplicas) return set_err(c, QQA_E_ARG, "S must be in [1, 4096]");
+  if (steps <= 0) return set_err(c, QQA_E_ARG, "steps must be positive");
+  return QQA_OK;
+}
+
 extern "C" {
 
 int qqa_create(qqa_ctx** out, int device, size_t hbm_budget_bytes, void* hip_stream) {
@@ -435,6 +559,7 @@ int qqa_graph_release(qqa_ctx* c, qqa_graph_id id) {
 static int check_solve_args(qqa_ctx* c, qqa_problem problem, int32_t S, int32_t steps, qqa_req* out_id) {
   if (!out_id) return set_err(c, QQA_E_ARG, "out_id is NULL");
   if (!known_problem(problem)) return set_err(c, QQA_E_ARG, "unknown problem");
+  if (problem == QQA_COLORING) return set_err(c, QQA_E_ARG, "graph coloring needs the colour count: qqa_solve_coloring");
   if (S <= 0 || S > kMaxReplicas) return set_err(c, QQA_E_ARG, "S must be in [1, 4096]");
   if (steps <= 0) return set_err(c, QQA_E_ARG, "steps must be positive");
   return QQA_OK;
@@ -452,6 +577,29 @@ int qqa_solve(qqa_ctx* c, const qqa_graph* g, qqa_problem problem, const qqa_sch
   rc = submit_plain(c, gid, true, problem, sched, S, steps, seed, out_id);
   qqa_graph_release(c, gid);  // freed when the request is collected
   return rc;
+}
+
+int qqa_solve_coloring(qqa_ctx* c, const qqa_graph* g, int32_t colors, const qqa_schedule* sched, int32_t S,
+                       int32_t steps, uint64_t seed, qqa_req* out_id) {
+  if (!c) return QQA_E_ARG;
+  if (!g) return set_err(c, QQA_E_ARG, "graph is NULL");
+  int rc = check_coloring_args(c, colors, S, steps, out_id);
+  if (rc) return rc;
+  qqa_graph_id gid;
+  rc = qqa_graph_upload(c, g, QQA_COLORING, &gid);
+  if (rc) return rc;
+  rc = submit_coloring(c, gid, true, colors, sched, S, steps, seed, out_id);
+  qqa_graph_release(c, gid);  // freed when the request is collected
+  return rc;
+}
+
+int qqa_solve_coloring_resident(qqa_ctx* c, qqa_graph_id g, int32_t colors, const qqa_schedule* sched, int32_t S,
+                                int32_t steps, uint64_t seed, qqa_req* out_id) {
+  if (!c) return QQA_E_ARG;
+  int rc = check_coloring_args(c, colors, S, steps, out_id);
+  if (rc) return rc;
+  (void)hipSetDevice(c->device);
+  return submit_coloring(c, g, false, colors, sched, S, steps, seed, out_id);
 }
 
 int qqa_solve_resident(qqa_ctx* c, qqa_graph_id g, qqa_problem problem, const qqa_schedule* sched, int32_t S,

@@ -62,6 +62,12 @@ struct Request {
   size_t hub_bytes = 0;
   float* coupling = nullptr;     // dense graphs: n x stride coupling product
   unsigned long long* colsum = nullptr;  // max clique: per-replica sums of P (2^-32 fixed point)
+  // graph coloring: colours K; state rows are n * K; sigma and G (n * K x stride), colours
+  // of every replica (n x stride bytes)
+  int colors = 0;
+  float* cat_sigma = nullptr;
+  float* cat_grad = nullptr;
+  uint8_t* cat_colors = nullptr;
   size_t coupling_bytes = 0;
   char* out_dev = nullptr;
   char* out_host = nullptr;

@@ -9,7 +9,7 @@
 
 namespace qqa {
 
-enum : int32_t { kMIS = 0, kMAXCUT = 1, kMAXCLIQUE = 2 };
+enum : int32_t { kMIS = 0, kMAXCUT = 1, kMAXCLIQUE = 2, kCOLORING = 3 };
 enum : int32_t { kADAMW = 0, kLANGEVIN = 1 };
 enum : uint32_t { kStreamInit = 0, kStreamNoise = 1 };
 
@@ -151,10 +151,29 @@ hipError_t launch_persistent(const PersistParams& pp, int engine, int rows_per_g
 
 // Dense coupling product C = W f(P) on the matrix cores (W symmetric n x n, P and C
 // n x stride; f(p) = 2p - 1 for max-cut, p for MIS).
+// every (lanes per row, quads per lane) pair the kernels are built for
+#define QQA_FOR_EACH_LAYOUT(X)                                                                   \
+  X(1, 1) X(1, 2) X(1, 4) X(1, 8) X(2, 1) X(2, 2) X(2, 4) X(2, 8) X(4, 1) X(4, 2) X(4, 4) X(4, 8)   \
+  X(8, 1) X(8, 2) X(8, 4) X(8, 8) X(16, 1) X(16, 2) X(16, 4) X(16, 8) X(32, 1) X(32, 2) X(32, 4)  \
+  X(32, 8) X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
+
 // Per-replica sums T[s] = sum_i P[i][s] (max clique), accumulated exactly in 2^-32 fixed
 // point: each p is rounded once to a multiple of 2^-32, and the integer sums are independent
 // of the order of addition.  T (stride entries) is cleared by the launcher.
 hipError_t launch_colsum(const float* P, int n, int stride, unsigned long long* T, hipStream_t st);
+
+// Graph coloring (categorical K-state variant): rows i*K + k of the replica layout.
+// sigma = Clamp-normalised rows of V; G = dR/dsigma over N*K rows (p.n = N*K, p.P_in = sigma,
+// p.ce = -gamma c alpha K); the update over N variables (p.n = N, p.P_in / P_out = V) also
+// rewrites sigma for the new V; evaluation writes colours X (n x stride bytes) and the
+// conflict count per replica into acc[0..S).
+hipError_t launch_cat_sigma(const float* V, float* sig, int n, int K, int stride, int S, hipStream_t st);
+hipError_t launch_cat_grad(const StepParams& p, int K, float* G, hipStream_t st);
+hipError_t launch_cat_update(const StepParams& p, int K, const float* G, float* sig, hipStream_t st);
+hipError_t launch_cat_eval(const int32_t* row_ptr, const int32_t* col, const float* V, uint8_t* X, int n, int K,
+                           int stride, int S, unsigned long long* acc, hipStream_t st);
+hipError_t launch_cat_extract(const uint8_t* X, int n, int stride, const int32_t* best, uint8_t* x, hipStream_t st);
+hipError_t launch_finalize(const EvalParams& p, hipStream_t st);
 
 hipError_t launch_dense_coupling(const float* W, const float* P, float* C, int n, int stride, int problem,
                                  hipStream_t st);

@@ -164,6 +164,11 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(EvalParams a) {
 // that are not adjacent, size (size - 1) / 2 - count; max-cut has none.
 __device__ __forceinline__ void derive(const EvalParams& a, int s, long long* A, long long* B, long long* o) {
   *A = (long long)a.acc[s];
+  if (a.problem == kCOLORING) {  // cost = violations = edges whose ends share a colour
+    *B = *A;
+    *o = *A;
+    return;
+  }
   const long long cnt = (long long)a.acc[a.stride + s];
   *B = a.problem == kMAXCLIQUE ? *A * (*A - 1) / 2 - cnt : cnt;
   *o = a.problem == kMAXCUT ? -*A : -*A + a.lambda * *B;
@@ -280,11 +285,6 @@ ReplicaShape replica_shape(int S, int lanes_per_row) {
   return r;
 }
 
-// every (lanes per row, quads per lane) pair the kernels are built for
-#define QQA_FOR_EACH_LAYOUT(X)                                                                   \
-  X(1, 1) X(1, 2) X(1, 4) X(1, 8) X(2, 1) X(2, 2) X(2, 4) X(2, 8) X(4, 1) X(4, 2) X(4, 4) X(4, 8)   \
-  X(8, 1) X(8, 2) X(8, 4) X(8, 8) X(16, 1) X(16, 2) X(16, 4) X(16, 8) X(32, 1) X(32, 2) X(32, 4)  \
-  X(32, 8) X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
 
 bool layout_supported(int S, int lanes_per_row) {
   const ReplicaShape r = replica_shape(S, lanes_per_row);
@@ -417,6 +417,10 @@ hipError_t launch_eval(const EvalParams& p, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  return launch_finalize(p, st);
+}
+
+hipError_t launch_finalize(const EvalParams& p, hipStream_t st) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlock), 0, st, p);
   return hipGetLastError();
 }

@@ -106,6 +106,7 @@ static bool on_grid(float w) {
 
 int validate_graph(const qqa_graph& g, int problem, std::string* why) {
   if (g.n <= 0) return fail(why, QQA_E_GRAPH, "graph needs n > 0");
+  if (g.dense && problem == QQA_COLORING) return fail(why, QQA_E_GRAPH, "graph coloring takes a CSR graph");
   if (g.dense) {
     const int n = g.n;
     if ((int64_t)n * n > (int64_t)1 << 31) return fail(why, QQA_E_GRAPH, "dense graph too large");
@@ -516,6 +517,91 @@ int qqa_dev_dense_coupling(const float* W, const float* P, float* C, int32_t n, 
     return fail(&g_dev_error, QQA_E_ARG, "bad dense coupling arguments");
   if (!known_problem(problem)) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
   DEV_CHECK(launch_dense_coupling(W, P, C, n, replica_shape(S).stride, problem, (hipStream_t)stream));
+  return QQA_OK;
+}
+
+int qqa_dev_color_step(const qqa_dev_graph* g, int32_t colors, const qqa_schedule* sched, int32_t S, int32_t t,
+                       int32_t K, uint64_t seed, const float* V_in, float* V_out, float* m, float* v,
+                       int32_t lanes_per_row, void* stream) {
+  int rc = dev_graph_check(g);
+  if (rc) return rc;
+  if (g->dense) return fail(&g_dev_error, QQA_E_ARG, "graph coloring takes a CSR graph");
+  if (colors < 2 || colors > 255) return fail(&g_dev_error, QQA_E_ARG, "colours must be in [2, 255]");
+  if (S <= 0 || S > kMaxReplicas) return fail(&g_dev_error, QQA_E_ARG, "S must be in [1, 4096]");
+  if (K <= 0 || t < 0 || t >= K) return fail(&g_dev_error, QQA_E_ARG, "need 0 <= t < K");
+  qqa_schedule s;
+  if (sched) s = *sched; else qqa_schedule_default(&s, QQA_COLORING, g->n);
+  std::string why;
+  if (!schedule_valid(s, &why)) return fail(&g_dev_error, QQA_E_ARG, why);
+  if (g->n > 0 && (!V_in || !V_out || V_in == V_out)) return fail(&g_dev_error, QQA_E_ARG, "need distinct V_in, V_out");
+  if (s.rule == QQA_STEP_ADAMW && g->n > 0 && (!m || !v)) return fail(&g_dev_error, QQA_E_ARG, "AdamW needs m and v");
+  if (lanes_per_row < 0 || lanes_per_row > 64 || !layout_supported(S, lanes_per_row))
+    return fail(&g_dev_error, QQA_E_ARG, "unsupported replica layout");
+  if (g->n == 0) return QQA_OK;
+  hipStream_t st = (hipStream_t)stream;
+  StepParams base{};
+  base.row_ptr = g->row_ptr;
+  base.col = g->col_idx;
+  base.m = m;
+  base.v = v;
+  base.n = g->n;
+  fill_static_scalars(base, s, QQA_COLORING, S, seed);
+  base.lanes_per_row = lanes_per_row;
+  const size_t state = (size_t)g->n * colors * base.stride * sizeof(float);
+  float *sig = nullptr, *G = nullptr;
+  DEV_CHECK(hipMallocAsync((void**)&sig, state, st));
+  DEV_CHECK(hipMallocAsync((void**)&G, state, st));
+  const double gamma = K <= 1 ? s.gamma_min
+                              : (double)s.gamma_min + ((double)s.gamma_max - (double)s.gamma_min) * t / (double)(K - 1);
+  const double cK = 1.0 / ((double)(colors - 1) * (std::pow((double)(colors - 1), s.entropy_alpha - 1) + 1.0));
+  StepParams pg = base;
+  pg.n = g->n * colors;
+  pg.P_in = sig;
+  pg.ce = (float)(-gamma * cK * (double)s.entropy_alpha * (double)colors);
+  StepParams pu = base;
+  pu.P_in = V_in;
+  pu.P_out = V_out;
+  fill_step_scalars(pu, s, t, K);
+  hipError_t e = launch_cat_sigma(V_in, sig, g->n, colors, base.stride, S, st);
+  if (e == hipSuccess) e = launch_cat_grad(pg, colors, G, st);
+  if (e == hipSuccess) e = launch_cat_update(pu, colors, G, sig, st);
+  (void)hipFreeAsync(sig, st);
+  (void)hipFreeAsync(G, st);
+  DEV_CHECK(e);
+  return QQA_OK;
+}
+
+int qqa_dev_color_eval(const qqa_dev_graph* g, int32_t colors, int32_t S, const float* V, uint8_t* X,
+                       int64_t* conflicts, int32_t* best, void* stream) {
+  if (!g || g->n < 0) return fail(&g_dev_error, QQA_E_ARG, "graph is NULL or n < 0");
+  if (g->dense) return fail(&g_dev_error, QQA_E_ARG, "graph coloring takes a CSR graph");
+  if (g->n > 0 && !g->row_ptr) return fail(&g_dev_error, QQA_E_ARG, "row_ptr missing");
+  if (colors < 2 || colors > 255) return fail(&g_dev_error, QQA_E_ARG, "colours must be in [2, 255]");
+  if (S <= 0 || S > kMaxReplicas) return fail(&g_dev_error, QQA_E_ARG, "S must be in [1, 4096]");
+  if (!X || !conflicts || !best || (g->n > 0 && !V)) return fail(&g_dev_error, QQA_E_ARG, "output missing");
+  hipStream_t st = (hipStream_t)stream;
+  const ReplicaShape r = replica_shape(S);
+  unsigned long long* acc = nullptr;
+  int64_t* tmp = nullptr;
+  DEV_CHECK(hipMallocAsync((void**)&acc, 2 * (size_t)r.stride * sizeof(unsigned long long), st));
+  DEV_CHECK(hipMallocAsync((void**)&tmp, 2 * (size_t)S * sizeof(int64_t), st));
+  hipError_t e = launch_cat_eval(g->row_ptr, g->col_idx, V, X, g->n, colors, r.stride, S, acc, st);
+  EvalParams ep{};
+  ep.n = g->n;
+  ep.S = S;
+  ep.stride = r.stride;
+  ep.problem = QQA_COLORING;
+  ep.acc = acc;
+  ep.size_or_cut = conflicts;
+  ep.viol = tmp;
+  ep.obj = tmp + S;
+  ep.best = best;
+  if (e == hipSuccess) e = launch_finalize(ep, st);
+  hipError_t e2 = hipFreeAsync(acc, st);
+  hipError_t e3 = hipFreeAsync(tmp, st);
+  DEV_CHECK(e);
+  DEV_CHECK(e2);
+  DEV_CHECK(e3);
   return QQA_OK;
 }
 

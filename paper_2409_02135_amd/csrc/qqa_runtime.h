@@ -20,7 +20,7 @@ void fill_step_scalars(StepParams& p, const qqa_schedule& s, int t, int K);
 void fill_static_scalars(StepParams& p, const qqa_schedule& s, int problem, int S, uint64_t seed);
 int validate_graph(const qqa_graph& g, int problem, std::string* why);
 inline bool known_problem(int problem) {
-  return problem == QQA_MIS || problem == QQA_MAXCUT || problem == QQA_MAXCLIQUE;
+  return problem == QQA_MIS || problem == QQA_MAXCUT || problem == QQA_MAXCLIQUE || problem == QQA_COLORING;
 }
 // Split plan for rows with more than kHubDegree neighbours (see qqa_internal.h).
 void build_hub_plan(const int32_t* row_ptr, int n, std::vector<HubChunk>* chunks, std::vector<int32_t>* hub_first);

@@ -155,7 +155,7 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     I.gid = graphs[i];
     I.problem = problems[i];
     if (!known_problem(I.problem)) return set_err(c, QQA_E_ARG, "unknown problem");
-    if (I.problem == QQA_MAXCLIQUE) return set_err(c, QQA_E_ARG, "max clique is solved one at a time");
+    if (I.problem == QQA_MAXCLIQUE || I.problem == QQA_COLORING) return set_err(c, QQA_E_ARG, "max clique and coloring are solved one at a time");
     if (I.g->problem != I.problem) return set_err(c, QQA_E_ARG, "graph was uploaded for another problem type");
     if (I.g->dense) return set_err(c, QQA_E_ARG, "dense graphs are solved one at a time");
     I.S = S[i];

@@ -457,7 +457,7 @@ int qqa_serve_submit(qqa_ctx* c, const qqa_graph* g, qqa_problem problem, const 
   if (!sv) return set_err(c, QQA_E_ARG, "server not started");
   if (!g || !out_id) return set_err(c, QQA_E_ARG, "NULL argument");
   if (!known_problem(problem)) return set_err(c, QQA_E_ARG, "unknown problem");
-  if (problem == QQA_MAXCLIQUE) return set_err(c, QQA_E_ARG, "max clique is solved one at a time");
+  if (problem == QQA_MAXCLIQUE || problem == QQA_COLORING) return set_err(c, QQA_E_ARG, "max clique and coloring are solved one at a time");
   if (S <= 0 || S > kMaxReplicas || steps <= 0) return set_err(c, QQA_E_ARG, "need 1 <= S <= 4096 and steps > 0");
   if (g->dense) return set_err(c, QQA_E_ARG, "dense graphs are solved one at a time");
   std::string why;

@@ -22,6 +22,8 @@ WORKLOADS = {
     "ba2000_m4_pm1_maxcut_S128_K1000": ("ba", 2000, 4, 0, "maxcut", 128, 1000),
     "dense256_gauss_maxcut_S32_K500": ("dense", 256, 0, 0, "maxcut", 32, 500),
     "rb20x12_maxclique_S32_K1000": ("rb", 20, 12, 2.6, 0.25, 0, "maxclique", 32, 1000),
+    # graph coloring: ("queens", board size, colours, graph seed, "coloring", S, steps)
+    "queen7_colors7_S32_K1000": ("queens", 7, 7, 0, "coloring", 32, 1000),
 }
 PROBLEM_CODES = {"mis": 0, "maxcut": 1, "maxclique": 2}
 SEEDS = list(range(10))
@@ -48,6 +50,13 @@ def one(args):
     import oracle
     import qqa_inputs as qi
     rec = WORKLOADS[name]
+    if rec[0] == "queens":
+        _, board, colors, _, _, S, K = rec
+        r = oracle.cat_solve(oracle.Params().as_float32(), qi.queens(board), colors, S, K, seed)
+        c = r["conflicts"]
+        return name, seed, {"best_objective": int(c.min()), "best_feasible": bool(c.min() == 0),
+                            "mean_objective": float(np.mean(c)), "feasible_fraction": float(np.mean(c == 0)),
+                            "mean_size_or_cut": float(np.mean(c))}
     if rec[0] == "rb":
         _, nv, dom, r, p, gseed, problem, S, K = rec
         g = qi.rb_model(nv, dom, r, p, gseed)
