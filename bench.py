@@ -39,6 +39,10 @@ WORKLOADS = {
     # max clique on a Model RB instance (20 variables x 12 values, planted clique of 20),
     # the paper's 1,000 parallel runs
     "maxclique_rb20x12_S1000_K3000": ("rb", 240, (20, 12, 2.6, 0.25), "maxclique", 1000, 3000),
+    # graph coloring (categorical K-state QQA): the largest queens graph of the paper's
+    # coloring table with 13 colours, 1,000 parallel runs; and an ER graph sized to load the GPU
+    "coloring_queen13_K13_S1000_K3000": ("queens", 169, 13, "coloring", 1000, 3000),
+    "coloring_er_n100000_d10_K8_S32_K1000": ("er_color", 100000, (10.0, 8), "coloring", 32, 1000),
 }
 DEFAULT = "mis_er_n20000_d5_S256_K3000"
 
@@ -49,6 +53,10 @@ def make_graph(family, n, d, problem, seed=0):
         return {"n": n, "dense": qi.dense_gaussian(n, seed)}
     if family == "rb":
         return qi.rb_model(*d, seed)
+    if family == "queens":
+        return qi.queens(int(round(n ** 0.5)))
+    if family == "er_color":
+        return qi.erdos_renyi(n, d[0], seed)
     if family == "rrg_swap":
         return qi.random_regular_swapped(n, int(d), seed)
     if family == "er":
@@ -235,6 +243,21 @@ def cpu_baseline(g, problem, S, K, updates=20):
             "seconds": round(dt, 3)}
 
 
+def cpu_baseline_coloring(g, colors, S, K, updates=20):
+    """The FP64 oracle's categorical update on a bounded sample: the first `updates`
+    updates of the same instance from the same start, one thread."""
+    import oracle
+    pr = oracle.Params().as_float32()
+    V = oracle.cat_init(0, g["n"], colors, S)
+    z = np.zeros_like(V)
+    t0 = time.perf_counter()
+    oracle.cat_run(pr, g, 0, updates, K, 0, V, z, z)
+    dt = time.perf_counter() - t0
+    return {"value": g["n"] * S * updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{updates} of {K} updates of the same instance from the same start ({colors} colours), "
+                      "single-threaded FP64 C", "seconds": round(dt, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,9 +297,14 @@ def main():
         K = args.updates
     g = make_graph(family, n, d, problem)
     dense = family == "dense"
+    coloring = problem == "coloring"
+    colors = (d if family == "queens" else d[1]) if coloring else 0
     nnz = n * (n - 1) if dense else int(g["col"].size)
     ctx = q.Context(0)
-    if dense:
+    if coloring:
+        gid = ctx.upload(g, problem)
+        lanes = max(args.lanes, 0)  # the tuner times the binary update kernel
+    elif dense:
         gid = ctx.upload(None, problem, dense=g["dense"])
         lanes = max(args.lanes, 0)  # the layout only concerns the fused update here
     else:
@@ -286,12 +314,17 @@ def main():
     print(f"# workload {args.workload}: n={n} nnz={nnz} S={S} updates={K} lanes_per_row={lanes}",
           file=sys.stderr, flush=True)
 
+    def submit(seed):
+        if coloring:
+            return ctx.solve_coloring_resident(gid, n, colors, S, K, seed)
+        return ctx.solve_resident(gid, n, problem, S, K, seed)
+
     for w in range(args.warmup):
-        ctx.poll(ctx.solve_resident(gid, n, problem, S, K, 1000 + w), want_x=False)
+        ctx.poll(submit(1000 + w), want_x=False)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ids = [ctx.solve_resident(gid, n, problem, S, K, s) for s in range(args.steps)]
+    ids = [submit(s) for s in range(args.steps)]
     results = [ctx.poll(i, want_x=False) for i in ids]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -314,6 +347,15 @@ def main():
                     "avg_launch_us": mm_us, "algorithmic_flops_per_launch": flops,
                     "update_loop_us_per_update": step_us,
                     "uniform_random_state_us": dense_coupling_us(q, g["dense"], n, S, problem)}
+    elif coloring:
+        # one update is two launches (gradient over N*K rows, then the per-variable update);
+        # algorithmic bytes: V, m, v read and written for every colour, plus the CSR
+        abytes = 24 * n * colors * S + 4 * (n + 1) + 4 * nnz
+        achieved = abytes / (step_us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "kernel": "cat_grad_kernel + cat_update_kernel", "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes,
+                    "sampled_grad_kernel_us": float(np.mean([r["kernel_us"] for r in results]))}
     else:
         abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
         achieved = abytes / (step_us * 1e-6) / 1e9
@@ -337,6 +379,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "problem": problem, "graph": family, "n": n, "nnz": nnz,
+                   **({"colors": colors} if coloring else {}),
                    "degree_param": d, "S": S, "updates_per_solve": K, "graph_seed": 0,
                    "lanes_per_row": lanes, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(dev_ms, 50)), "p99": float(np.percentile(dev_ms, 99)),
@@ -360,7 +403,8 @@ def main():
                                      "and BA (m=4) graphs, n log-uniform in [1e3,1e5], S in {32,128}, "
                                      "1000-3000 updates", "at_200_per_s": spec, "at_70pct_capacity": low}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, problem, S, K, updates=2 if dense else 20)
+        out["cpu_baseline"] = (cpu_baseline_coloring(g, colors, S, K, updates=5 if n > 10000 else 20) if coloring else
+                               cpu_baseline(g, problem, S, K, updates=2 if dense else 20))
     print(json.dumps(out), flush=True)
 
 
