@@ -104,6 +104,7 @@ def dense_coupling_us(q, W, n, S, problem, launches=20):
 
 DEVICE_SOURCES = ["qqa_device.h", "qqa_kernels.hip"]
 DENSE_SOURCES = ["qqa_dense.hip"]
+SLICE_SOURCES = ["qqa_device.h", "qqa_slice.hip"]
 
 
 def source_hash(sources):
@@ -273,6 +274,8 @@ def main():
                     help="replica layout (lanes per row); -1 = autotune before timing, 0 = default")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB elementwise copy three times (reference for HBM byte counters)")
+    ap.add_argument("--engine", default="auto", choices=["auto", "stream", "sliced", "persistent", "lds_block"],
+                    help="engine policy of the solving context")
     ap.add_argument("--updates", type=int, default=0,
                     help="override the updates per solve (short runs under hardware counters)")
     args = ap.parse_args()
@@ -311,6 +314,7 @@ def main():
         gid = ctx.upload(g, problem)
         lanes = ctx.autotune(gid, problem, S) if args.lanes < 0 else args.lanes
     ctx.set_replica_layout(S, lanes)
+    ctx.set_engine(args.engine)
     print(f"# workload {args.workload}: n={n} nnz={nnz} S={S} updates={K} lanes_per_row={lanes}",
           file=sys.stderr, flush=True)
 
@@ -359,9 +363,13 @@ def main():
     else:
         abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
         achieved = abytes / (step_us * 1e-6) / 1e9
-        roofline = {"bound": "hbm", "kernel": "step_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        sliced = results[0]["engine"] == "sliced"
+        # the sliced engine's update is two launches (row statistics, then the slices)
+        roofline = {"bound": "hbm", "kernel": "row_stats_kernel + slice_step_kernel" if sliced else "step_kernel",
+                    "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": traffic_from_profiles("step_kernel_traffic.json", DEVICE_SOURCES),
+                    "traffic": (traffic_from_profiles("slice_step_traffic.json", SLICE_SOURCES) if sliced else
+                                traffic_from_profiles("step_kernel_traffic.json", DEVICE_SOURCES)),
                     "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes,
                     "sampled_launch_us": float(np.mean([r["kernel_us"] for r in results]))}
 
@@ -381,7 +389,7 @@ def main():
         "config": {"workload": args.workload, "problem": problem, "graph": family, "n": n, "nnz": nnz,
                    **({"colors": colors} if coloring else {}),
                    "degree_param": d, "S": S, "updates_per_solve": K, "graph_seed": 0,
-                   "lanes_per_row": lanes, "parallelism": "single GPU"},
+                   "lanes_per_row": lanes, "engine": results[0]["engine"], "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(dev_ms, 50)), "p99": float(np.percentile(dev_ms, 99)),
                        "basis": "device time per solve (events on the solver stream)"},
         "roofline": roofline,

@@ -140,24 +140,31 @@ typedef struct {
     double step_loop_ms;         /* device time of the K-update loop */
     double latency_ms;           /* submit -> result ready (host clock) */
     int32_t engine;              /* qqa_engine that ran the update loop */
-    double kernel_us;            /* streaming engine: mean device duration of the dominant
-                                  * launch of an update (the coupling product for dense
-                                  * graphs, the update kernel otherwise), timed with events on
-                                  * up to 32 launches spread over the schedule; -1 otherwise */
+    double kernel_us;            /* streaming engines: mean device duration of the dominant
+                                  * launches of an update (the coupling product for dense
+                                  * graphs; the statistics and slice launches together for
+                                  * SLICED; the update kernel otherwise), timed with events on
+                                  * up to 32 updates spread over the schedule; -1 otherwise */
 } qqa_result;
 
 /* How the update loop runs.  STREAM: one launch per update, state streamed through
  * memory.  PERSISTENT: one cooperative launch for all updates; every lane group keeps
  * its rows' p, m, v in registers and only the new p goes to memory, updates separated by
  * a grid barrier.  LDS_BLOCK: one workgroup with P in LDS (small instances).  BATCH: a
- * ragged multi-instance launch (qqa_solve_batch, the server).  All engines perform the
- * same arithmetic per row and give identical results. */
+ * ragged multi-instance launch (qqa_solve_batch, the server).  SLICED: streaming, with
+ * the replica axis cut into 8 slices, slice s of every row updated on XCD s so that the
+ * neighbour gathers of an XCD stay within 1/8 of P (its L2); two launches per update (row
+ * statistics, then the slices).  Sparse graphs with S >= 61 (at least 2 replica quads per
+ * slice); it pays when an instance has few rows and many replicas.  All engines perform the same arithmetic per row and
+ * give identical results (STREAM layouts that split a row's edges over lane slices add
+ * the coupling sum in another order). */
 typedef enum {
     QQA_ENGINE_AUTO = -1,
     QQA_ENGINE_STREAM = 0,
     QQA_ENGINE_PERSISTENT = 1,
     QQA_ENGINE_LDS_BLOCK = 2,
-    QQA_ENGINE_BATCH = 3
+    QQA_ENGINE_BATCH = 3,
+    QQA_ENGINE_SLICED = 4
 } qqa_engine;
 
 /* device: HIP ordinal.  hbm_budget_bytes: cap on the device memory the context may
@@ -217,9 +224,11 @@ int qqa_autotune(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, int32_t S, int
 
 /* Engine policy of a context for single solves: QQA_ENGINE_AUTO (default) runs an instance
  * on LDS_BLOCK when it qualifies (one quad per lane in a full-width layout, no rows split
- * into chunks, P fits in one workgroup's LDS), else STREAM; QQA_ENGINE_PERSISTENT runs the
- * register-resident engine when the instance fits on chip (else STREAM);
- * QQA_ENGINE_LDS_BLOCK / QQA_ENGINE_STREAM force those engines where possible. */
+ * into chunks, P fits in one workgroup's LDS), else SLICED when the graph is sparse with
+ * at most 1024 rows and S >= 512 (too few rows to fill the GPU otherwise), else STREAM;
+ * QQA_ENGINE_PERSISTENT runs the register-resident engine when the instance fits on chip
+ * (else STREAM); QQA_ENGINE_LDS_BLOCK / QQA_ENGINE_SLICED / QQA_ENGINE_STREAM force those
+ * engines where possible.  QQA_E_ARG for BATCH or an unknown value. */
 int qqa_set_engine(qqa_ctx *c, qqa_engine policy);
 
 /* Wait up to timeout_us (0 = do not wait, < 0 = forever) for a request.  Returns QQA_OK

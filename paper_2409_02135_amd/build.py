@@ -2,9 +2,11 @@
 
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -13,7 +15,7 @@ LIB = os.path.join(PKG, "libqqa.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["qqa_kernels.hip", "qqa_slots.hip", "qqa_persist.hip", "qqa_dense.hip", "qqa_color.hip", "qqa_runtime.cpp", "qqa_ctx.cpp", "qqa_serve.cpp", "qqa_server.cpp"]
+SOURCES = ["qqa_kernels.hip", "qqa_slots.hip", "qqa_persist.hip", "qqa_dense.hip", "qqa_color.hip", "qqa_slice.hip", "qqa_runtime.cpp", "qqa_ctx.cpp", "qqa_serve.cpp", "qqa_server.cpp"]
 HEADERS = ["qqa_internal.h", "qqa_runtime.h", "qqa_ctx.h", "qqa_device.h", "qqa_batch.h"]
 
 FLAGS = [
@@ -32,10 +34,7 @@ def sources() -> list[str]:
     return [os.path.join(CSRC, s) for s in SOURCES]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP/C++ source into one shared library next to this file."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *sources(), "-o", tmp]
+def _run(cmd: list[str], verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -47,6 +46,22 @@ def build(verbose: bool = False) -> str:
         lines = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l]
         if lines:
             sys.stderr.write("\n".join(lines) + "\n")
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile every HIP/C++ source (in parallel, one object each) and link one shared
+    library next to this file."""
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1, 16))
+    with tempfile.TemporaryDirectory(prefix="qqa_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(s) + ".o") for s in sources()]
+        cmds = [[HIPCC, *compile_flags, *inc, "-c", src, "-o", obj] for src, obj in zip(sources(), objs)]
+        with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+            for f in [pool.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp%d" % os.getpid()
+        _run([HIPCC, *FLAGS, *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

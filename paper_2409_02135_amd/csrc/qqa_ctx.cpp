@@ -130,6 +130,7 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
   r->hub_bytes = (size_t)nchunks * r->shape.stride * sizeof(float);
   if (nchunks) get((void**)&r->hub_partial, r->hub_bytes);
   if (r->problem == QQA_MAXCLIQUE) get((void**)&r->colsum, (size_t)r->shape.stride * sizeof(unsigned long long));
+  if (r->engine == kEngineSliced) get((void**)&r->stats, (size_t)r->n * sizeof(float2));
   if (r->colors > 0) {
     get((void**)&r->cat_sigma, state);
     get((void**)&r->cat_grad, state);
@@ -145,7 +146,7 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
   get((void**)&r->out_dev, r->out_size);
   if (e == hipSuccess) e = c->hpool.get(r->out_size, (void**)&r->out_host);
   for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&r->ev[i]);
-  if (r->engine == kEngineStream && r->K > 0) {
+  if ((r->engine == kEngineStream || r->engine == kEngineSliced) && r->K > 0) {
     // sampled updates t with t % every == every / 2, at most kProbes of them
     r->probe_every = std::max(1, (r->K + kProbes - 1) / kProbes);
     const int samples = (r->K - r->probe_every / 2 + r->probe_every - 1) / r->probe_every;
@@ -179,6 +180,8 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
   r->coupling = nullptr;
   if (r->colsum) c->dpool.put(r->colsum, (size_t)r->shape.stride * sizeof(unsigned long long));
   r->colsum = nullptr;
+  if (r->stats) c->dpool.put(r->stats, (size_t)r->n * sizeof(float2));
+  r->stats = nullptr;
   if (r->cat_sigma) c->dpool.put(r->cat_sigma, state);
   if (r->cat_grad) c->dpool.put(r->cat_grad, state);
   if (r->cat_colors) c->dpool.put(r->cat_colors, (size_t)r->n * r->shape.stride);
@@ -292,7 +295,14 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
     const int allow = g.dense || problem == QQA_MAXCLIQUE ? 0 : c->engine_policy < 0 ? 1 : (c->engine_policy == QQA_ENGINE_LDS_BLOCK ? 1 :
                                                  (c->engine_policy == QQA_ENGINE_PERSISTENT ? 2 : 0));
     r->engine = allow ? persistent_plan(probe, g.nchunks > 0, allow, &r->rows_per_group, &r->grid) : kEngineStream;
-    if (r->engine != kEngineStream) {
+    // a streaming sparse solve runs sliced when asked for, or by default when it has few
+    // rows and many replicas
+    if (r->engine == kEngineStream && !g.dense && slice_shape(S).sq > 0 &&
+        (c->engine_policy == QQA_ENGINE_SLICED || (c->engine_policy < 0 && slice_by_default(g.n, S)))) {
+      r->engine = kEngineSliced;
+      r->footprint += (size_t)g.n * sizeof(float2);
+    }
+    if (r->engine != kEngineStream && r->engine != kEngineSliced) {
       r->table_bytes = (size_t)steps * sizeof(float4);
       r->footprint += r->table_bytes;
     }
@@ -323,7 +333,8 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   if (e == hipSuccess) e = launch_init(seed, g.n, S, r->P[0], r->m, r->v, c->stream);
   if (e == hipSuccess) e = hipEventRecord(r->ev[1], c->stream);
   StepParams p = request_step_params(r.get(), g);
-  if (r->engine == kEngineStream) {
+  if (r->engine == kEngineStream || r->engine == kEngineSliced) {
+    const bool sliced = r->engine == kEngineSliced;
     const int every = r->probe_every;
     for (int t = 0; t < steps && e == hipSuccess; ++t) {
       p.P_in = r->P[t & 1];
@@ -343,7 +354,12 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
       }
       if (g.nchunks && e == hipSuccess) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
       if (!g.dense && probe && e == hipSuccess) e = hipEventRecord(r->probe[pi], c->stream);
-      if (e == hipSuccess) e = launch_step(p, c->stream);
+      if (sliced) {
+        if (e == hipSuccess) e = launch_row_stats(p, r->stats, c->stream);
+        if (e == hipSuccess) e = launch_slice_step(p, r->stats, c->stream);
+      } else if (e == hipSuccess) {
+        e = launch_step(p, c->stream);
+      }
       if (!g.dense && probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
     }
   } else {
@@ -613,7 +629,8 @@ int qqa_solve_resident(qqa_ctx* c, qqa_graph_id g, qqa_problem problem, const qq
 
 int qqa_set_engine(qqa_ctx* c, qqa_engine policy) {
   if (!c) return QQA_E_ARG;
-  if (policy < QQA_ENGINE_AUTO || policy > QQA_ENGINE_LDS_BLOCK) return set_err(c, QQA_E_ARG, "unknown engine policy");
+  if (policy < QQA_ENGINE_AUTO || policy > QQA_ENGINE_SLICED || policy == QQA_ENGINE_BATCH)
+    return set_err(c, QQA_E_ARG, "unknown engine policy");
   c->engine_policy = policy;
   return QQA_OK;
 }
@@ -725,7 +742,7 @@ int qqa_poll(qqa_ctx* c, qqa_req id, qqa_result* out, int32_t timeout_us) {
   int rc = QQA_OK;
   if (r->cancelled) {
     rc = set_err(c, QQA_E_CANCELLED, "request was cancelled");
-  } else if (r->engine != kEngineStream && r->engine != 3 && out_bar(r->out_host, r->S)[1] != 0u) {
+  } else if ((r->engine == kEnginePersistent || r->engine == kEngineLdsBlock) && out_bar(r->out_host, r->S)[1] != 0u) {
     rc = set_err(c, QQA_E_DEVICE, "persistent engine: grid barrier timed out");
   } else if (out) {
     fill_result(r, out);

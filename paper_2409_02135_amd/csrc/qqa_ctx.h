@@ -32,7 +32,8 @@ struct DevGraph {
   bool release_pending = false;
 };
 
-// launches of the dominant kernel timed per streaming request
+// updates whose dominant launches (the update kernel; the sliced engine's statistics and
+// slice kernels together; the dense product) are timed per streaming request
 constexpr int kProbes = 32;
 
 struct Request {
@@ -62,6 +63,7 @@ struct Request {
   size_t hub_bytes = 0;
   float* coupling = nullptr;     // dense graphs: n x stride coupling product
   unsigned long long* colsum = nullptr;  // max clique: per-replica sums of P (2^-32 fixed point)
+  float2* stats = nullptr;               // sliced engine: per row {mu, -alpha_c / sigma} of P_in
   // graph coloring: colours K; state rows are n * K; sigma and G (n * K x stride), colours
   // of every replica (n x stride bytes)
   int colors = 0;

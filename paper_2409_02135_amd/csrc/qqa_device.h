@@ -92,56 +92,66 @@ __device__ __forceinline__ void store_coherent(float* p, const float4 v) {
   __hip_atomic_store(reinterpret_cast<unsigned long long*>(p) + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Neighbour rows loaded per iteration of the coupling loop (independent loads in flight).
-constexpr int kGatherUnroll = 4;
+// Neighbour quads loaded per batch of the coupling loop: a batch issues all its loads before
+// the first one is used, so a row's gathers cost one memory round trip per batch.
+constexpr int kGatherQuads = 8;
 
 // acc += sum over edges e in [e_begin, e_end) of w_e * f(p_col(e)), with f(p) = p (MIS or
-// max clique) or 2p - 1 (max-cut); kGatherUnroll neighbour rows are loaded per iteration.
+// max clique) or 2p - 1 (max-cut), accumulated in edge order.  Each batch takes
+// kGatherQuads / QPL edges (at least one): their column indices and weights, then all their
+// neighbour loads, then the fused multiply-adds.  The loads are unconditional (an edge past
+// the row's end loads the row's last neighbour again, and its product is discarded by a
+// select), so no branch separates them and they are all in flight together.
 // Normally every lane of the group walks all edges in edge order for its own quads.  Edge
 // split: when the row has fewer quads than the group has lanes (nq divides LPR, one quad
 // per lane), the LPR / nq lane slices take every (LPR / nq)-th edge for quad gl % nq, and a
 // butterfly over the slices adds their partial sums, so every lane ends with its quad's
-// sum (identical bits in each slice).  Both orders are fixed by the layout alone.
-template <int LPR, int QPL, bool FULL, bool COHERENT = false>
+// sum (identical bits in each slice).  Both orders are fixed by the layout alone.  SPLIT =
+// false keeps plain edge order whatever the shape (idle lanes instead).
+template <int LPR, int QPL, bool FULL, bool COHERENT = false, bool SPLIT = true>
 __device__ __forceinline__ void gather_coupling(const StepParams& a, const int e_begin, const int e_end, const int gl,
                                                 const int nq, const bool maxcut, float4 (&acc)[QPL]) {
-  constexpr int U = kGatherUnroll;
-  const int slices = (!FULL && QPL == 1 && nq < LPR && LPR % nq == 0) ? LPR / nq : 1;
+  // the persistent engines (COHERENT) keep one edge per batch: their registers hold state
+  constexpr int U = COHERENT ? 1 : (kGatherQuads / QPL > 0 ? kGatherQuads / QPL : 1);
+  const int slices = (SPLIT && !FULL && QPL == 1 && nq < LPR && LPR % nq == 0) ? LPR / nq : 1;
   const int lane_q = slices > 1 ? gl % nq : gl;  // the quad this lane gathers
   const int first = e_begin + (slices > 1 ? gl / nq : 0);
   for (int e0 = first; e0 < e_end; e0 += U * slices) {
-    int j[U];
+    const float* pj[U];
     float w[U];
+    bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = e0 + u * slices;
-      j[u] = e < e_end ? a.col[e] : -1;
-      w[u] = e < e_end ? (a.w ? a.w[e] : 1.f) : 0.f;
+      ok[u] = e < e_end;
+      const int ec = ok[u] ? e : e_end - 1;  // a valid edge of this row
+      pj[u] = a.P_in + (size_t)a.col[ec] * a.stride;
+      w[u] = a.w ? a.w[ec] : 1.f;
     }
+    float4 x[U][QPL];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (j[u] < 0) continue;
-      const float* pj = a.P_in + (size_t)j[u] * a.stride;
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int k = 0; k < QPL; ++k) {
         const int q = lane_q + LPR * k;
-        if (FULL || q < nq) {
-          float4 x = COHERENT ? load_coherent(pj + 4 * q) : *reinterpret_cast<const float4*>(pj + 4 * q);
-          if (maxcut) {
-            x.x = 2.f * x.x - 1.f;
-            x.y = 2.f * x.y - 1.f;
-            x.z = 2.f * x.z - 1.f;
-            x.w = 2.f * x.w - 1.f;
-          }
-          acc[k].x = fmaf(w[u], x.x, acc[k].x);
-          acc[k].y = fmaf(w[u], x.y, acc[k].y);
-          acc[k].z = fmaf(w[u], x.z, acc[k].z);
-          acc[k].w = fmaf(w[u], x.w, acc[k].w);
+        x[u][k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (FULL || q < nq)
+          x[u][k] = COHERENT ? load_coherent(pj[u] + 4 * q) : *reinterpret_cast<const float4*>(pj[u] + 4 * q);
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float xc = comp(x[u][k], c);
+          const float f = maxcut ? 2.f * xc - 1.f : xc;
+          const float r = fmaf(w[u], f, comp(acc[k], c));
+          set_comp(acc[k], c, ok[u] ? r : comp(acc[k], c));
         }
       }
-    }
   }
-  if (!FULL && QPL == 1 && slices > 1) {
+  if (SPLIT && !FULL && QPL == 1 && slices > 1) {
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) {
       if (off < nq) break;  // lanes differing in the slice bits only
@@ -178,7 +188,7 @@ __device__ __forceinline__ void load_row(const StepParams& a, const float* P, co
 // Coupling product of one row: C_i = sum_j A_ij p_j (MIS) or sum_j A_ij (2 p_j - 1)
 // (max-cut), accumulated in CSR order (or chunk order for split rows) so that the
 // rounding sequence depends on the graph only.
-template <int LPR, int QPL, bool FULL, bool COHERENT = false>
+template <int LPR, int QPL, bool FULL, bool COHERENT = false, bool SPLIT = true>
 __device__ __forceinline__ void row_coupling(const StepParams& a, const int row, const int gl, float4 (&acc)[QPL]) {
   const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
 #pragma unroll
@@ -207,25 +217,17 @@ __device__ __forceinline__ void row_coupling(const StepParams& a, const int row,
       }
     }
   } else {
-    gather_coupling<LPR, QPL, FULL, COHERENT>(a, a.row_ptr[row], a.row_ptr[row + 1], gl, nq, a.problem == kMAXCUT,
-                                              acc);
+    gather_coupling<LPR, QPL, FULL, COHERENT, SPLIT>(a, a.row_ptr[row], a.row_ptr[row + 1], gl, nq,
+                                                     a.problem == kMAXCUT, acc);
   }
 }
 
-// Everything after the coupling product: replica statistics mu_i, sigma_i (two passes,
-// population STD), gradient, AdamW or plain step, noise, clamp.  Writes the new values
-// of lane gl's replicas to po / mo / vo (padding replicas 0).  SUMS: the kernel may run
-// max clique (per-replica sums in a.colsum); kernels that never do leave it out and keep
-// their registers.
-template <int LPR, int QPL, bool FULL, bool SUMS = true>
-__device__ __forceinline__ void finish_row(const StepParams& a, const int row, const int gl, const float4 (&p)[QPL],
-                                           const float4 (&mm)[QPL], const float4 (&vv)[QPL],
-                                           const float4 (&acc)[QPL], float4 (&po)[QPL], float4 (&mo)[QPL],
-                                           float4 (&vo)[QPL]) {
-  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
-  const bool maxcut = a.problem == kMAXCUT;
-  const bool clique = SUMS && a.problem == kMAXCLIQUE;
-  const bool adam = a.rule == kADAMW;
+// Replica statistics of one row (Eq. 10): mu_i and the communication coefficient
+// cg_i = -alpha_c / sigma_i (0 when sigma_i = 0), two passes, population STD.  The sums run
+// over lane gl's quads, then the group's butterfly: the rounding depends on the layout only.
+template <int LPR, int QPL, bool FULL>
+__device__ __forceinline__ void row_stats(const StepParams& a, const int gl, const float4 (&p)[QPL], float& mu,
+                                          float& cg) {
   float sum = 0.f;
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
@@ -235,7 +237,7 @@ __device__ __forceinline__ void finish_row(const StepParams& a, const int row, c
       if (FULL || 4 * q + c < a.S) sum += comp(p[k], c);
   }
   sum = group_sum<LPR>(sum);
-  const float mu = sum * a.inv_S;
+  mu = sum * a.inv_S;
   float sq = 0.f;
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
@@ -249,14 +251,32 @@ __device__ __forceinline__ void finish_row(const StepParams& a, const int row, c
   }
   sq = group_sum<LPR>(sq);
   const float sigma = __builtin_amdgcn_sqrtf(sq * a.inv_S);
-  const float cg = sigma > 0.f ? -a.comm_alpha * __builtin_amdgcn_rcpf(sigma) : 0.f;
+  cg = sigma > 0.f ? -a.comm_alpha * __builtin_amdgcn_rcpf(sigma) : 0.f;
+}
 
+// Everything after the coupling product and the row statistics: gradient, AdamW or plain
+// step, noise, clamp.  Writes the new values of lane gl's replicas to po / mo / vo (padding
+// replicas 0).  Quad indices are local to `a` (whose pointers and S may describe a slice of
+// the row); q_off is the slice's first quad in the row, for the noise counter.  SUMS: the
+// kernel may run max clique (per-replica sums in a.colsum); kernels that never do leave it
+// out and keep their registers.
+template <int LPR, int QPL, bool FULL, bool SUMS = true>
+__device__ __forceinline__ void finish_elems(const StepParams& a, const int row, const int gl, const int q_off,
+                                             const float mu, const float cg, const float4 (&p)[QPL],
+                                             const float4 (&mm)[QPL], const float4 (&vv)[QPL],
+                                             const float4 (&acc)[QPL], float4 (&po)[QPL], float4 (&mo)[QPL],
+                                             float4 (&vo)[QPL]) {
+  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
+  const bool maxcut = a.problem == kMAXCUT;
+  const bool clique = SUMS && a.problem == kMAXCLIQUE;
+  const bool adam = a.rule == kADAMW;
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int q = gl + LPR * k;
     po[k] = mo[k] = vo[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (!FULL && q >= nq) continue;
-    const float4 xi = normals4(philox4x32_10((uint32_t)row, (uint32_t)q, a.k, kStreamNoise, a.key0, a.key1));
+    const float4 xi =
+        normals4(philox4x32_10((uint32_t)row, (uint32_t)(q_off + q), a.k, kStreamNoise, a.key0, a.key1));
     float4 T = make_float4(0.f, 0.f, 0.f, 0.f);  // max clique: 1^T p of the quad's replicas
     if (clique) {
 #pragma unroll
@@ -289,6 +309,17 @@ __device__ __forceinline__ void finish_row(const StepParams& a, const int row, c
       set_comp(vo[k], c, valid ? vn : 0.f);
     }
   }
+}
+
+// Statistics, then the element update, of one whole row.
+template <int LPR, int QPL, bool FULL, bool SUMS = true>
+__device__ __forceinline__ void finish_row(const StepParams& a, const int row, const int gl, const float4 (&p)[QPL],
+                                           const float4 (&mm)[QPL], const float4 (&vv)[QPL],
+                                           const float4 (&acc)[QPL], float4 (&po)[QPL], float4 (&mo)[QPL],
+                                           float4 (&vo)[QPL]) {
+  float mu, cg;
+  row_stats<LPR, QPL, FULL>(a, gl, p, mu, cg);
+  finish_elems<LPR, QPL, FULL, SUMS>(a, row, gl, 0, mu, cg, p, mm, vv, acc, po, mo, vo);
 }
 
 template <int LPR, int QPL, bool FULL, bool COHERENT = false>

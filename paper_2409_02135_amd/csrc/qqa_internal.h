@@ -142,7 +142,7 @@ struct PersistParams {
   int32_t t0, t1;
   unsigned* bar;                // [0] arrivals (zero before the launch), [1] abort flag
 };
-enum PersistEngine { kEngineStream = 0, kEnginePersistent = 1, kEngineLdsBlock = 2 };
+enum PersistEngine { kEngineStream = 0, kEnginePersistent = 1, kEngineLdsBlock = 2, kEngineSliced = 4 };
 // Which engine can run this instance (FULL layouts with one quad per lane, no split
 // rows); `allow` is a mask (1: one workgroup with P in LDS, 2: many workgroups with state
 // in registers).  Fills rows per group and the grid for the chosen one.
@@ -183,6 +183,26 @@ hipError_t launch_philox(uint64_t seed, int n, int nquads, uint32_t k, uint32_t 
 hipError_t launch_noise(uint64_t seed, int n, int S, uint32_t k, float* xi, hipStream_t st);
 hipError_t launch_init(uint64_t seed, int n, int S, float* P, float* m, float* v, hipStream_t st);
 hipError_t launch_step(const StepParams& p, hipStream_t st);
+
+// Sliced streaming update: the replica axis is cut into kReplicaSlices slices of at most sq quads
+// (sizes differ by at most one), one per XCD, each served by ls lanes x qs quads (sq == 0:
+// S is not sliceable, i.e. fewer than 2 quads per slice).  One update is
+// launch_row_stats (per row of P_in: {mu, -alpha_c / sigma}, into `stats`, n entries) then
+// launch_slice_step; the result is bitwise identical to launch_step.
+constexpr int kReplicaSlices = 8;
+// The automatic engine policy slices sparse streaming solves with few rows and many
+// replicas: at most one whole-row wavefront per SIMD leaves the GPU mostly idle, and the
+// slices give it kReplicaSlices times more lane groups.  With more rows, the whole-row
+// kernel is as fast or faster (its gathers are not limited by L2 misses on this GPU).
+constexpr int kSliceAutoMaxRows = 1024;
+constexpr int kSliceAutoMinReplicas = 512;
+inline bool slice_by_default(int n, int S) { return n <= kSliceAutoMaxRows && S >= kSliceAutoMinReplicas; }
+struct SliceShape {
+  int sq, ls, qs;
+};
+SliceShape slice_shape(int S);
+hipError_t launch_row_stats(const StepParams& p, float2* stats, hipStream_t st);
+hipError_t launch_slice_step(const StepParams& p, const float2* stats, hipStream_t st);
 
 // Partial coupling sums of every chunk into p.hub_partial (reads P_in, row_ptr, col, w).
 hipError_t launch_hub_partials(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st);

@@ -391,8 +391,8 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
     return fail(&g_dev_error, QQA_E_ARG, "unsupported replica layout");
   if (g->n == 0 || t0 == t1) return QQA_OK;
   hipStream_t st = (hipStream_t)stream;
-  if (problem == QQA_MAXCLIQUE && engine > 0)
-    return fail(&g_dev_error, QQA_E_ARG, "max clique runs on the streaming engine");
+  if (problem == QQA_MAXCLIQUE && engine > 0 && engine != kEngineSliced)
+    return fail(&g_dev_error, QQA_E_ARG, "max clique runs on the streaming engines");
   unsigned long long* T = nullptr;
   if (g->dense) {
     if (engine > 0) return fail(&g_dev_error, QQA_E_ARG, "dense coupling runs on the streaming engine");
@@ -437,15 +437,20 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
   build_hub_plan(rp.data(), g->n, &chunks, &hub_first);
   int rpg = 0, grid = 0;
   int use = kEngineStream;
-  if (engine != kEngineStream && problem != QQA_MAXCLIQUE) {
+  const bool sliceable = slice_shape(S).sq > 0;
+  if (engine == kEngineSliced) {
+    if (!sliceable) return fail(&g_dev_error, QQA_E_ARG, "engine cannot run this instance");
+    use = kEngineSliced;
+  } else if (engine != kEngineStream && problem != QQA_MAXCLIQUE) {
     // allow mask: 1 = one workgroup with P in LDS, 2 = many workgroups with registers
     const int allow = engine < 0 ? 3 : (engine == kEngineLdsBlock ? 1 : (engine == kEnginePersistent ? 2 : 0));
     if (!allow) return fail(&g_dev_error, QQA_E_ARG, "unknown engine");
     use = persistent_plan(p, !chunks.empty(), allow, &rpg, &grid);
     if (engine >= 0 && use != engine) return fail(&g_dev_error, QQA_E_ARG, "engine cannot run this instance");
   }
+  if (engine < 0 && use == kEngineStream && sliceable && slice_by_default(g->n, S)) use = kEngineSliced;
   float* P[2] = {P0, P1};
-  if (use == kEngineStream) {
+  if (use == kEngineStream || use == kEngineSliced) {
     HubChunk* d_chunks = nullptr;
     int32_t* d_first = nullptr;
     float* d_part = nullptr;
@@ -458,6 +463,8 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
       p.hub_first = d_first;
       p.hub_partial = d_part;
     }
+    float2* stats = nullptr;
+    if (use == kEngineSliced) DEV_CHECK(hipMallocAsync((void**)&stats, (size_t)g->n * sizeof(float2), st));
     hipError_t e = hipSuccess;
     for (int t = t0; t < t1 && e == hipSuccess; ++t) {
       p.P_in = P[t & 1];
@@ -465,9 +472,11 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
       fill_step_scalars(p, s, t, K);
       e = colsum_for(p, problem, &T, st);
       if (e == hipSuccess && !chunks.empty()) e = launch_hub_partials(p, d_chunks, (int)chunks.size(), st);
-      if (e == hipSuccess) e = launch_step(p, st);
+      if (e == hipSuccess && stats) e = launch_row_stats(p, stats, st);
+      if (e == hipSuccess) e = stats ? launch_slice_step(p, stats, st) : launch_step(p, st);
     }
     if (T) (void)hipFreeAsync(T, st);
+    if (stats) (void)hipFreeAsync(stats, st);
     if (!chunks.empty()) {
       (void)hipFreeAsync(d_chunks, st);
       (void)hipFreeAsync(d_first, st);
