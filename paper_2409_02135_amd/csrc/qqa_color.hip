@@ -11,9 +11,10 @@
 // objective gradient G = dR/dsigma.  One update is two launches:
 //   cat_grad_kernel    per row (i, k): sum_j A_ij sigma_jk (gathered through the graph's CSR
 //                      with the row pitch K * stride), + the entropy and STD terms -> G
-//   cat_update_kernel  per variable i: dR/dV_ik = (G_ik - sum_k' sigma_ik' G_ik') / Z_i,
+//   cat_update_*       per variable i: dR/dV_ik = (G_ik - sum_k' sigma_ik' G_ik') / Z_i,
 //                      AdamW, sqrt(2 eta T) xi (Philox row i*K + k), clamp -> V; then sigma
-//                      of the new V, in place.
+//                      of the new V, in place.  K <= 8 keeps the variable's K rows in
+//                      registers (one read of V, G, m, v); larger K takes three passes.
 // Rounding: x_i = argmax_k V_ik (first maximum); cost = edges whose ends share a colour.
 #include "qqa_device.h"
 
@@ -110,8 +111,104 @@ __global__ __launch_bounds__(kBlock) void cat_grad_kernel(StepParams a, int K, f
   }
 }
 
+// One pass over the K colour rows of variable i, quad q: V, G and the moments are read once
+// and kept in registers (K <= KMAX), then the step, then sigma of the new V from the same
+// registers.
+// sum_k sigma_k G_k is formed as (sum_k V_k G_k) / Z, which is the same quantity as the
+// generic kernel's (rounded differently).
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void cat_update_regs_kernel(StepParams a, int K, const float* __restrict__ G,
+                                                                 float* __restrict__ sig) {
+  const int nq = a.stride >> 2;
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (long long)a.n * nq) return;
+  const int i = (int)(t / nq), q = (int)(t % nq);
+  const bool adam = a.rule == kADAMW;
+  const size_t base = (size_t)i * K * a.stride + 4 * q;
+  float4 x[KMAX], g[KMAX], mm[KMAX], vv[KMAX];
+  float4 Z = make_float4(0.f, 0.f, 0.f, 0.f), XG = make_float4(0.f, 0.f, 0.f, 0.f), GS = XG;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k >= K) break;
+    const size_t off = base + (size_t)k * a.stride;
+    x[k] = *reinterpret_cast<const float4*>(a.P_in + off);
+    g[k] = *reinterpret_cast<const float4*>(G + off);
+    mm[k] = vv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (adam) {
+      mm[k] = *reinterpret_cast<const float4*>(a.m + off);
+      vv[k] = *reinterpret_cast<const float4*>(a.v + off);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k >= K) break;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      set_comp(Z, c, comp(Z, c) + comp(x[k], c));
+      set_comp(XG, c, fmaf(comp(x[k], c), comp(g[k], c), comp(XG, c)));
+      set_comp(GS, c, comp(GS, c) + comp(g[k], c));
+    }
+  }
+  const float u = 1.f / (float)K;
+  float4 D, Zc;  // sum_k sigma_k G_k and Z (Z := 1 for an all-zero row)
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float z = comp(Z, c);
+    set_comp(D, c, z > 0.f ? comp(XG, c) / z : comp(GS, c) * u);
+    set_comp(Zc, c, z > 0.f ? z : 1.f);
+  }
+  float4 Zo = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k >= K) break;
+    const size_t off = base + (size_t)k * a.stride;
+    const float4 xi =
+        normals4(philox4x32_10((uint32_t)(i * K + k), (uint32_t)q, a.k, kStreamNoise, a.key0, a.key1));
+    float4 po, mo, vo;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float grad = (comp(g[k], c) - comp(D, c)) / comp(Zc, c);
+      const float pc = comp(x[k], c);
+      float pn, mn = 0.f, vn = 0.f;
+      if (adam) {
+        mn = fmaf(a.beta1, comp(mm[k], c), a.omb1 * grad);
+        vn = fmaf(a.beta2, comp(vv[k], c), a.omb2 * (grad * grad));
+        const float den = __builtin_amdgcn_sqrtf(vn * a.inv_bc2) + a.eps;
+        pn = pc * a.wd_factor - a.lr * (mn * a.inv_bc1) * __builtin_amdgcn_rcpf(den);
+      } else {
+        pn = pc - a.lr * grad;
+      }
+      pn = fmaf(a.noise_scale, comp(xi, c), pn);
+      pn = fminf(fmaxf(pn, 0.f), 1.f);
+      const bool valid = 4 * q + c < a.S;
+      set_comp(po, c, valid ? pn : 0.f);
+      set_comp(mo, c, valid ? mn : 0.f);
+      set_comp(vo, c, valid ? vn : 0.f);
+      set_comp(Zo, c, comp(Zo, c) + (valid ? pn : 0.f));
+    }
+    x[k] = po;
+    *reinterpret_cast<float4*>(a.P_out + off) = po;
+    if (adam) {
+      *reinterpret_cast<float4*>(a.m + off) = mo;
+      *reinterpret_cast<float4*>(a.v + off) = vo;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k >= K) break;
+    float4 o;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float z = comp(Zo, c);
+      set_comp(o, c, 4 * q + c < a.S ? (z > 0.f ? comp(x[k], c) / z : u) : 0.f);
+    }
+    *reinterpret_cast<float4*>(sig + base + (size_t)k * a.stride) = o;
+  }
+}
+
 // per variable i and replica quad q: the chain rule through the normalisation, the step, and
 // sigma of the new state.  a.P_in = V_in, a.P_out = V_out, a.m / a.v, a.n = N variables.
+// Any K; three passes over the K colour rows.
 __global__ __launch_bounds__(kBlock) void cat_update_kernel(StepParams a, int K, const float* __restrict__ G,
                                                             float* __restrict__ sig) {
   const int nq = a.stride >> 2;
@@ -271,8 +368,13 @@ hipError_t launch_cat_grad(const StepParams& p, int K, float* G, hipStream_t st)
 
 hipError_t launch_cat_update(const StepParams& p, int K, const float* G, float* sig, hipStream_t st) {
   if (p.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(cat_update_kernel, dim3(blocks_for((long long)p.n * (p.stride >> 2))), dim3(kBlock), 0, st, p, K,
-                     G, sig);
+  const dim3 grid(blocks_for((long long)p.n * (p.stride >> 2))), block(kBlock);
+  if (K <= 4)
+    hipLaunchKernelGGL((cat_update_regs_kernel<4>), grid, block, 0, st, p, K, G, sig);
+  else if (K <= 8)
+    hipLaunchKernelGGL((cat_update_regs_kernel<8>), grid, block, 0, st, p, K, G, sig);
+  else  // more colours: the register footprint would leave too few loads in flight
+    hipLaunchKernelGGL(cat_update_kernel, grid, block, 0, st, p, K, G, sig);
   return hipGetLastError();
 }
 

@@ -74,8 +74,10 @@ GRAPHS = {
 }
 
 
+# colours 2..8 take the register-resident update kernel, more colours the three-pass one
 @pytest.mark.parametrize("gname,colors,S", [("queen5", 5, 16), ("queen8", 9, 64), ("er500", 4, 32), ("er500", 3, 1),
-                                            ("rrg200", 3, 256), ("queen8", 2, 100)])
+                                            ("rrg200", 3, 256), ("queen8", 2, 100), ("queen8", 8, 40),
+                                            ("queen8", 17, 40), ("er500", 31, 8)])
 def test_step_parity(orc, gname, colors, S):
     q = qqa()
     g = GRAPHS[gname]()
