@@ -364,8 +364,7 @@ def main():
         abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
         achieved = abytes / (step_us * 1e-6) / 1e9
         sliced = results[0]["engine"] == "sliced"
-        # the sliced engine's update is two launches (row statistics, then the slices)
-        roofline = {"bound": "hbm", "kernel": "row_stats_kernel + slice_step_kernel" if sliced else "step_kernel",
+        roofline = {"bound": "hbm", "kernel": "slice_step_kernel" if sliced else "step_kernel",
                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                     "traffic": (traffic_from_profiles("slice_step_traffic.json", SLICE_SOURCES) if sliced else

@@ -141,9 +141,8 @@ typedef struct {
     double latency_ms;           /* submit -> result ready (host clock) */
     int32_t engine;              /* qqa_engine that ran the update loop */
     double kernel_us;            /* streaming engines: mean device duration of the dominant
-                                  * launches of an update (the coupling product for dense
-                                  * graphs; the statistics and slice launches together for
-                                  * SLICED; the update kernel otherwise), timed with events on
+                                  * launch of an update (the coupling product for dense
+                                  * graphs, the update kernel otherwise), timed with events on
                                   * up to 32 updates spread over the schedule; -1 otherwise */
 } qqa_result;
 
@@ -153,11 +152,15 @@ typedef struct {
  * a grid barrier.  LDS_BLOCK: one workgroup with P in LDS (small instances).  BATCH: a
  * ragged multi-instance launch (qqa_solve_batch, the server).  SLICED: streaming, with
  * the replica axis cut into 8 slices, slice s of every row updated on XCD s so that the
- * neighbour gathers of an XCD stay within 1/8 of P (its L2); two launches per update (row
- * statistics, then the slices).  Sparse graphs with S >= 61 (at least 2 replica quads per
- * slice); it pays when an instance has few rows and many replicas.  All engines perform the same arithmetic per row and
- * give identical results (STREAM layouts that split a row's edges over lane slices add
- * the coupling sum in another order). */
+ * neighbour gathers of an XCD stay within 1/8 of P (its L2); one launch per update, which
+ * also leaves each slice's partial statistics {mean, M2} of the new values for the next
+ * update.  Sparse graphs with S >= 61 (at least 2 replica quads per slice).  STREAM,
+ * PERSISTENT, LDS_BLOCK and BATCH perform the same arithmetic per row and give identical
+ * results (STREAM layouts that split a row's edges over lane slices add the coupling sum in
+ * another order).  SLICED performs the same arithmetic except for the replica statistics,
+ * which it combines from the slices' partials: its results agree with the others to
+ * rounding after one update, and its trajectories then diverge from theirs as any two
+ * roundings of the method do.  It is deterministic and resumable like the others. */
 typedef enum {
     QQA_ENGINE_AUTO = -1,
     QQA_ENGINE_STREAM = 0,
@@ -224,8 +227,8 @@ int qqa_autotune(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, int32_t S, int
 
 /* Engine policy of a context for single solves: QQA_ENGINE_AUTO (default) runs an instance
  * on LDS_BLOCK when it qualifies (one quad per lane in a full-width layout, no rows split
- * into chunks, P fits in one workgroup's LDS), else SLICED when the graph is sparse with
- * at most 1024 rows and S >= 512 (too few rows to fill the GPU otherwise), else STREAM;
+ * into chunks, P fits in one workgroup's LDS), else SLICED when the graph is sparse,
+ * S >= 256 and P (n x stride floats) is at most 24 MiB, else STREAM;
  * QQA_ENGINE_PERSISTENT runs the register-resident engine when the instance fits on chip
  * (else STREAM); QQA_ENGINE_LDS_BLOCK / QQA_ENGINE_SLICED / QQA_ENGINE_STREAM force those
  * engines where possible.  QQA_E_ARG for BATCH or an unknown value. */

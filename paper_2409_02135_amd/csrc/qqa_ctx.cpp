@@ -130,7 +130,7 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
   r->hub_bytes = (size_t)nchunks * r->shape.stride * sizeof(float);
   if (nchunks) get((void**)&r->hub_partial, r->hub_bytes);
   if (r->problem == QQA_MAXCLIQUE) get((void**)&r->colsum, (size_t)r->shape.stride * sizeof(unsigned long long));
-  if (r->engine == kEngineSliced) get((void**)&r->stats, (size_t)r->n * sizeof(float2));
+  if (r->engine == kEngineSliced) get((void**)&r->stats, 2 * (size_t)r->n * kReplicaSlices * sizeof(float2));
   if (r->colors > 0) {
     get((void**)&r->cat_sigma, state);
     get((void**)&r->cat_grad, state);
@@ -180,7 +180,7 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
   r->coupling = nullptr;
   if (r->colsum) c->dpool.put(r->colsum, (size_t)r->shape.stride * sizeof(unsigned long long));
   r->colsum = nullptr;
-  if (r->stats) c->dpool.put(r->stats, (size_t)r->n * sizeof(float2));
+  if (r->stats) c->dpool.put(r->stats, 2 * (size_t)r->n * kReplicaSlices * sizeof(float2));
   r->stats = nullptr;
   if (r->cat_sigma) c->dpool.put(r->cat_sigma, state);
   if (r->cat_grad) c->dpool.put(r->cat_grad, state);
@@ -295,12 +295,12 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
     const int allow = g.dense || problem == QQA_MAXCLIQUE ? 0 : c->engine_policy < 0 ? 1 : (c->engine_policy == QQA_ENGINE_LDS_BLOCK ? 1 :
                                                  (c->engine_policy == QQA_ENGINE_PERSISTENT ? 2 : 0));
     r->engine = allow ? persistent_plan(probe, g.nchunks > 0, allow, &r->rows_per_group, &r->grid) : kEngineStream;
-    // a streaming sparse solve runs sliced when asked for, or by default when it has few
-    // rows and many replicas
+    // a streaming sparse solve runs sliced when asked for, or by default when its slices
+    // are whole cache lines and fit the XCDs' L2
     if (r->engine == kEngineStream && !g.dense && slice_shape(S).sq > 0 &&
         (c->engine_policy == QQA_ENGINE_SLICED || (c->engine_policy < 0 && slice_by_default(g.n, S)))) {
       r->engine = kEngineSliced;
-      r->footprint += (size_t)g.n * sizeof(float2);
+      r->footprint += 2 * (size_t)g.n * kReplicaSlices * sizeof(float2);
     }
     if (r->engine != kEngineStream && r->engine != kEngineSliced) {
       r->table_bytes = (size_t)steps * sizeof(float4);
@@ -335,6 +335,11 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   StepParams p = request_step_params(r.get(), g);
   if (r->engine == kEngineStream || r->engine == kEngineSliced) {
     const bool sliced = r->engine == kEngineSliced;
+    float2* part[2] = {r->stats, r->stats + (size_t)g.n * kReplicaSlices};
+    if (sliced && e == hipSuccess) {
+      p.P_in = r->P[0];
+      e = launch_slice_stats(p, part[0], c->stream);
+    }
     const int every = r->probe_every;
     for (int t = 0; t < steps && e == hipSuccess; ++t) {
       p.P_in = r->P[t & 1];
@@ -355,8 +360,7 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
       if (g.nchunks && e == hipSuccess) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
       if (!g.dense && probe && e == hipSuccess) e = hipEventRecord(r->probe[pi], c->stream);
       if (sliced) {
-        if (e == hipSuccess) e = launch_row_stats(p, r->stats, c->stream);
-        if (e == hipSuccess) e = launch_slice_step(p, r->stats, c->stream);
+        if (e == hipSuccess) e = launch_slice_step(p, part[t & 1], part[(t + 1) & 1], c->stream);
       } else if (e == hipSuccess) {
         e = launch_step(p, c->stream);
       }

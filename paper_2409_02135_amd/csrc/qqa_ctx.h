@@ -32,8 +32,8 @@ struct DevGraph {
   bool release_pending = false;
 };
 
-// updates whose dominant launches (the update kernel; the sliced engine's statistics and
-// slice kernels together; the dense product) are timed per streaming request
+// updates whose dominant launch (the update kernel, or the dense product) is timed per
+// streaming request
 constexpr int kProbes = 32;
 
 struct Request {
@@ -63,7 +63,7 @@ struct Request {
   size_t hub_bytes = 0;
   float* coupling = nullptr;     // dense graphs: n x stride coupling product
   unsigned long long* colsum = nullptr;  // max clique: per-replica sums of P (2^-32 fixed point)
-  float2* stats = nullptr;               // sliced engine: per row {mu, -alpha_c / sigma} of P_in
+  float2* stats = nullptr;               // sliced engine: 2 x n x 8 partial statistics (ping-pong)
   // graph coloring: colours K; state rows are n * K; sigma and G (n * K x stride), colours
   // of every replica (n x stride bytes)
   int colors = 0;

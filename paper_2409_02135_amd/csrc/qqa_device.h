@@ -108,11 +108,11 @@ constexpr int kGatherQuads = 8;
 // butterfly over the slices adds their partial sums, so every lane ends with its quad's
 // sum (identical bits in each slice).  Both orders are fixed by the layout alone.  SPLIT =
 // false keeps plain edge order whatever the shape (idle lanes instead).
-template <int LPR, int QPL, bool FULL, bool COHERENT = false, bool SPLIT = true>
+template <int LPR, int QPL, bool FULL, bool COHERENT = false, bool SPLIT = true, int QUADS = kGatherQuads>
 __device__ __forceinline__ void gather_coupling(const StepParams& a, const int e_begin, const int e_end, const int gl,
                                                 const int nq, const bool maxcut, float4 (&acc)[QPL]) {
   // the persistent engines (COHERENT) keep one edge per batch: their registers hold state
-  constexpr int U = COHERENT ? 1 : (kGatherQuads / QPL > 0 ? kGatherQuads / QPL : 1);
+  constexpr int U = COHERENT ? 1 : (QUADS / QPL > 0 ? QUADS / QPL : 1);
   const int slices = (SPLIT && !FULL && QPL == 1 && nq < LPR && LPR % nq == 0) ? LPR / nq : 1;
   const int lane_q = slices > 1 ? gl % nq : gl;  // the quad this lane gathers
   const int first = e_begin + (slices > 1 ? gl / nq : 0);
@@ -128,15 +128,16 @@ __device__ __forceinline__ void gather_coupling(const StepParams& a, const int e
       pj[u] = a.P_in + (size_t)a.col[ec] * a.stride;
       w[u] = a.w ? a.w[ec] : 1.f;
     }
+    // a lane past the row's last quad loads that quad again (unconditional loads, no join);
+    // its sums are never used
     float4 x[U][QPL];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int k = 0; k < QPL; ++k) {
         const int q = lane_q + LPR * k;
-        x[u][k] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (FULL || q < nq)
-          x[u][k] = COHERENT ? load_coherent(pj[u] + 4 * q) : *reinterpret_cast<const float4*>(pj[u] + 4 * q);
+        const float* src = pj[u] + 4 * ((FULL || q < nq) ? q : nq - 1);
+        x[u][k] = COHERENT ? load_coherent(src) : *reinterpret_cast<const float4*>(src);
       }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -171,39 +172,60 @@ __device__ __forceinline__ void load_row(const StepParams& a, const float* P, co
                                          float4 (&p)[QPL], float4 (&mm)[QPL], float4 (&vv)[QPL]) {
   const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
   const size_t base = (size_t)row * a.stride;
+  const bool adam = a.rule == kADAMW;
+  // Unconditional loads, so that no branch joins them (a join makes the compiler copy the
+  // loaded registers, which waits for the loads): a lane past the row's last quad reads
+  // that quad again, and its values are masked wherever they are used; without moments the
+  // row itself stands in for m and v, whose values are then not used.
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int q = gl + LPR * k;
-    p[k] = mm[k] = vv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (FULL || q < nq) {
-      p[k] = *reinterpret_cast<const float4*>(P + base + 4 * q);
-      if (a.rule == kADAMW) {
-        mm[k] = *reinterpret_cast<const float4*>(a.m + base + 4 * q);
-        vv[k] = *reinterpret_cast<const float4*>(a.v + base + 4 * q);
-      }
-    }
+    const size_t off = base + 4 * (size_t)((FULL || q < nq) ? q : nq - 1);
+    p[k] = *reinterpret_cast<const float4*>(P + off);
+    mm[k] = *reinterpret_cast<const float4*>((adam ? a.m : P) + off);
+    vv[k] = *reinterpret_cast<const float4*>((adam ? a.v : P) + off);
   }
+}
+
+// Where a row's coupling terms come from: its CSR range and, for a split row, its first
+// chunk (-1 otherwise).  Loaded before the row's own state, so that waiting for these few
+// words does not also wait for the state loads (vector loads complete in order).
+struct RowMeta {
+  int e0, e1, hub;
+};
+__device__ __forceinline__ RowMeta row_meta(const StepParams& a, const int row) {
+  RowMeta m{0, 0, -1};
+  if (a.hub_first) m.hub = a.hub_first[row];
+  m.e0 = a.row_ptr[row];
+  m.e1 = a.row_ptr[row + 1];
+  return m;
 }
 
 // Coupling product of one row: C_i = sum_j A_ij p_j (MIS) or sum_j A_ij (2 p_j - 1)
 // (max-cut), accumulated in CSR order (or chunk order for split rows) so that the
-// rounding sequence depends on the graph only.
-template <int LPR, int QPL, bool FULL, bool COHERENT = false, bool SPLIT = true>
-__device__ __forceinline__ void row_coupling(const StepParams& a, const int row, const int gl, float4 (&acc)[QPL]) {
+// rounding sequence depends on the graph only.  DENSE: read from the precomputed product
+// a.coupling instead (a compile-time choice: a runtime branch around that load would join
+// the sparse path and make it wait for every load in flight).
+template <int LPR, int QPL, bool FULL, bool COHERENT = false, bool SPLIT = true, bool DENSE = false,
+          int QUADS = kGatherQuads>
+__device__ __forceinline__ void row_coupling(const StepParams& a, const int row, const RowMeta& rm, const int gl,
+                                             float4 (&acc)[QPL]) {
   const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
-#pragma unroll
-  for (int k = 0; k < QPL; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (a.coupling) {
+  if (DENSE) {
 #pragma unroll
     for (int k = 0; k < QPL; ++k) {
       const int q = gl + LPR * k;
-      if (FULL || q < nq) acc[k] = *reinterpret_cast<const float4*>(a.coupling + (size_t)row * a.stride + 4 * q);
+      const size_t off = (size_t)row * a.stride + 4 * (size_t)((FULL || q < nq) ? q : nq - 1);
+      acc[k] = *reinterpret_cast<const float4*>(a.coupling + off);
     }
-  } else if (a.hub_first && a.hub_first[row] >= 0) {
-    const int first = a.hub_first[row];
-    const int nch = (a.row_ptr[row + 1] - a.row_ptr[row] + kHubChunk - 1) / kHubChunk;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (rm.hub >= 0) {
+    const int nch = (rm.e1 - rm.e0 + kHubChunk - 1) / kHubChunk;
     for (int c = 0; c < nch; ++c) {
-      const float* part = a.hub_partial + (size_t)(first + c) * a.stride;
+      const float* part = a.hub_partial + (size_t)(rm.hub + c) * a.stride;
 #pragma unroll
       for (int k = 0; k < QPL; ++k) {
         const int q = gl + LPR * k;
@@ -217,8 +239,7 @@ __device__ __forceinline__ void row_coupling(const StepParams& a, const int row,
       }
     }
   } else {
-    gather_coupling<LPR, QPL, FULL, COHERENT, SPLIT>(a, a.row_ptr[row], a.row_ptr[row + 1], gl, nq,
-                                                     a.problem == kMAXCUT, acc);
+    gather_coupling<LPR, QPL, FULL, COHERENT, SPLIT, QUADS>(a, rm.e0, rm.e1, gl, nq, a.problem == kMAXCUT, acc);
   }
 }
 
@@ -341,12 +362,14 @@ __device__ __forceinline__ void store_row(const StepParams& a, float* P, const i
   }
 }
 
-// One update of one row, state streamed from and to memory.
-template <int LPR, int QPL, bool FULL, bool SUMS = true>
+// One update of one row, state streamed from and to memory.  DENSE: the coupling product
+// was computed beforehand into a.coupling.
+template <int LPR, int QPL, bool FULL, bool SUMS = true, bool DENSE = false>
 __device__ __forceinline__ void update_row(const StepParams& a, const int row, const int gl) {
   float4 p[QPL], mm[QPL], vv[QPL], acc[QPL], po[QPL], mo[QPL], vo[QPL];
+  const RowMeta rm = DENSE ? RowMeta{0, 0, -1} : row_meta(a, row);
   load_row<LPR, QPL, FULL>(a, a.P_in, row, gl, p, mm, vv);  // issued before the gathers
-  row_coupling<LPR, QPL, FULL>(a, row, gl, acc);
+  row_coupling<LPR, QPL, FULL, false, true, DENSE>(a, row, rm, gl, acc);
   finish_row<LPR, QPL, FULL, SUMS>(a, row, gl, p, mm, vv, acc, po, mo, vo);
   store_row<LPR, QPL, FULL>(a, a.P_out, row, gl, po, mo, vo, true);
 }

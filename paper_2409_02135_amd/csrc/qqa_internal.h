@@ -184,25 +184,30 @@ hipError_t launch_noise(uint64_t seed, int n, int S, uint32_t k, float* xi, hipS
 hipError_t launch_init(uint64_t seed, int n, int S, float* P, float* m, float* v, hipStream_t st);
 hipError_t launch_step(const StepParams& p, hipStream_t st);
 
-// Sliced streaming update: the replica axis is cut into kReplicaSlices slices of at most sq quads
-// (sizes differ by at most one), one per XCD, each served by ls lanes x qs quads (sq == 0:
-// S is not sliceable, i.e. fewer than 2 quads per slice).  One update is
-// launch_row_stats (per row of P_in: {mu, -alpha_c / sigma}, into `stats`, n entries) then
-// launch_slice_step; the result is bitwise identical to launch_step.
+// Sliced streaming update: the replica axis is cut into kReplicaSlices slices of at most sq
+// quads (sizes differ by at most one), one per XCD, each served by ls lanes x qs quads
+// (sq == 0: S is not sliceable, i.e. fewer than 2 quads per slice).  Partial statistics
+// {mean, M2} per (slice, row), kReplicaSlices x n entries, ping-pong between updates:
+// launch_slice_stats forms them from p.P_in before the first update; each launch_slice_step
+// reads part_in (of P_in) and writes part_out (of P_out).  Same arithmetic per element as
+// launch_step, except that mu and sigma are combined from the slices' partials.
 constexpr int kReplicaSlices = 8;
-// The automatic engine policy slices sparse streaming solves with few rows and many
-// replicas: at most one whole-row wavefront per SIMD leaves the GPU mostly idle, and the
-// slices give it kReplicaSlices times more lane groups.  With more rows, the whole-row
-// kernel is as fast or faster (its gathers are not limited by L2 misses on this GPU).
-constexpr int kSliceAutoMaxRows = 1024;
-constexpr int kSliceAutoMinReplicas = 512;
-inline bool slice_by_default(int n, int S) { return n <= kSliceAutoMaxRows && S >= kSliceAutoMinReplicas; }
+// The automatic engine policy slices sparse streaming solves when every slice is at least
+// one 128-byte line of a row (S >= 256) and one XCD's slice of P fits in its 4 MiB L2 with
+// room to spare (P at most 24 MiB).  Narrower slices waste fetched lines; larger P leaves
+// the gathers missing L2 anyway.
+constexpr int kSliceAutoMinReplicas = 256;
+constexpr size_t kSliceAutoMaxBytes = (size_t)24 << 20;
+inline bool slice_by_default(int n, int S) {
+  const size_t stride = 4 * (size_t)((S + 3) / 4);
+  return S >= kSliceAutoMinReplicas && (size_t)n * stride * sizeof(float) <= kSliceAutoMaxBytes;
+}
 struct SliceShape {
   int sq, ls, qs;
 };
 SliceShape slice_shape(int S);
-hipError_t launch_row_stats(const StepParams& p, float2* stats, hipStream_t st);
-hipError_t launch_slice_step(const StepParams& p, const float2* stats, hipStream_t st);
+hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st);
+hipError_t launch_slice_step(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st);
 
 // Partial coupling sums of every chunk into p.hub_partial (reads P_in, row_ptr, col, w).
 hipError_t launch_hub_partials(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st);

@@ -68,15 +68,16 @@ __global__ __launch_bounds__(kBlock) void hub_partial_kernel(StepParams a, const
   }
 }
 
-// SUMS: the max-clique instance (reads the per-replica sums); the others do not carry it
-template <int LPR, int QPL, bool FULL, bool SUMS>
+// SUMS: the max-clique instance (reads the per-replica sums); the others do not carry it.
+// DENSE: the coupling product comes from a.coupling (dense graphs, any problem).
+template <int LPR, int QPL, bool FULL, bool SUMS, bool DENSE = false>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepParams a) {
   int row = (int)(((long long)blockIdx.x * kBlock + threadIdx.x) / LPR);
   // a whole wavefront serves one row when LPR = 64: make that explicit so the CSR reads
   // become scalar loads and neighbour addresses a scalar base plus the lane offset
   if (LPR == 64) row = __builtin_amdgcn_readfirstlane(row);
   if (row >= a.n) return;  // whole LPR-lane groups leave together
-  update_row<LPR, QPL, FULL, SUMS>(a, row, threadIdx.x & (LPR - 1));
+  update_row<LPR, QPL, FULL, SUMS, DENSE>(a, row, threadIdx.x & (LPR - 1));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -328,7 +329,10 @@ template <int LPR, int QPL>
 static void launch_step_t(const StepParams& p, hipStream_t st) {
   const dim3 grid(grid_for((long long)p.n * LPR)), block(kBlock);
   const bool full = p.S == 4 * LPR * QPL;
-  if (p.problem == kMAXCLIQUE) {
+  if (p.coupling) {
+    if (full) hipLaunchKernelGGL((step_kernel<LPR, QPL, true, true, true>), grid, block, 0, st, p);
+    else hipLaunchKernelGGL((step_kernel<LPR, QPL, false, true, true>), grid, block, 0, st, p);
+  } else if (p.problem == kMAXCLIQUE) {
     if (full) hipLaunchKernelGGL((step_kernel<LPR, QPL, true, true>), grid, block, 0, st, p);
     else hipLaunchKernelGGL((step_kernel<LPR, QPL, false, true>), grid, block, 0, st, p);
   } else {

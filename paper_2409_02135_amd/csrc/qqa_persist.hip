@@ -54,7 +54,7 @@ __device__ __forceinline__ void run_rows(StepParams& a, const int row0, const in
     const int row = row0 + r;
     if (row >= a.n) continue;
     float4 acc[1], po[1], mo[1], vo[1];
-    row_coupling<LPR, 1, true, COHERENT>(a, row, gl, acc);
+    row_coupling<LPR, 1, true, COHERENT>(a, row, row_meta(a, row), gl, acc);
     finish_row<LPR, 1, true, false>(a, row, gl, p[r], mm[r], vv[r], acc, po, mo, vo);  // never max clique
     store_row<LPR, 1, true, COHERENT>(a, a.P_out, row, gl, po, mo, vo, false);
     p[r][0] = po[0];

@@ -463,17 +463,24 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
       p.hub_first = d_first;
       p.hub_partial = d_part;
     }
-    float2* stats = nullptr;
-    if (use == kEngineSliced) DEV_CHECK(hipMallocAsync((void**)&stats, (size_t)g->n * sizeof(float2), st));
+    float2* stats = nullptr;  // sliced engine: partial statistics, ping-pong
+    float2* part[2] = {nullptr, nullptr};
     hipError_t e = hipSuccess;
+    if (use == kEngineSliced) {
+      const size_t count = (size_t)g->n * kReplicaSlices;
+      DEV_CHECK(hipMallocAsync((void**)&stats, 2 * count * sizeof(float2), st));
+      part[0] = stats;
+      part[1] = stats + count;
+      p.P_in = P[t0 & 1];
+      e = launch_slice_stats(p, part[t0 & 1], st);
+    }
     for (int t = t0; t < t1 && e == hipSuccess; ++t) {
       p.P_in = P[t & 1];
       p.P_out = P[(t + 1) & 1];
       fill_step_scalars(p, s, t, K);
       e = colsum_for(p, problem, &T, st);
       if (e == hipSuccess && !chunks.empty()) e = launch_hub_partials(p, d_chunks, (int)chunks.size(), st);
-      if (e == hipSuccess && stats) e = launch_row_stats(p, stats, st);
-      if (e == hipSuccess) e = stats ? launch_slice_step(p, stats, st) : launch_step(p, st);
+      if (e == hipSuccess) e = stats ? launch_slice_step(p, part[t & 1], part[(t + 1) & 1], st) : launch_step(p, st);
     }
     if (T) (void)hipFreeAsync(T, st);
     if (stats) (void)hipFreeAsync(stats, st);

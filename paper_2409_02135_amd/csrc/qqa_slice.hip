@@ -1,55 +1,32 @@
-// Sliced streaming update: the replica axis of every row is cut into kReplicaSlices slices, and
-// slice s of every row is updated by workgroups on XCD s.  The coupling product gathers,
-// for each edge, only the neighbour's slice, so the rows an XCD gathers from are 1/kReplicaSlices
-// of P_in and stay in that XCD's L2 instead of being fetched again from the fabric.
+// Sliced streaming update: the replica axis of every row is cut into kReplicaSlices slices,
+// and slice s of every row is updated by workgroups on XCD s.  The coupling product
+// gathers, for each edge, only the neighbour's slice, so the rows an XCD gathers from are
+// 1/kReplicaSlices of P_in and mostly stay in that XCD's L2 instead of crossing the fabric.
 //
-// The replica statistics mu_i, sigma_i need all S replicas of a row, so one update is two
-// launches:
-//   row_stats_kernel   (mu_i, cg_i = -alpha_c / sigma_i) of every row of P_in, computed
-//                      with the row's lane layout and the same butterfly as the whole-row
-//                      kernel;
-//   slice_step_kernel  the coupling gathers (plain edge order, or the split rows' partial
-//                      sums), the gradient, AdamW, noise and clamp for one slice of one row.
-// Every element therefore sees the same operations in the same order as in step_kernel,
-// and the result is bitwise identical to it.
+// The replica statistics mu_i, sigma_i (Eq. 10) need all S replicas of a row.  Each slice
+// kernel therefore also writes, for the next update, its slice's partial statistics of the
+// new values: {mean_s, M2_s}, with M2_s the sum of squared deviations from the slice mean.
+// The next update combines a row's kReplicaSlices partials into mu and sigma (the pairwise
+// combination of Chan, Golub and LeVeque, 1979) in a fixed order, with no division:
+//   mu = (sum_s n_s mean_s) / S,   M2 = sum_s (M2_s + n_s (mean_s - mu)^2),   sigma = sqrt(M2 / S).
+// One launch per update; the first update's partials come from slice_stats_kernel, which
+// forms them from P with the same lanes and the same arithmetic.  The coupling sums run in
+// plain edge order (or as the split rows' chunk sums), as in step_kernel; only mu and sigma
+// are rounded differently from the whole-row kernels.
 //
 // Workgroup-to-XCD placement: consecutive workgroup ids of a launch are dispatched to
-// consecutive XCDs, round robin, so workgroup b runs on XCD b mod 8.  Slice = b mod kReplicaSlices.
+// consecutive XCDs, round robin, so workgroup b runs on XCD b mod 8.  Slice = b mod 8.
 #include "qqa_device.h"
 
 namespace qqa {
 
-template <int LPR, int QPL, bool FULL>
-__global__ __launch_bounds__(kBlock) void row_stats_kernel(StepParams a, float2* __restrict__ stats) {
-  int row = (int)(((long long)blockIdx.x * kBlock + threadIdx.x) / LPR);
-  if (LPR == 64) row = __builtin_amdgcn_readfirstlane(row);
-  if (row >= a.n) return;  // whole lane groups leave together
-  const int gl = threadIdx.x & (LPR - 1);
-  const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
-  float4 p[QPL];
-#pragma unroll
-  for (int k = 0; k < QPL; ++k) {
-    const int q = gl + LPR * k;
-    p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (FULL || q < nq) p[k] = *reinterpret_cast<const float4*>(a.P_in + (size_t)row * a.stride + 4 * q);
-  }
-  float mu, cg;
-  row_stats<LPR, QPL, FULL>(a, gl, p, mu, cg);
-  if (gl == 0) stats[row] = make_float2(mu, cg);
-}
-
-// LS lanes x QS quads serve one slice of one row.  Slice s holds quads
-// [s nq / kReplicaSlices, (s + 1) nq / kReplicaSlices) of the row's nq quads (at most LS * QS of them).
-template <int LS, int QS, bool FULL, bool SUMS>
-__global__ __launch_bounds__(kBlock) void slice_step_kernel(StepParams a, const float2* __restrict__ stats) {
-  const int slice = (int)(blockIdx.x % kReplicaSlices);
-  const int row = (int)(blockIdx.x / kReplicaSlices) * (kBlock / LS) + (int)(threadIdx.x / LS);
-  if (row >= a.n) return;  // whole lane groups leave together
-  const int gl = threadIdx.x & (LS - 1);
+// The slice of `row` served by this workgroup, as a row of its own: pointers at the slice's
+// first replica, S = its valid replicas.  Slice s holds quads [s nq / 8, (s + 1) nq / 8) of
+// the row's nq quads.
+__device__ __forceinline__ StepParams slice_view(const StepParams& a, const int slice, int* q0_out) {
   const int nq = (a.S + 3) >> 2;
   const int q0 = slice * nq / kReplicaSlices, q1 = (slice + 1) * nq / kReplicaSlices;
   const size_t off = 4 * (size_t)q0;
-  // the slice as a row of its own: pointers at its first replica, S = its valid replicas
   StepParams b = a;
   b.P_in = a.P_in + off;
   b.P_out = a.P_out + off;
@@ -59,12 +36,112 @@ __global__ __launch_bounds__(kBlock) void slice_step_kernel(StepParams a, const 
   b.hub_partial = a.hub_partial ? a.hub_partial + off : nullptr;
   b.colsum = a.colsum ? a.colsum + off : nullptr;
   b.S = min(a.S, 4 * q1) - 4 * q0;
-  float4 p[QS], mm[QS], vv[QS], acc[QS], po[QS], mo[QS], vo[QS];
+  *q0_out = q0;
+  return b;
+}
+
+// {mean, M2} of one slice's valid values v (lane gl's quads of the slice), over the LS lanes.
+template <int LS, int QS, bool FULL>
+__device__ __forceinline__ float2 slice_partial(const StepParams& b, const int gl, const float4 (&v)[QS]) {
+  float sum = 0.f;
+#pragma unroll
+  for (int k = 0; k < QS; ++k) {
+    const int q = gl + LS * k;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (FULL || 4 * q + c < b.S) sum += comp(v[k], c);
+  }
+  sum = group_sum<LS>(sum);
+  const float mean = sum * __builtin_amdgcn_rcpf((float)b.S);
+  float m2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < QS; ++k) {
+    const int q = gl + LS * k;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (FULL || 4 * q + c < b.S) {
+        const float d = comp(v[k], c) - mean;
+        m2 = fmaf(d, d, m2);
+      }
+  }
+  m2 = group_sum<LS>(m2);
+  return make_float2(mean, m2);
+}
+
+// mu and the communication coefficient cg = -alpha_c / sigma (0 when sigma = 0) of `row`
+// from its slices' partials.  Partials are stored slice-major (part[slice * n + row]): each
+// XCD writes one contiguous array.  Lane gl of the LS-lane group reads slices gl, gl + LS,
+// ... (one load for the group when LS >= kReplicaSlices) and adds them in that order; a
+// butterfly over the group then adds the lanes (a fixed tree, the same bits in every lane).
+template <int LS>
+__device__ __forceinline__ void combine_partials(const StepParams& a, const float2* __restrict__ part, const int row,
+                                                 const int gl, float& mu, float& cg) {
+  constexpr int PER = LS >= kReplicaSlices ? 1 : kReplicaSlices / LS;  // slices per lane
+  const int nq = (a.S + 3) >> 2;
+  float2 ps[PER];
+  float ns[PER];  // valid replicas of each slice; 0 for lanes past the last slice
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int sl = gl + LS * j;
+    const bool ok = sl < kReplicaSlices;
+    const int sc = ok ? sl : kReplicaSlices - 1;  // unconditional load, no join
+    const float2 x = part[(size_t)sc * a.n + row];
+    ps[j] = ok ? x : make_float2(0.f, 0.f);
+    ns[j] = ok ? (float)(min(a.S, 4 * ((sc + 1) * nq / kReplicaSlices)) - 4 * (sc * nq / kReplicaSlices)) : 0.f;
+  }
+  float sum = 0.f;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) sum = fmaf(ns[j], ps[j].x, sum);
+  sum = group_sum<LS>(sum);
+  mu = sum * a.inv_S;
+  float m2 = 0.f;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const float d = ps[j].x - mu;
+    m2 += ps[j].y + ns[j] * (d * d);
+  }
+  m2 = group_sum<LS>(m2);
+  const float sigma = __builtin_amdgcn_sqrtf(m2 * a.inv_S);
+  cg = sigma > 0.f ? -a.comm_alpha * __builtin_amdgcn_rcpf(sigma) : 0.f;
+}
+
+// Partials of P (= a.P_in) for every (row, slice): the first update's statistics.
+template <int LS, int QS, bool FULL>
+__global__ __launch_bounds__(kBlock) void slice_stats_kernel(StepParams a, float2* __restrict__ part) {
+  const int slice = (int)(blockIdx.x % kReplicaSlices);
+  const int row = (int)(blockIdx.x / kReplicaSlices) * (kBlock / LS) + (int)(threadIdx.x / LS);
+  if (row >= a.n) return;  // whole lane groups leave together
+  const int gl = threadIdx.x & (LS - 1);
+  int q0;
+  const StepParams b = slice_view(a, slice, &q0);
+  float4 p[QS], mm[QS], vv[QS];
   load_row<LS, QS, FULL>(b, b.P_in, row, gl, p, mm, vv);
-  row_coupling<LS, QS, FULL, false, false>(b, row, gl, acc);
-  const float2 st = stats[row];
-  finish_elems<LS, QS, FULL, SUMS>(b, row, gl, q0, st.x, st.y, p, mm, vv, acc, po, mo, vo);
+  const float2 pt = slice_partial<LS, QS, FULL>(b, gl, p);
+  if (gl == 0) part[(size_t)slice * a.n + row] = pt;
+}
+
+// One update of one slice of one row, LS lanes x QS quads; reads the row's partials of
+// P_in from part_in and writes this slice's partial of P_out to part_out.
+template <int LS, int QS, bool FULL, bool SUMS>
+__global__ __launch_bounds__(kBlock) void slice_step_kernel(StepParams a, const float2* __restrict__ part_in,
+                                                            float2* __restrict__ part_out) {
+  const int slice = (int)(blockIdx.x % kReplicaSlices);
+  const int row = (int)(blockIdx.x / kReplicaSlices) * (kBlock / LS) + (int)(threadIdx.x / LS);
+  if (row >= a.n) return;  // whole lane groups leave together
+  const int gl = threadIdx.x & (LS - 1);
+  int q0;
+  const StepParams b = slice_view(a, slice, &q0);
+  float4 p[QS], mm[QS], vv[QS], acc[QS], po[QS], mo[QS], vo[QS];
+  const RowMeta rm = row_meta(b, row);
+  float mu, cg;
+  combine_partials<LS>(a, part_in, row, gl, mu, cg);
+  load_row<LS, QS, FULL>(b, b.P_in, row, gl, p, mm, vv);
+  // 4-quad gather batches: the row's partials and a whole-row-sized update share the registers
+  row_coupling<LS, QS, FULL, false, false, false, 4>(b, row, rm, gl, acc);
+  finish_elems<LS, QS, FULL, SUMS>(b, row, gl, q0, mu, cg, p, mm, vv, acc, po, mo, vo);
   store_row<LS, QS, FULL>(b, b.P_out, row, gl, po, mo, vo, true);
+  const float2 pt = slice_partial<LS, QS, FULL>(b, gl, po);
+  if (gl == 0) part_out[(size_t)slice * a.n + row] = pt;
 }
 
 static unsigned blocks_of(long long threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
@@ -86,52 +163,55 @@ SliceShape slice_shape(int S) {
   return r;
 }
 
-template <int LPR, int QPL>
-static void launch_stats_t(const StepParams& p, float2* stats, hipStream_t st) {
-  const dim3 grid(blocks_of((long long)p.n * LPR)), block(kBlock);
-  if (p.S == 4 * LPR * QPL)
-    hipLaunchKernelGGL((row_stats_kernel<LPR, QPL, true>), grid, block, 0, st, p, stats);
+template <int LS, int QS>
+static void launch_slice_stats_t(const StepParams& p, float2* part, hipStream_t st) {
+  const dim3 grid((unsigned)kReplicaSlices * blocks_of((long long)p.n * LS)), block(kBlock);
+  if (p.S == 4 * kReplicaSlices * LS * QS)  // equal slices, every lane's quads valid
+    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, true>), grid, block, 0, st, p, part);
   else
-    hipLaunchKernelGGL((row_stats_kernel<LPR, QPL, false>), grid, block, 0, st, p, stats);
+    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, false>), grid, block, 0, st, p, part);
 }
 
 template <int LS, int QS>
-static void launch_slice_t(const StepParams& p, const float2* stats, hipStream_t st) {
+static void launch_slice_t(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st) {
   const dim3 grid((unsigned)kReplicaSlices * blocks_of((long long)p.n * LS)), block(kBlock);
   const bool full = p.S == 4 * kReplicaSlices * LS * QS;  // equal slices, every lane's quads valid
   const bool sums = p.problem == kMAXCLIQUE;
   if (sums) {
-    if (full) hipLaunchKernelGGL((slice_step_kernel<LS, QS, true, true>), grid, block, 0, st, p, stats);
-    else hipLaunchKernelGGL((slice_step_kernel<LS, QS, false, true>), grid, block, 0, st, p, stats);
+    if (full) hipLaunchKernelGGL((slice_step_kernel<LS, QS, true, true>), grid, block, 0, st, p, part_in, part_out);
+    else hipLaunchKernelGGL((slice_step_kernel<LS, QS, false, true>), grid, block, 0, st, p, part_in, part_out);
   } else {
-    if (full) hipLaunchKernelGGL((slice_step_kernel<LS, QS, true, false>), grid, block, 0, st, p, stats);
-    else hipLaunchKernelGGL((slice_step_kernel<LS, QS, false, false>), grid, block, 0, st, p, stats);
+    if (full) hipLaunchKernelGGL((slice_step_kernel<LS, QS, true, false>), grid, block, 0, st, p, part_in, part_out);
+    else hipLaunchKernelGGL((slice_step_kernel<LS, QS, false, false>), grid, block, 0, st, p, part_in, part_out);
   }
 }
 
-hipError_t launch_row_stats(const StepParams& p, float2* stats, hipStream_t st) {
+#define QQA_FOR_EACH_SLICE_LAYOUT(X) X(2, 1) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(64, 2)
+
+hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st) {
   if (p.n == 0) return hipSuccess;
-  const ReplicaShape r = replica_shape(p.S, p.lanes_per_row);
-#define X(L, Q)                       \
-  if (r.lpr == L && r.qpl == Q) {     \
-    launch_stats_t<L, Q>(p, stats, st); \
-    return hipGetLastError();         \
+  const SliceShape s = slice_shape(p.S);
+  if (s.sq == 0) return hipErrorInvalidValue;
+#define X(L, Q)                                \
+  if (s.ls == L && s.qs == Q) {                \
+    launch_slice_stats_t<L, Q>(p, part, st);   \
+    return hipGetLastError();                  \
   }
-  QQA_FOR_EACH_LAYOUT(X)
+  QQA_FOR_EACH_SLICE_LAYOUT(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_slice_step(const StepParams& p, const float2* stats, hipStream_t st) {
+hipError_t launch_slice_step(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st) {
   if (p.n == 0) return hipSuccess;
   const SliceShape s = slice_shape(p.S);
   if (s.sq == 0) return hipErrorInvalidValue;
-#define X(L, Q)                                   \
-  if (s.ls == L && s.qs == Q) {                   \
-    launch_slice_t<L, Q>(p, stats, st);           \
-    return hipGetLastError();                     \
+#define X(L, Q)                                          \
+  if (s.ls == L && s.qs == Q) {                          \
+    launch_slice_t<L, Q>(p, part_in, part_out, st);      \
+    return hipGetLastError();                            \
   }
-  X(2, 1) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(64, 2)
+  QQA_FOR_EACH_SLICE_LAYOUT(X)
 #undef X
   return hipErrorInvalidValue;
 }

@@ -1,8 +1,10 @@
-"""The sliced streaming engine (replica axis cut into 8 slices, one per XCD; row statistics
-computed by a launch of their own) gives the same bits as the whole-row streaming engine
-over many updates: full and ragged slices, the smallest and largest slice widths, split
-(hub) rows, max-cut weights, max clique's per-replica sums, the Langevin rule and
-non-default lane layouts.  One update matches the oracle, and a context runs it by policy."""
+"""The sliced streaming engine (replica axis cut into 8 slices, one per XCD; replica statistics
+combined from the slices' partials, which each update leaves for the next): one update
+matches the oracle, from a given state and from a state the engine reached itself (so the
+partials it wrote are checked); a run interrupted and resumed gives the same bits as one
+run through; one update agrees with the whole-row engine to rounding.  Full and ragged
+slices, the narrowest and widest slice widths, split (hub) rows, max-cut weights, max
+clique's per-replica sums and the Langevin rule.  A context runs it by policy."""
 
 import numpy as np
 import pytest
@@ -21,7 +23,7 @@ def qqa():
     return q
 
 
-def run(q, g, problem, S, t0, t1, K, seed, engine, lanes=0, sched=None, state=None):
+def run(q, g, problem, S, t0, t1, K, seed, engine, sched=None, state=None):
     d = torch.device("cuda")
     stride = q.qqa_replica_stride(S)
     sched = sched or q.schedule(problem, g["n"])
@@ -33,7 +35,7 @@ def run(q, g, problem, S, t0, t1, K, seed, engine, lanes=0, sched=None, state=No
         P = [P0, torch.full_like(P0, -1.0)]
     else:
         P, m, v = [x.clone() for x in state[0]], state[1].clone(), state[2].clone()
-    q.qqa_dev_run(q.DevGraph(g), problem, sched, S, t0, t1, K, seed, P[0], P[1], m, v, engine, lanes)
+    q.qqa_dev_run(q.DevGraph(g), problem, sched, S, t0, t1, K, seed, P[0], P[1], m, v, engine)
     torch.cuda.synchronize()
     return P, m, v
 
@@ -43,49 +45,74 @@ def rb_graph():
 
 
 CASES = [
-    # name, graph, problem, S, lanes (both engines)
-    ("er20000_S256_mis", lambda: qi.erdos_renyi(20000, 5.0, 0), "mis", 256, 0),
-    ("er20000_S256_mis_lanes32", lambda: qi.erdos_renyi(20000, 5.0, 0), "mis", 256, 32),
-    ("ba5000_S128_maxcut_hubs", lambda: qi.pm1_weights(qi.barabasi_albert(5000, 4, 1), 1), "maxcut", 128, 0),
-    ("er4000_S100_mis_ragged", lambda: qi.erdos_renyi(4000, 8.0, 2), "mis", 100, 0),
-    ("er4000_S61_mis_narrowest", lambda: qi.erdos_renyi(4000, 8.0, 3), "mis", 61, 0),
-    ("er3000_S1000_maxcut", lambda: qi.pm1_weights(qi.erdos_renyi(3000, 6.0, 4), 2), "maxcut", 1000, 0),
-    ("rrg2000_S4096_mis_widest", lambda: qi.random_regular(2000, 3, 5), "mis", 4096, 0),
-    ("rb_S64_maxclique", rb_graph, "maxclique", 64, 0),
+    # name, graph, problem, S
+    ("er20000_S256_mis", lambda: qi.erdos_renyi(20000, 5.0, 0), "mis", 256),
+    ("ba5000_S128_maxcut_hubs", lambda: qi.pm1_weights(qi.barabasi_albert(5000, 4, 1), 1), "maxcut", 128),
+    ("er4000_S100_mis_ragged", lambda: qi.erdos_renyi(4000, 8.0, 2), "mis", 100),
+    ("er4000_S61_mis_narrowest", lambda: qi.erdos_renyi(4000, 8.0, 3), "mis", 61),
+    ("er3000_S1000_maxcut", lambda: qi.pm1_weights(qi.erdos_renyi(3000, 6.0, 4), 2), "maxcut", 1000),
+    ("rrg2000_S4096_mis_widest", lambda: qi.random_regular(2000, 3, 5), "mis", 4096),
+    ("rb_S64_maxclique", rb_graph, "maxclique", 64),
+    ("rb_S1000_maxclique", rb_graph, "maxclique", 1000),
 ]
 
 
-@pytest.mark.parametrize("name,make,problem,S,lanes", CASES, ids=[c[0] for c in CASES])
-def test_sliced_matches_streaming_bitwise(name, make, problem, S, lanes):
+@pytest.mark.parametrize("name,make,problem,S", CASES, ids=[c[0] for c in CASES])
+def test_sliced_resume_is_bitwise_continuous_and_deterministic(name, make, problem, S):
     q = qqa()
     g = make()
     K, seed = 200, 7
-    a = run(q, g, problem, S, 0, 23, K, seed, "stream", lanes)
-    b = run(q, g, problem, S, 0, 23, K, seed, "sliced", lanes)
-    for x, y in zip([a[0][1], a[1], a[2]], [b[0][1], b[1], b[2]]):
+    a = run(q, g, problem, S, 0, 23, K, seed, "sliced")
+    a2 = run(q, g, problem, S, 0, 23, K, seed, "sliced")
+    for x, y in zip([a[0][1], a[1], a[2]], [a2[0][1], a2[1], a2[2]]):
         assert torch.equal(x, y), name
-    # resumed mid-schedule from the streamed state
-    c = run(q, g, problem, S, 23, 40, K, seed, "sliced", lanes, state=a)
-    d = run(q, g, problem, S, 0, 40, K, seed, "stream", lanes)
+    # resumed mid-schedule: the first update's partials are formed from P exactly as the
+    # previous update would have left them
+    c = run(q, g, problem, S, 23, 40, K, seed, "sliced", state=a)
+    d = run(q, g, problem, S, 0, 40, K, seed, "sliced")
     for x, y in zip([c[0][0], c[1], c[2]], [d[0][0], d[1], d[2]]):
         assert torch.equal(x, y), name
 
 
-def test_sliced_langevin_matches_streaming_bitwise():
+@pytest.mark.parametrize("name,make,problem,S", CASES, ids=[c[0] for c in CASES])
+def test_sliced_one_update_agrees_with_whole_rows(name, make, problem, S):
     q = qqa()
-    g = qi.erdos_renyi(5000, 6.0, 8)
-    sched = q.schedule("mis", g["n"])
-    sched.rule = q.QQA_STEP_LANGEVIN
-    a = run(q, g, "mis", 160, 0, 15, 100, 3, "stream", sched=sched)
-    b = run(q, g, "mis", 160, 0, 15, 100, 3, "sliced", sched=sched)
-    assert torch.equal(a[0][1], b[0][1])
+    g = make()
+    a = run(q, g, problem, S, 0, 1, 100, 3, "stream")
+    b = run(q, g, problem, S, 0, 1, 100, 3, "sliced")
+    # the replica statistics are rounded differently; everything else is the same arithmetic.
+    # AdamW's first step moves p by -lr g / (|g| + eps): where |g| is tiny that step turns
+    # a rounding-level change of g into a visible one, so a handful of elements may differ
+    # more (the oracle tests bound those by the step's sensitivity)
+    dP = (a[0][1] - b[0][1]).abs()
+    assert int((dP > 1e-5).sum()) <= max(4, dP.numel() // 100000), (name, float(dP.max()))
+    assert float(dP.max()) <= 2 * 0.1 + 1e-6  # at most the size of two steps
+    assert torch.allclose(a[1], b[1], rtol=1e-3, atol=1e-7) and torch.allclose(a[2], b[2], rtol=1e-3, atol=1e-9)
 
 
-def test_sliced_one_update_matches_oracle(orc):
+def _check_against_oracle(q, orc, label, g, problem, sched, S, t, K, seed, state_in, gpu_out):
     from test_gpu_parity import check_step, oracle_params, step_sensitivity
+    P, m, v = (x[:, :S].astype(np.float32) for x in state_in)
+    ref = orc.step(oracle_params(orc, q, sched, problem), g, t, K, seed, P, m, v)
+    adam = sched.rule == 0
+    sens = step_sensitivity(ref, m.astype(np.float64), v.astype(np.float64), t, sched, adam)
+    check_step(label, gpu_out, ref, S, adam, sched.beta1, sched.beta2, sens, float(np.float32(sched.comm_alpha)))
+
+
+ORACLE_CASES = [
+    ("ba3000_S200_maxcut_hubs", lambda: qi.pm1_weights(qi.barabasi_albert(3000, 4, 2), 3), "maxcut", 200),
+    ("er3000_S256_mis", lambda: qi.erdos_renyi(3000, 6.0, 5), "mis", 256),
+    ("er1000_S1000_mis_ragged", lambda: qi.erdos_renyi(1000, 8.0, 6), "mis", 1000),
+    ("er800_S61_mis", lambda: qi.erdos_renyi(800, 5.0, 7), "mis", 61),
+    ("rb_S300_maxclique", rb_graph, "maxclique", 300),
+]
+
+
+@pytest.mark.parametrize("name,make,problem,S", ORACLE_CASES, ids=[c[0] for c in ORACLE_CASES])
+def test_sliced_one_update_matches_oracle(orc, name, make, problem, S):
     q = qqa()
-    g = qi.pm1_weights(qi.barabasi_albert(3000, 4, 2), 3)
-    S, K, seed, t = 200, 100, 9, 17
+    g = make()
+    K, seed, t = 100, 9, 17
     P, m, v = qi.synthetic_state(g["n"], S, seed=4)
     d = torch.device("cuda")
     stride = q.qqa_replica_stride(S)
@@ -94,14 +121,39 @@ def test_sliced_one_update_matches_oracle(orc):
     if t % 2:
         Pt = Pt[::-1]
     mt, vt = torch.as_tensor(pad(m), device=d), torch.as_tensor(pad(v), device=d)
-    sched = q.schedule("maxcut", g["n"])
-    q.qqa_dev_run(q.DevGraph(g), "maxcut", sched, S, t, t + 1, K, seed, Pt[0], Pt[1], mt, vt, "sliced")
+    sched = q.schedule(problem, g["n"])
+    q.qqa_dev_run(q.DevGraph(g), problem, sched, S, t, t + 1, K, seed, Pt[0], Pt[1], mt, vt, "sliced")
     torch.cuda.synchronize()
     gpu = (Pt[(t + 1) & 1].cpu().numpy(), mt.cpu().numpy(), vt.cpu().numpy())
-    ref = orc.step(oracle_params(orc, q, sched, "maxcut"), g, t, K, seed, P, m, v)
-    m64, v64 = m.astype(np.float64), v.astype(np.float64)
-    sens = step_sensitivity(ref, m64, v64, t, sched, True)
-    check_step("sliced BA3000 S200", gpu, ref, S, True, sched.beta1, sched.beta2, sens)
+    _check_against_oracle(q, orc, f"sliced {name}", g, problem, sched, S, t, K, seed, (pad(P), pad(m), pad(v)), gpu)
+
+
+@pytest.mark.parametrize("name,make,problem,S", ORACLE_CASES[:3], ids=[c[0] for c in ORACLE_CASES[:3]])
+def test_sliced_partials_from_its_own_updates_match_oracle(orc, name, make, problem, S):
+    """Update t of a run from the start uses the partial statistics update t - 1 wrote."""
+    q = qqa()
+    g = make()
+    K, seed, t = 100, 11, 6
+    sched = q.schedule(problem, g["n"])
+    before = run(q, g, problem, S, 0, t, K, seed, "sliced")
+    after = run(q, g, problem, S, 0, t + 1, K, seed, "sliced")
+    state_in = (before[0][t & 1].cpu().numpy(), before[1].cpu().numpy(), before[2].cpu().numpy())
+    gpu = (after[0][(t + 1) & 1].cpu().numpy(), after[1].cpu().numpy(), after[2].cpu().numpy())
+    _check_against_oracle(q, orc, f"sliced run {name}", g, problem, sched, S, t, K, seed, state_in, gpu)
+
+
+def test_sliced_langevin_agrees_with_whole_rows():
+    q = qqa()
+    g = qi.erdos_renyi(5000, 6.0, 8)
+    sched = q.schedule("mis", g["n"])
+    sched.rule = q.QQA_STEP_LANGEVIN
+    a = run(q, g, "mis", 160, 0, 1, 100, 3, "stream", sched=sched)
+    b = run(q, g, "mis", 160, 0, 1, 100, 3, "sliced", sched=sched)
+    assert float((a[0][1] - b[0][1]).abs().max()) <= 1e-5  # Langevin: p - lr g, well conditioned
+    c = run(q, g, "mis", 160, 0, 9, 100, 3, "sliced", sched=sched)
+    d = run(q, g, "mis", 160, 0, 4, 100, 3, "sliced", sched=sched)
+    e = run(q, g, "mis", 160, 4, 9, 100, 3, "sliced", sched=sched, state=d)
+    assert torch.equal(c[0][1], e[0][1])
 
 
 def test_sliced_rejects_narrow_replica_counts():
@@ -111,26 +163,30 @@ def test_sliced_rejects_narrow_replica_counts():
     assert e.value.code == q.QQA_E_ARG
 
 
-def test_context_sliced_policy_same_results():
+def test_context_sliced_policy():
+    from test_gpu_solve import objective_of
     q = qqa()
     ctx = q.Context(0)
-    for g, problem, S in [(qi.pm1_weights(qi.barabasi_albert(6000, 4, 1), 1), "maxcut", 128),
-                          (qi.erdos_renyi(20000, 5.0, 0), "mis", 256),
-                          (rb_graph(), "maxclique", 96)]:
+    for g, problem, S in [(qi.pm1_weights(qi.barabasi_albert(6000, 4, 1), 1), "maxcut", 256),
+                          (qi.erdos_renyi(20000, 5.0, 0), "mis", 256)]:
         gid = ctx.upload(g, problem)
         ctx.set_engine("sliced")
         a = ctx.poll(ctx.solve_resident(gid, g["n"], problem, S, 150, 3))
-        ctx.set_engine("stream")
         b = ctx.poll(ctx.solve_resident(gid, g["n"], problem, S, 150, 3))
         ctx.release(gid)
-        assert a["engine"] == "sliced" and b["engine"] == "stream"
+        assert a["engine"] == "sliced" and a["kernel_us"] > 0
         assert np.array_equal(a["obj"], b["obj"]) and np.array_equal(a["best_x"], b["best_x"])
-        assert a["kernel_us"] > 0
-    # automatic policy: sliced for few rows with many replicas, else whole rows
+        assert a["best_objective"] == objective_of(g, a["best_x"], problem)
+    # automatic policy: slices of whole 128-byte lines whose share of P fits an XCD's L2
     ctx.set_engine("auto")
-    for g, S, engine in [(qi.erdos_renyi(1000, 8.0, 1), 1000, "sliced"), (qi.erdos_renyi(1000, 8.0, 1), 256, "stream"),
-                         (qi.erdos_renyi(2000, 8.0, 1), 1000, "stream")]:
+    for g, S, engine in [(qi.erdos_renyi(2000, 8.0, 1), 256, "sliced"), (qi.erdos_renyi(2000, 8.0, 1), 128, "stream"),
+                         (qi.erdos_renyi(1000, 8.0, 1), 1000, "sliced"), (qi.erdos_renyi(30000, 4.0, 1), 256, "stream")]:
         gid = ctx.upload(g, "mis")
-        assert ctx.poll(ctx.solve_resident(gid, g["n"], "mis", S, 50, 1))["engine"] == engine
+        assert ctx.poll(ctx.solve_resident(gid, g["n"], "mis", S, 50, 1))["engine"] == engine, (g["n"], S)
         ctx.release(gid)
+    g = rb_graph()
+    gid = ctx.upload(g, "maxclique")
+    r = ctx.poll(ctx.solve_resident(gid, g["n"], "maxclique", 1000, 400, 2))
+    ctx.release(gid)
+    assert r["engine"] == "sliced" and r["feasible"] and r["best_size_or_cut"] >= 18  # planted clique: 20
     ctx.close()
