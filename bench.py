@@ -363,12 +363,15 @@ def main():
     else:
         abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
         achieved = abytes / (step_us * 1e-6) / 1e9
-        sliced = results[0]["engine"] == "sliced"
-        roofline = {"bound": "hbm", "kernel": "slice_step_kernel" if sliced else "step_kernel",
+        engine = results[0]["engine"]
+        sliced = engine == "sliced"
+        kernel = {"sliced": "slice_step_kernel", "compact": "compact_step_kernel"}.get(engine, "step_kernel")
+        roofline = {"bound": "hbm", "kernel": kernel,
                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                     "traffic": (traffic_from_profiles("slice_step_traffic.json", SLICE_SOURCES) if sliced else
-                                traffic_from_profiles("step_kernel_traffic.json", DEVICE_SOURCES)),
+                                traffic_from_profiles("step_kernel_traffic.json", DEVICE_SOURCES)
+                                if kernel == "step_kernel" else None),
                     "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes,
                     "sampled_launch_us": float(np.mean([r["kernel_us"] for r in results]))}
 

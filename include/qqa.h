@@ -160,14 +160,18 @@ typedef struct {
  * another order).  SLICED performs the same arithmetic except for the replica statistics,
  * which it combines from the slices' partials: its results agree with the others to
  * rounding after one update, and its trajectories then diverge from theirs as any two
- * roundings of the method do.  It is deterministic and resumable like the others. */
+ * roundings of the method do.  It is deterministic and resumable like the others.
+ * COMPACT: one replica per variable (S = 1, sparse MIS or max-cut): P, m, v held as one
+ * float per variable instead of a padded quad, one lane per variable, one launch per
+ * update; bitwise STREAM's results at one lane per row (the default layout for S = 1). */
 typedef enum {
     QQA_ENGINE_AUTO = -1,
     QQA_ENGINE_STREAM = 0,
     QQA_ENGINE_PERSISTENT = 1,
     QQA_ENGINE_LDS_BLOCK = 2,
     QQA_ENGINE_BATCH = 3,
-    QQA_ENGINE_SLICED = 4
+    QQA_ENGINE_SLICED = 4,
+    QQA_ENGINE_COMPACT = 5
 } qqa_engine;
 
 /* device: HIP ordinal.  hbm_budget_bytes: cap on the device memory the context may
@@ -221,17 +225,20 @@ int qqa_solve_batch(qqa_ctx *c, int32_t count, const qqa_graph_id *graphs, const
 int qqa_set_replica_layout(qqa_ctx *c, int32_t S, int32_t lanes_per_row);
 
 /* Autotuner: time every supported layout for S on an uploaded graph (a few updates each,
- * on scratch state), keep the fastest for S in this context and return it in
- * *lanes_per_row (may be NULL). */
+ * on scratch state, with the streaming update kernel, or the compact one for S = 1 under
+ * the automatic or COMPACT policy), keep the fastest for S in this context and return it
+ * in *lanes_per_row (may be NULL). */
 int qqa_autotune(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, int32_t S, int32_t *lanes_per_row);
 
 /* Engine policy of a context for single solves: QQA_ENGINE_AUTO (default) runs an instance
  * on LDS_BLOCK when it qualifies (one quad per lane in a full-width layout, no rows split
- * into chunks, P fits in one workgroup's LDS), else SLICED when the graph is sparse,
- * S >= 256 and P (n x stride floats) is at most 24 MiB, else STREAM;
+ * into chunks, P fits in one workgroup's LDS), else COMPACT for S = 1 (sparse MIS or
+ * max-cut), else SLICED when the graph is sparse, S >= 256 and P (n x stride floats) is at
+ * most 24 MiB, else STREAM;
  * QQA_ENGINE_PERSISTENT runs the register-resident engine when the instance fits on chip
- * (else STREAM); QQA_ENGINE_LDS_BLOCK / QQA_ENGINE_SLICED / QQA_ENGINE_STREAM force those
- * engines where possible.  QQA_E_ARG for BATCH or an unknown value. */
+ * (else STREAM); QQA_ENGINE_LDS_BLOCK / QQA_ENGINE_SLICED / QQA_ENGINE_COMPACT /
+ * QQA_ENGINE_STREAM force those engines where possible.  QQA_E_ARG for BATCH or an unknown
+ * value. */
 int qqa_set_engine(qqa_ctx *c, qqa_engine policy);
 
 /* Wait up to timeout_us (0 = do not wait, < 0 = forever) for a request.  Returns QQA_OK

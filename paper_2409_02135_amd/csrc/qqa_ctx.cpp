@@ -131,6 +131,7 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
   if (nchunks) get((void**)&r->hub_partial, r->hub_bytes);
   if (r->problem == QQA_MAXCLIQUE) get((void**)&r->colsum, (size_t)r->shape.stride * sizeof(unsigned long long));
   if (r->engine == kEngineSliced) get((void**)&r->stats, 2 * (size_t)r->n * kReplicaSlices * sizeof(float2));
+  if (r->engine == kEngineCompact) get((void**)&r->compact, 4 * (size_t)r->n * sizeof(float));
   if (r->colors > 0) {
     get((void**)&r->cat_sigma, state);
     get((void**)&r->cat_grad, state);
@@ -146,7 +147,7 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
   get((void**)&r->out_dev, r->out_size);
   if (e == hipSuccess) e = c->hpool.get(r->out_size, (void**)&r->out_host);
   for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&r->ev[i]);
-  if ((r->engine == kEngineStream || r->engine == kEngineSliced) && r->K > 0) {
+  if ((r->engine == kEngineStream || r->engine == kEngineSliced || r->engine == kEngineCompact) && r->K > 0) {
     // sampled updates t with t % every == every / 2, at most kProbes of them
     r->probe_every = std::max(1, (r->K + kProbes - 1) / kProbes);
     const int samples = (r->K - r->probe_every / 2 + r->probe_every - 1) / r->probe_every;
@@ -182,6 +183,8 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
   r->colsum = nullptr;
   if (r->stats) c->dpool.put(r->stats, 2 * (size_t)r->n * kReplicaSlices * sizeof(float2));
   r->stats = nullptr;
+  if (r->compact) c->dpool.put(r->compact, 4 * (size_t)r->n * sizeof(float));
+  r->compact = nullptr;
   if (r->cat_sigma) c->dpool.put(r->cat_sigma, state);
   if (r->cat_grad) c->dpool.put(r->cat_grad, state);
   if (r->cat_colors) c->dpool.put(r->cat_colors, (size_t)r->n * r->shape.stride);
@@ -295,6 +298,12 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
     const int allow = g.dense || problem == QQA_MAXCLIQUE ? 0 : c->engine_policy < 0 ? 1 : (c->engine_policy == QQA_ENGINE_LDS_BLOCK ? 1 :
                                                  (c->engine_policy == QQA_ENGINE_PERSISTENT ? 2 : 0));
     r->engine = allow ? persistent_plan(probe, g.nchunks > 0, allow, &r->rows_per_group, &r->grid) : kEngineStream;
+    // one replica per variable: compact state (asked for, or by default)
+    if (r->engine == kEngineStream && !g.dense && S == 1 && problem != QQA_MAXCLIQUE &&
+        (c->engine_policy == QQA_ENGINE_COMPACT || c->engine_policy < 0)) {
+      r->engine = kEngineCompact;
+      r->footprint += 4 * (size_t)g.n * sizeof(float);
+    }
     // a streaming sparse solve runs sliced when asked for, or by default when its slices
     // are whole cache lines and fit the XCDs' L2
     if (r->engine == kEngineStream && !g.dense && slice_shape(S).sq > 0 &&
@@ -302,7 +311,7 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
       r->engine = kEngineSliced;
       r->footprint += 2 * (size_t)g.n * kReplicaSlices * sizeof(float2);
     }
-    if (r->engine != kEngineStream && r->engine != kEngineSliced) {
+    if (r->engine == kEnginePersistent || r->engine == kEngineLdsBlock) {
       r->table_bytes = (size_t)steps * sizeof(float4);
       r->footprint += r->table_bytes;
     }
@@ -333,7 +342,27 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   if (e == hipSuccess) e = launch_init(seed, g.n, S, r->P[0], r->m, r->v, c->stream);
   if (e == hipSuccess) e = hipEventRecord(r->ev[1], c->stream);
   StepParams p = request_step_params(r.get(), g);
-  if (r->engine == kEngineStream || r->engine == kEngineSliced) {
+  if (r->engine == kEngineCompact) {
+    const size_t n = (size_t)g.n;
+    float* Pc[2] = {r->compact, r->compact + n};
+    float* mc = r->compact + 2 * n;
+    float* vc = r->compact + 3 * n;
+    const int stride = r->shape.stride;
+    if (e == hipSuccess) e = launch_compact_pack(r->P[0], stride, g.n, Pc[0], c->stream);
+    if (r->m && e == hipSuccess) e = launch_compact_pack(r->m, stride, g.n, mc, c->stream);  // AdamW only
+    if (r->v && e == hipSuccess) e = launch_compact_pack(r->v, stride, g.n, vc, c->stream);
+    const int every = r->probe_every;
+    for (int t = 0; t < steps && e == hipSuccess; ++t) {
+      fill_step_scalars(p, r->sched, t, steps);
+      const size_t pi = 2 * (size_t)(t / every);
+      const bool probe = t % every == every / 2 && pi + 1 < r->probe.size();
+      if (probe) e = hipEventRecord(r->probe[pi], c->stream);
+      if (e == hipSuccess) e = launch_compact_step(p, Pc[t & 1], Pc[(t + 1) & 1], mc, vc, c->stream);
+      if (probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
+    }
+    // the final state in the padded layout, for the exact evaluation
+    if (e == hipSuccess) e = launch_compact_unpack(Pc[steps & 1], g.n, stride, r->P[steps & 1], c->stream);
+  } else if (r->engine == kEngineStream || r->engine == kEngineSliced) {
     const bool sliced = r->engine == kEngineSliced;
     float2* part[2] = {r->stats, r->stats + (size_t)g.n * kReplicaSlices};
     if (sliced && e == hipSuccess) {
@@ -633,7 +662,7 @@ int qqa_solve_resident(qqa_ctx* c, qqa_graph_id g, qqa_problem problem, const qq
 
 int qqa_set_engine(qqa_ctx* c, qqa_engine policy) {
   if (!c) return QQA_E_ARG;
-  if (policy < QQA_ENGINE_AUTO || policy > QQA_ENGINE_SLICED || policy == QQA_ENGINE_BATCH)
+  if (policy < QQA_ENGINE_AUTO || policy > QQA_ENGINE_COMPACT || policy == QQA_ENGINE_BATCH)
     return set_err(c, QQA_E_ARG, "unknown engine policy");
   c->engine_policy = policy;
   return QQA_OK;
@@ -663,7 +692,12 @@ int qqa_autotune(qqa_ctx* c, qqa_graph_id gid, qqa_problem problem, int32_t S, i
   r.S = S;
   r.n = g.n;
   r.shape = replica_shape(S);
-  const size_t fp = request_footprint(g.n, S, r.sched.rule, problem) + (size_t)g.nchunks * r.shape.stride * sizeof(float);
+  // one replica per variable: time the compact engine, which the context then runs
+  const bool compact = S == 1 && problem != QQA_MAXCLIQUE &&
+                       (c->engine_policy < 0 || c->engine_policy == QQA_ENGINE_COMPACT);
+  if (compact) r.engine = kEngineCompact;
+  const size_t fp = request_footprint(g.n, S, r.sched.rule, problem) + (size_t)g.nchunks * r.shape.stride * sizeof(float) +
+                    (compact ? 4 * (size_t)g.n * sizeof(float) : 0);
   if (c->in_use + fp > c->budget) return set_err(c, QQA_E_NOMEM, "no budget left for tuning state");
   int rc = alloc_request_buffers(c, &r, &c->err, g.nchunks);
   if (rc) return rc;
@@ -686,6 +720,11 @@ int qqa_autotune(qqa_ctx* c, qqa_graph_id gid, qqa_problem problem, int32_t S, i
   hipError_t e = launch_init(1, g.n, S, r.P[0], r.m, r.v, c->stream);
   // max clique: valid per-replica sums for the timed updates (their values do not matter)
   if (e == hipSuccess && r.colsum) e = launch_colsum(r.P[0], g.n, r.shape.stride, r.colsum, c->stream);
+  const size_t n = (size_t)g.n;
+  float* Pc[2] = {r.compact, r.compact ? r.compact + n : nullptr};
+  if (compact && e == hipSuccess) e = launch_compact_pack(r.P[0], r.shape.stride, g.n, Pc[0], c->stream);
+  if (compact && r.m && e == hipSuccess) e = launch_compact_pack(r.m, r.shape.stride, g.n, r.compact + 2 * n, c->stream);
+  if (compact && r.v && e == hipSuccess) e = launch_compact_pack(r.v, r.shape.stride, g.n, r.compact + 3 * n, c->stream);
   int last_lpr = -1;
   for (int want = 1; want <= 64 && e == hipSuccess; want <<= 1) {
     const ReplicaShape sh = replica_shape(S, want);
@@ -698,6 +737,10 @@ int qqa_autotune(qqa_ctx* c, qqa_graph_id gid, qqa_problem problem, int32_t S, i
       p.P_in = r.P[t & 1];
       p.P_out = r.P[(t + 1) & 1];
       fill_step_scalars(p, r.sched, t, warm + timed);
+      if (compact) {
+        e = launch_compact_step(p, Pc[t & 1], Pc[(t + 1) & 1], r.compact + 2 * n, r.compact + 3 * n, c->stream);
+        continue;
+      }
       if (g.nchunks) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
       if (e == hipSuccess) e = launch_step(p, c->stream);
     }

@@ -64,6 +64,7 @@ struct Request {
   float* coupling = nullptr;     // dense graphs: n x stride coupling product
   unsigned long long* colsum = nullptr;  // max clique: per-replica sums of P (2^-32 fixed point)
   float2* stats = nullptr;               // sliced engine: 2 x n x 8 partial statistics (ping-pong)
+  float* compact = nullptr;              // compact engine: P[2], m, v as n floats each
   // graph coloring: colours K; state rows are n * K; sigma and G (n * K x stride), colours
   // of every replica (n x stride bytes)
   int colors = 0;

@@ -142,7 +142,7 @@ struct PersistParams {
   int32_t t0, t1;
   unsigned* bar;                // [0] arrivals (zero before the launch), [1] abort flag
 };
-enum PersistEngine { kEngineStream = 0, kEnginePersistent = 1, kEngineLdsBlock = 2, kEngineSliced = 4 };
+enum PersistEngine { kEngineStream = 0, kEnginePersistent = 1, kEngineLdsBlock = 2, kEngineSliced = 4, kEngineCompact = 5 };
 // Which engine can run this instance (FULL layouts with one quad per lane, no split
 // rows); `allow` is a mask (1: one workgroup with P in LDS, 2: many workgroups with state
 // in registers).  Fills rows per group and the grid for the chosen one.
@@ -207,6 +207,14 @@ struct SliceShape {
 };
 SliceShape slice_shape(int S);
 hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st);
+
+// Compact engine (S = 1, sparse MIS or max-cut): P, m, v as n floats each.  pack takes
+// replica 0 of every row of a padded n x stride array; unpack writes rows {x, 0, 0, 0}
+// (stride 4).  The step is bitwise step_kernel's at one lane per row.
+hipError_t launch_compact_step(const StepParams& p, const float* Pc_in, float* Pc_out, float* mc, float* vc,
+                               hipStream_t st);
+hipError_t launch_compact_pack(const float* src, int stride, int n, float* dst, hipStream_t st);
+hipError_t launch_compact_unpack(const float* src, int n, int stride, float* dst, hipStream_t st);
 hipError_t launch_slice_step(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st);
 
 // Partial coupling sums of every chunk into p.hub_partial (reads P_in, row_ptr, col, w).

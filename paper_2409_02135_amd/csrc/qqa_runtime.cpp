@@ -392,7 +392,7 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
   if (g->n == 0 || t0 == t1) return QQA_OK;
   hipStream_t st = (hipStream_t)stream;
   if (problem == QQA_MAXCLIQUE && engine > 0 && engine != kEngineSliced)
-    return fail(&g_dev_error, QQA_E_ARG, "max clique runs on the streaming engines");
+    return fail(&g_dev_error, QQA_E_ARG, "max clique runs on the streaming and sliced engines");
   unsigned long long* T = nullptr;
   if (g->dense) {
     if (engine > 0) return fail(&g_dev_error, QQA_E_ARG, "dense coupling runs on the streaming engine");
@@ -438,9 +438,13 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
   int rpg = 0, grid = 0;
   int use = kEngineStream;
   const bool sliceable = slice_shape(S).sq > 0;
+  const bool compactable = S == 1 && problem != QQA_MAXCLIQUE;
   if (engine == kEngineSliced) {
     if (!sliceable) return fail(&g_dev_error, QQA_E_ARG, "engine cannot run this instance");
     use = kEngineSliced;
+  } else if (engine == kEngineCompact) {
+    if (!compactable) return fail(&g_dev_error, QQA_E_ARG, "engine cannot run this instance");
+    use = kEngineCompact;
   } else if (engine != kEngineStream && problem != QQA_MAXCLIQUE) {
     // allow mask: 1 = one workgroup with P in LDS, 2 = many workgroups with registers
     const int allow = engine < 0 ? 3 : (engine == kEngineLdsBlock ? 1 : (engine == kEnginePersistent ? 2 : 0));
@@ -448,8 +452,39 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
     use = persistent_plan(p, !chunks.empty(), allow, &rpg, &grid);
     if (engine >= 0 && use != engine) return fail(&g_dev_error, QQA_E_ARG, "engine cannot run this instance");
   }
+  if (engine < 0 && use == kEngineStream && compactable) use = kEngineCompact;
   if (engine < 0 && use == kEngineStream && sliceable && slice_by_default(g->n, S)) use = kEngineSliced;
   float* P[2] = {P0, P1};
+  if (use == kEngineCompact) {
+    const size_t n = (size_t)g->n;
+    const bool adam = s.rule == QQA_STEP_ADAMW;
+    int32_t* d_first = nullptr;
+    if (!chunks.empty()) {
+      DEV_CHECK(hipMallocAsync((void**)&d_first, hub_first.size() * sizeof(int32_t), st));
+      DEV_CHECK(hipMemcpyAsync(d_first, hub_first.data(), hub_first.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      p.hub_first = d_first;
+    }
+    float* cbuf = nullptr;
+    DEV_CHECK(hipMallocAsync((void**)&cbuf, 4 * n * sizeof(float), st));
+    float* Pc[2] = {cbuf, cbuf + n};
+    float* mc = cbuf + 2 * n;
+    float* vc = cbuf + 3 * n;
+    hipError_t e = launch_compact_pack(P[t0 & 1], p.stride, g->n, Pc[t0 & 1], st);
+    if (adam && e == hipSuccess) e = launch_compact_pack(m, p.stride, g->n, mc, st);
+    if (adam && e == hipSuccess) e = launch_compact_pack(v, p.stride, g->n, vc, st);
+    for (int t = t0; t < t1 && e == hipSuccess; ++t) {
+      fill_step_scalars(p, s, t, K);
+      e = launch_compact_step(p, Pc[t & 1], Pc[(t + 1) & 1], mc, vc, st);
+    }
+    if (e == hipSuccess) e = launch_compact_unpack(Pc[t1 & 1], g->n, p.stride, P[t1 & 1], st);
+    if (adam && e == hipSuccess) e = launch_compact_unpack(mc, g->n, p.stride, m, st);
+    if (adam && e == hipSuccess) e = launch_compact_unpack(vc, g->n, p.stride, v, st);
+    (void)hipFreeAsync(cbuf, st);
+    if (d_first) (void)hipFreeAsync(d_first, st);
+    DEV_CHECK(hipStreamSynchronize(st));
+    DEV_CHECK(e);
+    return QQA_OK;
+  }
   if (use == kEngineStream || use == kEngineSliced) {
     HubChunk* d_chunks = nullptr;
     int32_t* d_first = nullptr;
