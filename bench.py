@@ -345,9 +345,9 @@ def main():
         mm_us = float(np.mean([r["kernel_us"] for r in results]))
         flops = 2.0 * n * n * S
         achieved = flops / (mm_us * 1e-6) / 1e12
-        roofline = {"bound": "mfma", "kernel": "dense_coupling_kernel", "achieved": achieved,
+        roofline = {"bound": "mfma", "kernel": "dense_tile128_kernel", "achieved": achieved,
                     "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-                    "traffic": traffic_from_profiles("dense_coupling_kernel_traffic.json", DENSE_SOURCES),
+                    "traffic": traffic_from_profiles("dense_tile128_kernel_traffic.json", DENSE_SOURCES),
                     "avg_launch_us": mm_us, "algorithmic_flops_per_launch": flops,
                     "update_loop_us_per_update": step_us,
                     "uniform_random_state_us": dense_coupling_us(q, g["dense"], n, S, problem)}

@@ -298,7 +298,9 @@ int qqa_dev_init(uint64_t seed, int32_t n, int32_t S, float *P, float *m, float 
 
 /* Dense coupling product on the matrix cores (FP32 MFMA, FP32 accumulation):
  * C[i*stride + s] = sum_k W[i*n + k] f(P[k*stride + s]), f(p) = 2p - 1 (QQA_MAXCUT) or p
- * (QQA_MIS), for a symmetric n x n W (device).  P, C: device n x stride. */
+ * (QQA_MIS), for a symmetric n x n W (device).  P, C: device n x stride.  The k range may
+ * be split over workgroups, with the parts' partial products (stream-ordered scratch)
+ * added in a fixed order: the result is deterministic. */
 int qqa_dev_dense_coupling(const float *W, const float *P, float *C, int32_t n, int32_t S, qqa_problem problem,
                            void *stream);
 

@@ -140,7 +140,8 @@ int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks)
   r->coupling_bytes = 0;
   auto git = c->graphs.find(r->graph);
   if (git != c->graphs.end() && git->second.dense) {
-    r->coupling_bytes = state;
+    // the product's split-K parts (one part when the k range is not split)
+    r->coupling_bytes = (size_t)dense_splits(r->n, r->shape.stride) * state;
     get((void**)&r->coupling, r->coupling_bytes);
   }
   r->out_size = out_bytes(r->n, r->S);
@@ -218,6 +219,7 @@ StepParams request_step_params(const Request* r, const DevGraph& g) {
   p.hub_partial = r->hub_partial;
   p.colsum = r->colsum;
   p.coupling = g.dense ? r->coupling : nullptr;
+  p.coupling_parts = g.dense ? dense_splits(r->n, r->shape.stride) : 0;
   p.m = r->m;
   p.v = r->v;
   p.n = r->n;
@@ -286,7 +288,7 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   r->shape = replica_shape(S);
   r->lanes_per_row = c->layout_for(S);
   r->footprint = request_footprint(g.n, S, r->sched.rule, problem) + (size_t)g.nchunks * r->shape.stride * sizeof(float) +
-                 (g.dense ? (size_t)g.n * r->shape.stride * sizeof(float) : 0);
+                 (g.dense ? (size_t)dense_splits(g.n, r->shape.stride) * g.n * r->shape.stride * sizeof(float) : 0);
   if (r->footprint + g.bytes > c->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the HBM budget");
   {
     StepParams probe = request_step_params(r.get(), g);
@@ -383,7 +385,7 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
       const bool probe = t % every == every / 2 && pi + 1 < r->probe.size();
       if (g.dense) {
         if (probe) e = hipEventRecord(r->probe[pi], c->stream);
-        if (e == hipSuccess) e = launch_dense_coupling(g.dense, p.P_in, r->coupling, g.n, p.stride, problem, c->stream);
+        if (e == hipSuccess) e = launch_dense_parts(g.dense, p.P_in, r->coupling, g.n, p.stride, problem, c->stream);
         if (probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
       }
       if (g.nchunks && e == hipSuccess) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);

@@ -212,11 +212,19 @@ __device__ __forceinline__ void row_coupling(const StepParams& a, const int row,
                                              float4 (&acc)[QPL]) {
   const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
   if (DENSE) {
+    const size_t pitch = (size_t)a.n * a.stride;  // between partial products
 #pragma unroll
     for (int k = 0; k < QPL; ++k) {
       const int q = gl + LPR * k;
       const size_t off = (size_t)row * a.stride + 4 * (size_t)((FULL || q < nq) ? q : nq - 1);
       acc[k] = *reinterpret_cast<const float4*>(a.coupling + off);
+      for (int part = 1; part < a.coupling_parts; ++part) {
+        const float4 x = *reinterpret_cast<const float4*>(a.coupling + part * pitch + off);
+        acc[k].x += x.x;
+        acc[k].y += x.y;
+        acc[k].z += x.z;
+        acc[k].w += x.w;
+      }
     }
     return;
   }

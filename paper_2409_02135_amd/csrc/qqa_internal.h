@@ -46,6 +46,8 @@ struct StepParams {
   const int32_t* col;
   const float* w;          // nullptr: unweighted
   const float* coupling;   // dense path: precomputed coupling product, n x stride, or nullptr
+  int32_t coupling_parts;  // dense path: coupling holds this many partial products (n x stride
+                           // each, consecutive), added in part order; 0 or 1: one product
   const int32_t* hub_first;  // per row: first chunk of a split row, -1 otherwise (nullptr: no hubs)
   const float* hub_partial;  // per chunk: partial coupling sums, nchunks x stride
   // max clique: per-replica sums 1^T p of P_in in 2^-32 fixed point ([stride]), else nullptr
@@ -175,8 +177,16 @@ hipError_t launch_cat_eval(const int32_t* row_ptr, const int32_t* col, const flo
 hipError_t launch_cat_extract(const uint8_t* X, int n, int stride, const int32_t* best, uint8_t* x, hipStream_t st);
 hipError_t launch_finalize(const EvalParams& p, hipStream_t st);
 
+// `work` holds dense_workspace_bytes(n, stride) bytes of split-K partial products (none
+// needed when that is 0); C must not overlap it.  launch_dense_parts writes the
+// dense_splits(n, stride) partial products to `parts` (n x stride each, consecutive)
+// without adding them: an update kernel with coupling_parts = dense_splits adds them.
+int dense_splits(int n, int stride);
+size_t dense_workspace_bytes(int n, int stride);
 hipError_t launch_dense_coupling(const float* W, const float* P, float* C, int n, int stride, int problem,
-                                 hipStream_t st);
+                                 float* work, hipStream_t st);
+hipError_t launch_dense_parts(const float* W, const float* P, float* parts, int n, int stride, int problem,
+                              hipStream_t st);
 
 hipError_t launch_philox(uint64_t seed, int n, int nquads, uint32_t k, uint32_t stream_id, uint32_t* out,
                          hipStream_t st);

@@ -327,13 +327,15 @@ int qqa_dev_step(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule
   unsigned long long* T = nullptr;
   DEV_CHECK(colsum_for(p, problem, &T, st));
   if (g->dense) {
-    float* C = nullptr;
-    DEV_CHECK(hipMallocAsync((void**)&C, (size_t)g->n * p.stride * sizeof(float), st));
+    float* C = nullptr;  // the product's split-K parts, added by the update kernel
+    const int parts = dense_splits(g->n, p.stride);
+    DEV_CHECK(hipMallocAsync((void**)&C, (size_t)parts * g->n * p.stride * sizeof(float), st));
     p.row_ptr = nullptr;
     p.col = nullptr;
     p.w = nullptr;
     p.coupling = C;
-    hipError_t e = launch_dense_coupling(g->dense, P_in, C, g->n, p.stride, problem, st);
+    p.coupling_parts = parts;
+    hipError_t e = launch_dense_parts(g->dense, P_in, C, g->n, p.stride, problem, st);
     if (e == hipSuccess) e = launch_step(p, st);
     (void)hipFreeAsync(C, st);
     if (T) (void)hipFreeAsync(T, st);
@@ -402,9 +404,11 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
     p.n = g->n;
     fill_static_scalars(p, s, problem, S, seed);
     p.lanes_per_row = lanes_per_row;
-    float* C = nullptr;
-    DEV_CHECK(hipMallocAsync((void**)&C, (size_t)g->n * p.stride * sizeof(float), st));
+    float* C = nullptr;  // the product's split-K parts, added by the update kernel
+    const int parts = dense_splits(g->n, p.stride);
+    DEV_CHECK(hipMallocAsync((void**)&C, (size_t)parts * g->n * p.stride * sizeof(float), st));
     p.coupling = C;
+    p.coupling_parts = parts;
     float* P[2] = {P0, P1};
     hipError_t e = hipSuccess;
     for (int t = t0; t < t1 && e == hipSuccess; ++t) {
@@ -412,7 +416,7 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
       p.P_out = P[(t + 1) & 1];
       fill_step_scalars(p, s, t, K);
       e = colsum_for(p, problem, &T, st);
-      if (e == hipSuccess) e = launch_dense_coupling(g->dense, p.P_in, C, g->n, p.stride, problem, st);
+      if (e == hipSuccess) e = launch_dense_parts(g->dense, p.P_in, C, g->n, p.stride, problem, st);
       if (e == hipSuccess) e = launch_step(p, st);
     }
     (void)hipFreeAsync(C, st);
@@ -567,7 +571,14 @@ int qqa_dev_dense_coupling(const float* W, const float* P, float* C, int32_t n, 
   if (n < 0 || S <= 0 || S > kMaxReplicas || (n > 0 && (!W || !P || !C)))
     return fail(&g_dev_error, QQA_E_ARG, "bad dense coupling arguments");
   if (!known_problem(problem)) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
-  DEV_CHECK(launch_dense_coupling(W, P, C, n, replica_shape(S).stride, problem, (hipStream_t)stream));
+  const int stride = replica_shape(S).stride;
+  const size_t wb = dense_workspace_bytes(n, stride);
+  hipStream_t st = (hipStream_t)stream;
+  float* work = nullptr;
+  if (wb) DEV_CHECK(hipMallocAsync((void**)&work, wb, st));
+  const hipError_t e = launch_dense_coupling(W, P, C, n, stride, problem, work, st);
+  if (work) (void)hipFreeAsync(work, st);
+  DEV_CHECK(e);
   return QQA_OK;
 }
 
