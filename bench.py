@@ -36,6 +36,8 @@ WORKLOADS = {
     "maxcut_dense_n4096_gauss_S256_K3000": ("dense", 4096, 0, "maxcut", 256, 3000),
     # the MIS scaling study's shape: random 20-regular graph, one million variables, S = 1
     "mis_rrg_n1000000_d20_S1_K3000": ("rrg_swap", 1000000, 20, "mis", 1, 3000),
+    # the study's degree-100 graphs: every row above the split threshold (64 neighbours)
+    "mis_rrg_n100000_d100_S1_K3000": ("rrg_swap", 100000, 100, "mis", 1, 3000),
     # max clique on a Model RB instance (20 variables x 12 values, planted clique of 20),
     # the paper's 1,000 parallel runs
     "maxclique_rb20x12_S1000_K3000": ("rb", 240, (20, 12, 2.6, 0.25), "maxclique", 1000, 3000),
@@ -226,6 +228,21 @@ def served(q, rate, arrival_window, pool, seed=0, max_slots=256):
             "feasible_fraction": float(np.mean([r["feasible"] for r in res]))}
 
 
+def host_info(n, S, K, updates, dt):
+    """Where the oracle ran, its cost per replica-variable update, and the full run that cost
+    extrapolates to (linear in updates)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "ns_per_update": dt / (n * S * updates) * 1e9, "full_run_s_extrapolated": dt * K / updates}
+
+
 def cpu_baseline(g, problem, S, K, updates=20):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload: the first
     `updates` updates of the schedule from the same start, one thread."""
@@ -241,7 +258,7 @@ def cpu_baseline(g, problem, S, K, updates=20):
     dt = time.perf_counter() - t0
     return {"value": g["n"] * S * updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{updates} of {K} updates of the same instance from the same start, single-threaded FP64 C",
-            "seconds": round(dt, 3)}
+            "seconds": round(dt, 3), **host_info(g["n"], S, K, updates, dt)}
 
 
 def cpu_baseline_coloring(g, colors, S, K, updates=20):
@@ -256,7 +273,7 @@ def cpu_baseline_coloring(g, colors, S, K, updates=20):
     dt = time.perf_counter() - t0
     return {"value": g["n"] * S * updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{updates} of {K} updates of the same instance from the same start ({colors} colours), "
-                      "single-threaded FP64 C", "seconds": round(dt, 3)}
+                      "single-threaded FP64 C", "seconds": round(dt, 3), **host_info(g["n"], S, K, updates, dt)}
 
 
 def main():
@@ -414,7 +431,7 @@ def main():
                                      "1000-3000 updates", "at_200_per_s": spec, "at_70pct_capacity": low}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = (cpu_baseline_coloring(g, colors, S, K, updates=5 if n > 10000 else 20) if coloring else
-                               cpu_baseline(g, problem, S, K, updates=2 if dense else 20))
+                               cpu_baseline(g, problem, S, K, updates=3 if dense else 20))
     print(json.dumps(out), flush=True)
 
 

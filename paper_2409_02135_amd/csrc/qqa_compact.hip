@@ -46,6 +46,49 @@ __device__ __forceinline__ float compact_gather(const StepParams& a, const float
   return acc;
 }
 
+// Split rows: the sum over 16-edge chunks of [e0, e1), each chunk's sum formed exactly as
+// compact_gather forms it (the LPR lane slices, then the butterfly), the chunk sums added in
+// chunk order.  kHubGroup chunks at a time have all their loads issued before any is used, so
+// a row of many chunks does not wait for one chunk's loads before issuing the next's.
+constexpr int kHubGroup = 4;
+
+template <int LPR>
+__device__ __forceinline__ float compact_hub_sum(const StepParams& a, const float* __restrict__ P, const int e0,
+                                                 const int e1, const int gl, const bool maxcut) {
+  constexpr int U = (kHubChunk + LPR - 1) / LPR;  // edges per lane and chunk
+  float C = 0.f;
+  for (int g0 = e0; g0 < e1; g0 += kHubGroup * kHubChunk) {
+    float x[kHubGroup][U], w[kHubGroup][U];
+    bool ok[kHubGroup][U];
+#pragma unroll
+    for (int c = 0; c < kHubGroup; ++c) {
+      const int c0 = g0 + c * kHubChunk, c1 = min(c0 + kHubChunk, e1);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = c0 + gl + u * LPR;
+        ok[c][u] = e < c1;
+        const int ec = ok[c][u] ? e : e1 - 1;  // a valid edge of the row: unconditional loads
+        x[c][u] = P[a.col[ec]];
+        w[c][u] = a.w ? a.w[ec] : 1.f;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kHubGroup; ++c) {
+      float acc = 0.f;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const float f = maxcut ? 2.f * x[c][u] - 1.f : x[c][u];
+        const float r = fmaf(w[c][u], f, acc);
+        acc = ok[c][u] ? r : acc;
+      }
+#pragma unroll
+      for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
+      if (g0 + c * kHubChunk < e1) C += acc;  // chunks past the row's end add nothing
+    }
+  }
+  return C;
+}
+
 // One update of every variable: Pc_in -> Pc_out, m and v in place (n floats each).  LPR
 // lanes share a variable's edges; every lane forms the same update and lane 0 stores it.
 template <int LPR>
@@ -65,9 +108,7 @@ __global__ __launch_bounds__(kBlock) void compact_step_kernel(StepParams a, cons
   vv[0] = make_float4(adam ? vc[row] : 0.f, 0.f, 0.f, 0.f);
   float C = 0.f;
   if (rm.hub >= 0) {
-    // split rows: 16-edge chunk sums (each from zero), added in chunk order
-    for (int c0 = rm.e0; c0 < rm.e1; c0 += kHubChunk)
-      C += compact_gather<LPR>(a, Pc_in, c0, min(c0 + kHubChunk, rm.e1), gl, maxcut);
+    C = compact_hub_sum<LPR>(a, Pc_in, rm.e0, rm.e1, gl, maxcut);
   } else {
     C = compact_gather<LPR>(a, Pc_in, rm.e0, rm.e1, gl, maxcut);
   }
