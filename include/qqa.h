@@ -55,8 +55,8 @@ extern "C" {
  *   QQA_MAXCUT     -sum_{i<j} A_ij (1 - (2p_i - 1)(2p_j - 1)) / 2
  *   QQA_MAXCLIQUE  -sum_i p_i + lambda/2 (1^T p (1^T p - 1) - p^T A p); its gradient
  *                  needs the per-replica sum 1^T p over all variables in every update.
- *                  Max clique runs on the streaming engine of plain solves only (not in
- *                  batches or the server).
+ *                  Max clique runs on the streaming and sliced engines of plain solves
+ *                  only (not in batches or the server).
  *   QQA_COLORING   categorical K-state variant (appendix "Generalization to discrete
  *                  optimization problems"): per replica V in [0,1]^(N x K), sigma_ik =
  *                  V_ik / sum_k' V_ik' (uniform for an all-zero row), objective
@@ -199,7 +199,11 @@ int qqa_solve_resident(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, const qq
  * count; qqa_poll returns it as for the other problems.  Device state is colors x the
  * binary problems'.  qqa_solve_coloring_resident takes a graph uploaded with QQA_COLORING.
  * QQA_E_ARG for colors outside [2, 255]; qqa_solve / qqa_solve_resident refuse
- * QQA_COLORING. */
+ * QQA_COLORING.  An update is a gradient launch and an update launch; under the automatic
+ * engine policy, shapes where one variable's colours x replica quads fit a wavefront (at most
+ * 8 colours, a power-of-two number of quads served one per lane) run both in one launch with
+ * bitwise the same results (QQA_ENGINE_STREAM keeps two launches).  kernel_us times the
+ * gradient launch, or the single launch. */
 int qqa_solve_coloring(qqa_ctx *c, const qqa_graph *g, int32_t colors, const qqa_schedule *sched,
                        int32_t S, int32_t steps, uint64_t seed, qqa_req *out_id);
 int qqa_solve_coloring_resident(qqa_ctx *c, qqa_graph_id g, int32_t colors, const qqa_schedule *sched,
@@ -333,7 +337,8 @@ int qqa_dev_run(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule 
 /* One graph-coloring update t of a K-update schedule on caller buffers: V_in, V_out, m, v
  * are device arrays of n * colors rows x stride floats (row i*colors + k holds colour k of
  * variable i for every replica); V_out must not alias V_in; m, v updated in place.  The
- * Clamp-normalised sigma of V_in is formed internally (stream-ordered scratch). */
+ * Clamp-normalised sigma of V_in is formed internally (stream-ordered scratch).  Shapes that
+ * the single-launch form serves (see qqa_solve_coloring) use it. */
 int qqa_dev_color_step(const qqa_dev_graph *g, int32_t colors, const qqa_schedule *sched, int32_t S,
                        int32_t t, int32_t K, uint64_t seed, const float *V_in, float *V_out, float *m,
                        float *v, int32_t lanes_per_row, void *stream);

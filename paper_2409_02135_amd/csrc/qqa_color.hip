@@ -284,6 +284,151 @@ __global__ __launch_bounds__(kBlock) void cat_update_kernel(StepParams a, int K,
   }
 }
 
+// Gradient and update in one launch, for shapes where one variable's K colour rows of NQ
+// replica quads fit a lane group: lane l = k NQ + q of an LG = KP NQ lane group serves colour
+// k (KP: K rounded up to a power of two; lanes k >= K only take part in the exchanges) and
+// quad q of variable i.  sigma is read from sig_in (the neighbours' rows and the own row) and
+// the new sigma goes to sig_out, so the neighbours' rows are never overwritten while read.
+// Per element the operations and their order are those of cat_grad_kernel at one quad per
+// lane followed by cat_update_regs_kernel: the colour sums of a replica (Z, sum V G, sum G,
+// and the new Z) are formed in colour order from values exchanged through LDS.  ce is the
+// gradient kernel's entropy coefficient (-gamma c alpha K); a is the update's parameters.
+template <int NQ, int KP>
+__global__ __launch_bounds__(kBlock) void cat_fused_kernel(StepParams a, int K, float ce,
+                                                           const float* __restrict__ sig_in,
+                                                           float* __restrict__ sig_out) {
+  constexpr int LG = NQ * KP;
+  constexpr int GPB = kBlock / LG;  // variables per block
+  __shared__ float4 xs[GPB][KP][NQ];
+  __shared__ float4 gs[GPB][KP][NQ];
+  const int grp = (int)threadIdx.x / LG, l = (int)threadIdx.x % LG;
+  const int k = l / NQ, q = l % NQ;
+  const int i = (int)blockIdx.x * GPB + grp;
+  const bool live = i < a.n;
+  const bool colour = live && k < K;
+  // lanes past the last variable or colour load a valid row (unconditional loads) and store nothing
+  const int ic = live ? i : a.n - 1, kc = k < K ? k : K - 1;
+  const size_t off = ((size_t)ic * K + kc) * a.stride + 4 * q;
+  const size_t pitch = (size_t)K * a.stride;  // between variables' colour-kc rows
+  const bool adam = a.rule == kADAMW;
+  const int e0 = a.row_ptr[ic], e1 = a.row_ptr[ic + 1];
+  const float4 s_own = *reinterpret_cast<const float4*>(sig_in + off);
+  const float4 x = *reinterpret_cast<const float4*>(a.P_in + off);
+  const float4 mm = *reinterpret_cast<const float4*>((adam ? a.m : a.P_in) + off);
+  const float4 vv = *reinterpret_cast<const float4*>((adam ? a.v : a.P_in) + off);
+
+  // sum_j A_ij sigma_jk in edge order, neighbours' rows loaded in batches
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float* sk = sig_in + (size_t)kc * a.stride + 4 * q;
+  for (int b = e0; b < e1; b += kGatherQuads) {
+    float4 y[kGatherQuads];
+    bool ok[kGatherQuads];
+#pragma unroll
+    for (int u = 0; u < kGatherQuads; ++u) {
+      const int e = b + u;
+      ok[u] = e < e1;
+      y[u] = *reinterpret_cast<const float4*>(sk + (size_t)a.col[ok[u] ? e : e1 - 1] * pitch);
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherQuads; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float r = fmaf(1.f, comp(y[u], c), comp(acc, c));
+        set_comp(acc, c, ok[u] ? r : comp(acc, c));
+      }
+  }
+  // replica statistics of sigma_ik over the NQ lanes of colour k, then G = dR/dsigma_ik
+  float sum = 0.f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (4 * q + c < a.S) sum += comp(s_own, c);
+#pragma unroll
+  for (int o = NQ / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, NQ);
+  const float mu = sum * a.inv_S;
+  float sq = 0.f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (4 * q + c < a.S) {
+      const float d = comp(s_own, c) - mu;
+      sq = fmaf(d, d, sq);
+    }
+#pragma unroll
+  for (int o = NQ / 2; o > 0; o >>= 1) sq += __shfl_xor(sq, o, NQ);
+  const float sd = __builtin_amdgcn_sqrtf(sq * a.inv_S);
+  const float cg = sd > 0.f ? -a.comm_alpha * __builtin_amdgcn_rcpf(sd) : 0.f;
+  const float Kf = (float)K;
+  float4 G;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float sv = comp(s_own, c);
+    const float g = comp(acc, c) + ce * ipow_odd(fmaf(Kf, sv, -1.f), a.alpha_e - 1) + cg * (sv - mu);
+    set_comp(G, c, 4 * q + c < a.S ? g : 0.f);
+  }
+
+  // the colour sums of each replica, in colour order
+  xs[grp][k][q] = x;
+  gs[grp][k][q] = G;
+  __syncthreads();
+  float4 Z = make_float4(0.f, 0.f, 0.f, 0.f), XG = Z, GS = Z;
+  for (int kk = 0; kk < K; ++kk) {
+    const float4 xv = xs[grp][kk][q], gv = gs[grp][kk][q];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      set_comp(Z, c, comp(Z, c) + comp(xv, c));
+      set_comp(XG, c, fmaf(comp(xv, c), comp(gv, c), comp(XG, c)));
+      set_comp(GS, c, comp(GS, c) + comp(gv, c));
+    }
+  }
+  const float u = 1.f / Kf;
+  const float4 xi = normals4(philox4x32_10((uint32_t)(ic * K + kc), (uint32_t)q, a.k, kStreamNoise, a.key0, a.key1));
+  float4 po, mo, vo;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float z = comp(Z, c);
+    const float D = z > 0.f ? comp(XG, c) / z : comp(GS, c) * u;
+    const float grad = (comp(G, c) - D) / (z > 0.f ? z : 1.f);
+    const float pc = comp(x, c);
+    float pn, mn = 0.f, vn = 0.f;
+    if (adam) {
+      mn = fmaf(a.beta1, comp(mm, c), a.omb1 * grad);
+      vn = fmaf(a.beta2, comp(vv, c), a.omb2 * (grad * grad));
+      const float den = __builtin_amdgcn_sqrtf(vn * a.inv_bc2) + a.eps;
+      pn = pc * a.wd_factor - a.lr * (mn * a.inv_bc1) * __builtin_amdgcn_rcpf(den);
+    } else {
+      pn = pc - a.lr * grad;
+    }
+    pn = fmaf(a.noise_scale, comp(xi, c), pn);
+    pn = fminf(fmaxf(pn, 0.f), 1.f);
+    const bool valid = 4 * q + c < a.S;
+    set_comp(po, c, valid ? pn : 0.f);
+    set_comp(mo, c, valid ? mn : 0.f);
+    set_comp(vo, c, valid ? vn : 0.f);
+  }
+  // sigma of the new V: its colour sums, in colour order
+  __syncthreads();
+  xs[grp][k][q] = po;
+  __syncthreads();
+  float4 Zo = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int kk = 0; kk < K; ++kk) {
+    const float4 pv = xs[grp][kk][q];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) set_comp(Zo, c, comp(Zo, c) + comp(pv, c));
+  }
+  if (!colour) return;
+  float4 so;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float z = comp(Zo, c);
+    set_comp(so, c, 4 * q + c < a.S ? (z > 0.f ? comp(po, c) / z : u) : 0.f);
+  }
+  *reinterpret_cast<float4*>(a.P_out + off) = po;
+  if (adam) {
+    *reinterpret_cast<float4*>(a.m + off) = mo;
+    *reinterpret_cast<float4*>(a.v + off) = vo;
+  }
+  *reinterpret_cast<float4*>(sig_out + off) = so;
+}
+
 // colours x_i = argmax_k V_ik (first maximum) per replica
 __global__ __launch_bounds__(kBlock) void cat_color_kernel(const float* __restrict__ V, uint8_t* __restrict__ X,
                                                            int n, int K, int stride, int S) {
@@ -376,6 +521,35 @@ hipError_t launch_cat_update(const StepParams& p, int K, const float* G, float* 
   else  // more colours: the register footprint would leave too few loads in flight
     hipLaunchKernelGGL(cat_update_kernel, grid, block, 0, st, p, K, G, sig);
   return hipGetLastError();
+}
+
+bool cat_fused_shape(int S, int lanes_per_row, int K) {
+  const int nq = (S + 3) / 4;
+  if (K < 2 || K > 8 || (nq & (nq - 1)) != 0) return false;
+  const ReplicaShape r = replica_shape(S, lanes_per_row);
+  int kp = 2;
+  while (kp < K) kp *= 2;
+  return r.lpr == nq && r.qpl == 1 && kp * nq <= 64;
+}
+
+hipError_t launch_cat_fused(const StepParams& p, int K, float ce, const float* sig_in, float* sig_out,
+                            hipStream_t st) {
+  if (p.n == 0) return hipSuccess;
+  if (!cat_fused_shape(p.S, p.lanes_per_row, K)) return hipErrorInvalidValue;
+  const int nq = (p.S + 3) / 4;
+  int kp = 2;
+  while (kp < K) kp *= 2;
+#define X(NQ, KP)                                                                                         \
+  if (nq == NQ && kp == KP) {                                                                             \
+    constexpr int gpb = kBlock / (NQ * KP);                                                               \
+    hipLaunchKernelGGL((cat_fused_kernel<NQ, KP>), dim3((unsigned)((p.n + gpb - 1) / gpb)), dim3(kBlock), 0, st, p, \
+                       K, ce, sig_in, sig_out);                                                           \
+    return hipGetLastError();                                                                             \
+  }
+  X(1, 2) X(2, 2) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(1, 8) X(2, 8)
+  X(4, 8) X(8, 8)
+#undef X
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_cat_eval(const int32_t* row_ptr, const int32_t* col, const float* V, uint8_t* X, int n, int K,

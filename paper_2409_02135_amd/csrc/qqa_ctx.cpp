@@ -481,6 +481,10 @@ static int submit_coloring(qqa_ctx* c, int64_t gid, bool temp, int32_t colors, c
   if (e == hipSuccess) e = launch_cat_sigma(r->P[0], r->cat_sigma, g.n, colors, (int)stride, S, c->stream);
   if (e == hipSuccess) e = hipEventRecord(r->ev[1], c->stream);
   const int every = r->probe_every;
+  // small shapes: gradient and update in one launch, sigma ping-ponging between the two
+  // state-sized buffers (the gradient buffer is then not needed)
+  const bool fused = c->engine_policy < 0 && cat_fused_shape(S, r->lanes_per_row, colors);
+  float* sig[2] = {r->cat_sigma, r->cat_grad};
   for (int t = 0; t < steps && e == hipSuccess; ++t) {
     StepParams pg = base;
     pg.n = g.n * colors;
@@ -493,6 +497,11 @@ static int submit_coloring(qqa_ctx* c, int64_t gid, bool temp, int32_t colors, c
     const size_t pi = 2 * (size_t)(t / every);
     const bool probe = t % every == every / 2 && pi + 1 < r->probe.size();
     if (probe) e = hipEventRecord(r->probe[pi], c->stream);
+    if (fused) {
+      if (e == hipSuccess) e = launch_cat_fused(pu, colors, pg.ce, sig[t & 1], sig[(t + 1) & 1], c->stream);
+      if (probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
+      continue;
+    }
     if (e == hipSuccess) e = launch_cat_grad(pg, colors, r->cat_grad, c->stream);
     if (probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
     if (e == hipSuccess) e = launch_cat_update(pu, colors, r->cat_grad, r->cat_sigma, c->stream);

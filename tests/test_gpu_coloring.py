@@ -1,9 +1,10 @@
 """Graph coloring (the categorical K-state variant) through the C ABI: one update against the
 oracle from the same float32 state (several graphs, colour counts, replica counts and every
-replica layout, and states on the oracle's own trajectory), the colouring and its conflict
-count bit-exact against the oracle on the same state, whole solves whose reported cost is
-exact for the returned colouring, ten-seed quality against stored oracle results, and the
-argument checks."""
+replica layout, and states on the oracle's own trajectory; shapes served by the single-launch
+update and by the two-launch one), the colouring and its conflict count bit-exact against the
+oracle on the same state, whole solves whose reported cost is exact for the returned
+colouring, the single-launch update bitwise equal to the two-launch one over whole solves,
+ten-seed quality against stored oracle results, and the argument checks."""
 
 import json
 import os
@@ -193,3 +194,22 @@ def test_argument_checks():
     assert e.value.code == q.QQA_E_ARG
     ctx.release(gid)
     ctx.close()
+
+
+@pytest.mark.parametrize("gname,colors,S", [("er2000", 8, 32), ("queen6", 4, 16), ("er2000", 3, 64), ("queen6", 5, 8),
+                                            ("er2000", 2, 4), ("queen6", 7, 1)])
+def test_single_launch_update_matches_two_launches_bitwise(gname, colors, S):
+    """Shapes whose colours x replica quads fit a wavefront run gradient and update in one
+    launch under the automatic policy; the streaming policy keeps two launches."""
+    q = qqa()
+    g = qi.erdos_renyi(2000, 7.0, 3) if gname == "er2000" else qi.queens(6)
+    ctx = q.Context(0)
+    gid = ctx.upload(g, "coloring")
+    ctx.set_engine("auto")
+    a = ctx.poll(ctx.solve_coloring_resident(gid, g["n"], colors, S, 300, 5))
+    ctx.set_engine("stream")
+    b = ctx.poll(ctx.solve_coloring_resident(gid, g["n"], colors, S, 300, 5))
+    ctx.release(gid)
+    ctx.close()
+    assert np.array_equal(a["obj"], b["obj"]) and np.array_equal(a["best_x"], b["best_x"])
+    assert a["best_objective"] == conflicts_of(g, a["best_x"].astype(np.int64))
