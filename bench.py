@@ -291,7 +291,7 @@ def main():
                     help="replica layout (lanes per row); -1 = autotune before timing, 0 = default")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB elementwise copy three times (reference for HBM byte counters)")
-    ap.add_argument("--engine", default="auto", choices=["auto", "stream", "sliced", "persistent", "lds_block"],
+    ap.add_argument("--engine", default="auto", choices=["auto", "stream", "sliced", "compact", "persistent", "lds_block"],
                     help="engine policy of the solving context")
     ap.add_argument("--updates", type=int, default=0,
                     help="override the updates per solve (short runs under hardware counters)")

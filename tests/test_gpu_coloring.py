@@ -177,6 +177,15 @@ def test_ten_seed_quality_within_oracle_spread():
     assert ref_mean.min() <= mean.mean() <= ref_mean.max(), (mean, ref_mean)
 
 
+def test_full_size_single_launch_update(orc):
+    """The coloring benchmark shape (ER n = 10^5, mean degree 10, 8 colours, S = 32), which the
+    single-launch update serves: one update from a synthetic state against the oracle."""
+    q = qqa()
+    g = qi.erdos_renyi(100000, 10.0, 0)
+    V, m, v = state(g["n"], 8, 32, 13)
+    compare("er1e5 K8 S32", q, orc, g, 8, 32, 456, 1000, 3, V, m, v)
+
+
 def test_argument_checks():
     q = qqa()
     g = qi.queens(4)

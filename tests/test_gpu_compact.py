@@ -94,6 +94,33 @@ def test_compact_one_update_matches_oracle(orc):
     check_step("compact BA3000", gpu, ref, 1, True, sched.beta1, sched.beta2, sens, float(np.float32(sched.comm_alpha)))
 
 
+def test_full_size_compact_matches_streaming_and_oracle(orc):
+    """The scaling study's shape at its largest (random 20-regular graph, n = 10^6, S = 1) at
+    the 4-lane edge split: 30 updates bitwise equal to the whole-row kernel's, and one update
+    from a synthetic state against the oracle."""
+    from test_gpu_parity import check_step, oracle_params, step_sensitivity
+    q = qqa()
+    g = qi.random_regular_swapped(1000000, 20, 0)
+    K, seed = 3000, 2
+    a = run(q, g, "mis", 0, 30, K, seed, "stream", lanes=4)
+    b = run(q, g, "mis", 0, 30, K, seed, "compact", lanes=4)
+    for x, y in zip([a[0][0], a[1], a[2]], [b[0][0], b[1], b[2]]):
+        assert torch.equal(x, y)
+    t = 2222
+    P, m, v = qi.synthetic_state(g["n"], 1, seed=6)
+    d = torch.device("cuda")
+    pad = lambda a: np.pad(a, ((0, 0), (0, 3)))
+    Pt = [torch.as_tensor(pad(P), device=d), torch.full((g["n"], 4), -1.0, device=d)]
+    mt, vt = torch.as_tensor(pad(m), device=d), torch.as_tensor(pad(v), device=d)
+    sched = q.schedule("mis", g["n"])
+    q.qqa_dev_run(q.DevGraph(g), "mis", sched, 1, t, t + 1, K, seed, Pt[0], Pt[1], mt, vt, "compact", 4)
+    torch.cuda.synchronize()
+    gpu = (Pt[1].cpu().numpy(), mt.cpu().numpy(), vt.cpu().numpy())
+    ref = orc.step(oracle_params(orc, q, sched, "mis"), g, t, K, seed, P, m, v)
+    sens = step_sensitivity(ref, m.astype(np.float64), v.astype(np.float64), t, sched, True)
+    check_step("compact RRG 1e6", gpu, ref, 1, True, sched.beta1, sched.beta2, sens, float(np.float32(sched.comm_alpha)))
+
+
 def test_compact_rejections():
     q = qqa()
     g = qi.erdos_renyi(500, 5.0, 0)

@@ -142,6 +142,31 @@ def test_sliced_partials_from_its_own_updates_match_oracle(orc, name, make, prob
     _check_against_oracle(q, orc, f"sliced run {name}", g, problem, sched, S, t, K, seed, state_in, gpu)
 
 
+def test_full_size_sliced_matches_oracle(orc):
+    """The sparse MIS benchmark shape (ER n = 20,000, mean degree 5, S = 256, 3,000 updates) in
+    the engine a solve picks for it: one update from a synthetic state, then update 6 of a
+    run from the start, which combines the partials update 5 wrote."""
+    q = qqa()
+    g, problem, S, K = qi.erdos_renyi(20000, 5.0, 0), "mis", 256, 3000
+    sched = q.schedule(problem, g["n"])
+    seed, t = 21, 1234
+    P, m, v = qi.synthetic_state(g["n"], S, seed=8)
+    d = torch.device("cuda")
+    stride = q.qqa_replica_stride(S)
+    Pt = [torch.as_tensor(P, device=d), torch.full((g["n"], stride), -1.0, device=d)]
+    mt, vt = torch.as_tensor(m, device=d), torch.as_tensor(v, device=d)
+    q.qqa_dev_run(q.DevGraph(g), problem, sched, S, t, t + 1, K, seed, Pt[0], Pt[1], mt, vt, "sliced")
+    torch.cuda.synchronize()
+    gpu = (Pt[1].cpu().numpy(), mt.cpu().numpy(), vt.cpu().numpy())
+    _check_against_oracle(q, orc, "sliced C2 synthetic", g, problem, sched, S, t, K, seed, (P, m, v), gpu)
+    t = 6
+    before = run(q, g, problem, S, 0, t, K, seed, "sliced")
+    after = run(q, g, problem, S, 0, t + 1, K, seed, "sliced")
+    state_in = (before[0][t & 1].cpu().numpy(), before[1].cpu().numpy(), before[2].cpu().numpy())
+    gpu = (after[0][(t + 1) & 1].cpu().numpy(), after[1].cpu().numpy(), after[2].cpu().numpy())
+    _check_against_oracle(q, orc, "sliced C2 run", g, problem, sched, S, t, K, seed, state_in, gpu)
+
+
 def test_sliced_langevin_agrees_with_whole_rows():
     q = qqa()
     g = qi.erdos_renyi(5000, 6.0, 8)
