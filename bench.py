@@ -107,6 +107,7 @@ def dense_coupling_us(q, W, n, S, problem, launches=20):
 DEVICE_SOURCES = ["qqa_device.h", "qqa_kernels.hip"]
 DENSE_SOURCES = ["qqa_dense.hip"]
 SLICE_SOURCES = ["qqa_device.h", "qqa_slice.hip"]
+COMPACT_SOURCES = ["qqa_device.h", "qqa_compact.hip"]
 
 
 def source_hash(sources):
@@ -120,16 +121,18 @@ def device_source_hash():
     return source_hash(DEVICE_SOURCES)
 
 
-def traffic_from_profiles(record, sources):
-    """Measured HBM bytes per launch of a kernel, from a committed rocprofv3 counter
-    summary, if it was taken with the current kernel source; else None."""
+def traffic_from_profiles(record, sources, workload):
+    """Measured HBM bytes per launch of a kernel on this workload, from a committed rocprofv3
+    counter summary (one record, or a list of records for several workloads), if it was
+    taken with the current kernel source; else None."""
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", record)))
+        recs = json.load(open(os.path.join(ROOT, "profiles", record)))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != source_hash(sources):
-        return None
-    return rec.get("bytes_per_launch")
+    for rec in recs if isinstance(recs, list) else [recs]:
+        if rec.get("workload") == workload and rec.get("kernel_source_sha256") == source_hash(sources):
+            return rec.get("bytes_per_launch")
+    return None
 
 
 def batched_vs_plain(q, count=512, S=32, K=2000, seed=0):
@@ -364,7 +367,7 @@ def main():
         achieved = flops / (mm_us * 1e-6) / 1e12
         roofline = {"bound": "mfma", "kernel": "dense_tile128_kernel", "achieved": achieved,
                     "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-                    "traffic": traffic_from_profiles("dense_tile128_kernel_traffic.json", DENSE_SOURCES),
+                    "traffic": traffic_from_profiles("dense_tile128_kernel_traffic.json", DENSE_SOURCES, args.workload),
                     "avg_launch_us": mm_us, "algorithmic_flops_per_launch": flops,
                     "update_loop_us_per_update": step_us,
                     "uniform_random_state_us": dense_coupling_us(q, g["dense"], n, S, problem)}
@@ -386,14 +389,15 @@ def main():
         abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
         achieved = abytes / (step_us * 1e-6) / 1e9
         engine = results[0]["engine"]
-        sliced = engine == "sliced"
-        kernel = {"sliced": "slice_step_kernel", "compact": "compact_step_kernel"}.get(engine, "step_kernel")
+        kernel = {"sliced": "slice_step_kernel", "compact": "compact_step_kernel", "lds_block": "lds_block_kernel",
+                  "persistent": "persistent_kernel"}.get(engine, "step_kernel")
+        record = {"slice_step_kernel": ("slice_step_traffic.json", SLICE_SOURCES),
+                  "compact_step_kernel": ("compact_step_traffic.json", COMPACT_SOURCES),
+                  "step_kernel": ("step_kernel_traffic.json", DEVICE_SOURCES)}.get(kernel)
         roofline = {"bound": "hbm", "kernel": kernel,
                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": (traffic_from_profiles("slice_step_traffic.json", SLICE_SOURCES) if sliced else
-                                traffic_from_profiles("step_kernel_traffic.json", DEVICE_SOURCES)
-                                if kernel == "step_kernel" else None),
+                    "traffic": traffic_from_profiles(*record, args.workload) if record else None,
                     "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes,
                     "sampled_launch_us": float(np.mean([r["kernel_us"] for r in results]))}
 
