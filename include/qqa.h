@@ -252,14 +252,17 @@ int qqa_poll(qqa_ctx *c, qqa_req id, qqa_result *out, int32_t timeout_us);
 int qqa_cancel(qqa_ctx *c, qqa_req id);
 
 /* ---------------------------------------------------------------------------------
- * Continuous-batching server.  A server thread advances all admitted requests together:
- * every update is one launch per replica-layout class covering every admitted request,
+ * Continuous-batching server.  A server thread advances admitted requests together:
+ * every update is one launch per replica-layout class covering every running request,
  * each at its own update index, so requests that arrive while others run overlap on
  * the device.  It works in rounds of 16 updates; at each round boundary it retires
  * finished requests (rounded, evaluated and copied back during the previous round) and
  * admits queued requests first-come-first-served while a slot is free and the request's
  * HBM footprint (state, graph, schedule table, result) fits the server budget (the
- * context budget not in use when the server started).  A served result is identical to
+ * context budget not in use when the server started).  Each round advances the admitted
+ * requests with the least remaining work (updates left x rows x replica stride) until an
+ * update covers about 8M replica-variables; the others keep their place for the round.
+ * So small requests finish at close to their time alone.  A served result is identical to
  * the same solve run alone.  Replica layouts set on the context before qqa_serve_start
  * apply.  Collect results with qqa_poll (queue_ms = submit -> admission, latency_ms =
  * submit -> result).  Dense graphs and max clique are not served (QQA_E_ARG).

@@ -4,8 +4,14 @@
 // kRound updates.  At the start of a round the stream is idle: finished slots are
 // retired (their results are already in pinned host memory), queued requests are
 // admitted first-come-first-served while a slot is free and their HBM footprint fits the
-// budget, and the compact work lists of the active slots are rebuilt.  Then kRound
-// update launches advance every active slot, each at its own update index
+// budget, and the compact work lists of the running slots are rebuilt.  The running slots
+// are the admitted ones with the least remaining work (updates left x rows x replica
+// stride), taken in that order until one update of them covers kRunElements replica-
+// variables, enough to fill the device; the others wait for the round, their start moved
+// on by kRound so their update index stays where it was.  Shortest remaining work first
+// finishes small requests at close to their time alone instead of sharing the device with
+// every large one, which cuts the median latency at no cost in throughput.  Then kRound
+// update launches advance every running slot, each at its own update index
 // t = t_arg - start, and the slots that reach their last update during the round are
 // evaluated and copied back.  Requests that arrive while others run join at the next
 // round boundary, so their work overlaps on the device.  Each slot runs the same row
@@ -36,6 +42,8 @@ namespace qqa {
 
 namespace {
 constexpr int kRound = 16;
+// replica-variables per update launch beyond which more running slots add no throughput
+constexpr int64_t kRunElements = int64_t(8) << 20;
 constexpr int64_t kServerIdBase = int64_t(1) << 40;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -93,6 +101,7 @@ struct Server {
   std::vector<std::shared_ptr<ServerReq>> slots;
   // device tables
   SlotDesc* d_slots = nullptr;
+  std::vector<SlotDesc> h_slots;  // host copy of d_slots
   int32_t* d_zero = nullptr;  // the slot kernels' clock word, kept at 0: t = t_arg - start
   char* d_lists = nullptr;    // work lists and slot ids, rebuilt at round boundaries
   size_t lists_cap = 0;
@@ -203,6 +212,7 @@ void Server::run() {
       r->start = clock;
       const SlotDesc d = make_slot(r->g, r->problem, r->sched, r->S, r->K, r->seed, r->lanes, r->arena, r->L,
                                    r->out_dev, d_table, r->start);
+      h_slots[slot] = d;
       if (e == hipSuccess) e = hipMemcpy(d_slots + slot, &d, sizeof(SlotDesc), hipMemcpyHostToDevice);
       if (e != hipSuccess) {
         fail_all(std::string("server admission: ") + hipGetErrorString(e));
@@ -228,9 +238,38 @@ void Server::run() {
     hubs.clear();
     eval_items.clear();
     ids.clear();
-    std::map<std::pair<int, int>, std::vector<int>> cls_slots;
+    // running slots: least remaining work first, until an update covers kRunElements
+    std::vector<std::pair<int64_t, int>> by_work;
     for (int s = 0; s < max_slots; ++s)
-      if (slots[s] && slots[s]->state == ServerReq::kActive) cls_slots[{slots[s]->S, slots[s]->lanes}].push_back(s);
+      if (slots[s] && slots[s]->state == ServerReq::kActive) {
+        const auto& r = slots[s];
+        const int64_t left = (int64_t)(r->K - std::max(0, clock - r->start));
+        by_work.push_back({left * r->n * (int64_t)qqa_replica_stride(r->S), s});
+      }
+    std::sort(by_work.begin(), by_work.end());
+    std::map<std::pair<int, int>, std::vector<int>> cls_slots;
+    int64_t running = 0;
+    int dirty0 = max_slots, dirty1 = -1;
+    for (const auto& kv : by_work) {
+      const auto& r = slots[kv.second];
+      if (running < kRunElements) {
+        running += (int64_t)r->n * qqa_replica_stride(r->S);
+        cls_slots[{r->S, r->lanes}].push_back(kv.second);
+      } else {  // waits this round: its next update index is unchanged at the next boundary
+        r->start += kRound;
+        h_slots[kv.second].start = r->start;
+        dirty0 = std::min(dirty0, kv.second);
+        dirty1 = std::max(dirty1, kv.second);
+      }
+    }
+    if (dirty1 >= dirty0)
+      e = hipMemcpy(d_slots + dirty0, h_slots.data() + dirty0, (size_t)(dirty1 - dirty0 + 1) * sizeof(SlotDesc),
+                    hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      fail_all(std::string("server slot table: ") + hipGetErrorString(e));
+      return;
+    }
+    for (auto& kv : cls_slots) std::sort(kv.second.begin(), kv.second.end());  // slot order within a class
     for (auto& kv : cls_slots) {
       const size_t i0 = items.size(), h0 = hubs.size(), e0 = eval_items.size(), d0 = ids.size();
       for (int s : kv.second) {
@@ -433,6 +472,7 @@ int qqa_serve_start(qqa_ctx* c, int32_t max_slots) {
   sv->budget = c->budget > c->in_use ? c->budget - c->in_use : 0;
   sv->layout = c->layout;
   sv->slots.assign(max_slots, nullptr);
+  sv->h_slots.assign(max_slots, SlotDesc{});
   hipError_t e = hipStreamCreateWithFlags(&sv->st, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc((void**)&sv->d_slots, (size_t)max_slots * sizeof(SlotDesc));
   if (e == hipSuccess) e = hipMalloc((void**)&sv->d_zero, 256);
