@@ -57,6 +57,31 @@ def test_served_results_equal_alone_and_overlap():
     ctx.close()
 
 
+def test_requests_beyond_one_launch_wait_their_turn_and_equal_alone():
+    """Five requests of 3.8 M replica-variables each are more than a round runs at once (about
+    8 M per update): the ones with the least remaining work run first, the others keep their
+    update index while they wait, and small requests that arrive later go ahead of them.
+    Every result still equals the same solve alone."""
+    q = qqa()
+    big = [(qi.erdos_renyi(30000, 5.0, 40 + k), "mis", 128, K, 900 + k) for k, K in enumerate([150, 60, 120, 90, 30])]
+    small = [(qi.pm1_weights(qi.barabasi_albert(2000, 4, 50 + k), k), "maxcut", 32, 40, 950 + k) for k in range(3)]
+    ctx = q.Context(0)
+    ctx.serve_start(16)
+    ids = [ctx.serve_submit(*r) for r in big]
+    time.sleep(0.005)
+    ids += [ctx.serve_submit(*r) for r in small]
+    served = [ctx.poll(i) for i in ids]
+    ctx.serve_stop()
+    for (g, p, S, K, seed), r in zip(big + small, served):
+        alone = ctx.poll(ctx.solve(g, p, S, K, seed))
+        assert np.array_equal(r["obj"], alone["obj"]), (g["n"], p, S, K)
+        assert np.array_equal(r["best_x"], alone["best_x"])
+    # the shortest of the large requests finished before the longest one
+    lat = [r["latency_ms"] for r in served[:5]]
+    assert lat[4] < lat[0]
+    ctx.close()
+
+
 def test_tight_budget_queues_and_oversize_is_rejected():
     q = qqa()
     small = mixed_requests(6, seed=1)
