@@ -37,9 +37,9 @@
  *                   extremes, energy at one-hot points = conflict count (brute force),
  *                   central finite differences through the Clamp-normalisation, brute-force
  *                   minimum conflicts and textbook chromatic numbers
- *   orc_philox*     parity unpinned against the published known-answer vectors (not
- *                   available here); pinned by bijectivity and by uniform/normal
- *                   goodness-of-fit statistics only
+ *   orc_philox*     the published known-answer vectors of Philox4x32-10 (Salmon et al.,
+ *                   SC 2011, Random123), bijectivity (an independent inverse), avalanche,
+ *                   uniform/normal goodness-of-fit statistics
  */
 #include <math.h>
 #include <stdint.h>
