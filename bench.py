@@ -300,8 +300,8 @@ def main():
                     help="override the updates per solve (short runs under hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is "
-              "a design in DESIGN.md, not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this library runs on a "
+              "single GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
