@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void cat_update_kernel(StepParams a, int K,
 // lane followed by cat_update_regs_kernel: the colour sums of a replica (Z, sum V G, sum G,
 // and the new Z) are formed in colour order from values exchanged through LDS.  ce is the
 // gradient kernel's entropy coefficient (-gamma c alpha K); a is the update's parameters.
-template <int NQ, int KP>
+template <int NQ, int KP, int GB>
 __global__ __launch_bounds__(kBlock) void cat_fused_kernel(StepParams a, int K, float ce,
                                                            const float* __restrict__ sig_in,
                                                            float* __restrict__ sig_out) {
@@ -317,20 +317,21 @@ __global__ __launch_bounds__(kBlock) void cat_fused_kernel(StepParams a, int K, 
   const float4 mm = *reinterpret_cast<const float4*>((adam ? a.m : a.P_in) + off);
   const float4 vv = *reinterpret_cast<const float4*>((adam ? a.v : a.P_in) + off);
 
-  // sum_j A_ij sigma_jk in edge order, neighbours' rows loaded in batches
+  // sum_j A_ij sigma_jk in edge order, neighbours' rows loaded in batches of GB (the batch
+  // size changes no sum, only how many loads are in flight before the first is used)
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   const float* sk = sig_in + (size_t)kc * a.stride + 4 * q;
-  for (int b = e0; b < e1; b += kGatherQuads) {
-    float4 y[kGatherQuads];
-    bool ok[kGatherQuads];
+  for (int b = e0; b < e1; b += GB) {
+    float4 y[GB];
+    bool ok[GB];
 #pragma unroll
-    for (int u = 0; u < kGatherQuads; ++u) {
+    for (int u = 0; u < GB; ++u) {
       const int e = b + u;
       ok[u] = e < e1;
       y[u] = *reinterpret_cast<const float4*>(sk + (size_t)a.col[ok[u] ? e : e1 - 1] * pitch);
     }
 #pragma unroll
-    for (int u = 0; u < kGatherQuads; ++u)
+    for (int u = 0; u < GB; ++u)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const float r = fmaf(1.f, comp(y[u], c), comp(acc, c));
@@ -532,18 +533,24 @@ bool cat_fused_shape(int S, int lanes_per_row, int K) {
   return r.lpr == nq && r.qpl == 1 && kp * nq <= 64;
 }
 
-hipError_t launch_cat_fused(const StepParams& p, int K, float ce, const float* sig_in, float* sig_out,
+hipError_t launch_cat_fused(const StepParams& p, int K, float ce, const float* sig_in, float* sig_out, int64_t nnz,
                             hipStream_t st) {
   if (p.n == 0) return hipSuccess;
   if (!cat_fused_shape(p.S, p.lanes_per_row, K)) return hipErrorInvalidValue;
   const int nq = (p.S + 3) / 4;
   int kp = 2;
   while (kp < K) kp *= 2;
+  // neighbours loaded per batch: 16 above a mean degree of 8 (measured at ER n = 1e5, K = 8,
+  // S = 32: 250 against 260 us per update at mean degree 10, but 205 against 194 at degree 5)
+  const bool wide = nnz > 8 * (int64_t)p.n;
 #define X(NQ, KP)                                                                                         \
   if (nq == NQ && kp == KP) {                                                                             \
     constexpr int gpb = kBlock / (NQ * KP);                                                               \
-    hipLaunchKernelGGL((cat_fused_kernel<NQ, KP>), dim3((unsigned)((p.n + gpb - 1) / gpb)), dim3(kBlock), 0, st, p, \
-                       K, ce, sig_in, sig_out);                                                           \
+    const dim3 grid((unsigned)((p.n + gpb - 1) / gpb));                                                   \
+    if (wide)                                                                                             \
+      hipLaunchKernelGGL((cat_fused_kernel<NQ, KP, 16>), grid, dim3(kBlock), 0, st, p, K, ce, sig_in, sig_out); \
+    else                                                                                                  \
+      hipLaunchKernelGGL((cat_fused_kernel<NQ, KP, 8>), grid, dim3(kBlock), 0, st, p, K, ce, sig_in, sig_out); \
     return hipGetLastError();                                                                             \
   }
   X(1, 2) X(2, 2) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(1, 8) X(2, 8)

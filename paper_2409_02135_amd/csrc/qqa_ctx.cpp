@@ -498,7 +498,7 @@ static int submit_coloring(qqa_ctx* c, int64_t gid, bool temp, int32_t colors, c
     const bool probe = t % every == every / 2 && pi + 1 < r->probe.size();
     if (probe) e = hipEventRecord(r->probe[pi], c->stream);
     if (fused) {
-      if (e == hipSuccess) e = launch_cat_fused(pu, colors, pg.ce, sig[t & 1], sig[(t + 1) & 1], c->stream);
+      if (e == hipSuccess) e = launch_cat_fused(pu, colors, pg.ce, sig[t & 1], sig[(t + 1) & 1], g.nnz, c->stream);
       if (probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
       continue;
     }

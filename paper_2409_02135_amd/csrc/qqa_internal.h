@@ -176,9 +176,10 @@ hipError_t launch_cat_update(const StepParams& p, int K, const float* G, float* 
 // coefficient), reading sigma from sig_in and writing the new sigma to sig_out; for shapes
 // where cat_fused_shape holds (K <= 8 colours, a power-of-two number of replica quads served
 // one per lane by the layout, K rounded up to a power of two times the quads <= 64).  Bitwise
-// the same as launch_cat_grad followed by launch_cat_update.
+// the same as launch_cat_grad followed by launch_cat_update.  nnz (the graph's edge count)
+// sets how many neighbour loads each lane keeps in flight.
 bool cat_fused_shape(int S, int lanes_per_row, int K);
-hipError_t launch_cat_fused(const StepParams& p, int K, float ce, const float* sig_in, float* sig_out,
+hipError_t launch_cat_fused(const StepParams& p, int K, float ce, const float* sig_in, float* sig_out, int64_t nnz,
                             hipStream_t st);
 hipError_t launch_cat_eval(const int32_t* row_ptr, const int32_t* col, const float* V, uint8_t* X, int n, int K,
                            int stride, int S, unsigned long long* acc, hipStream_t st);

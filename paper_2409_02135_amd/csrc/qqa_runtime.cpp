@@ -627,7 +627,7 @@ int qqa_dev_color_step(const qqa_dev_graph* g, int32_t colors, const qqa_schedul
   hipError_t e = launch_cat_sigma(V_in, sig, g->n, colors, base.stride, S, st);
   if (cat_fused_shape(S, lanes_per_row, colors)) {
     // one launch; G's buffer takes the new sigma
-    if (e == hipSuccess) e = launch_cat_fused(pu, colors, pg.ce, sig, G, st);
+    if (e == hipSuccess) e = launch_cat_fused(pu, colors, pg.ce, sig, G, g->nnz, st);
   } else {
     if (e == hipSuccess) e = launch_cat_grad(pg, colors, G, st);
     if (e == hipSuccess) e = launch_cat_update(pu, colors, G, sig, st);

@@ -206,12 +206,14 @@ def test_argument_checks():
 
 
 @pytest.mark.parametrize("gname,colors,S", [("er2000", 8, 32), ("queen6", 4, 16), ("er2000", 3, 64), ("queen6", 5, 8),
-                                            ("er2000", 2, 4), ("queen6", 7, 1)])
+                                            ("er2000", 2, 4), ("queen6", 7, 1), ("er2000d12", 8, 32)])
 def test_single_launch_update_matches_two_launches_bitwise(gname, colors, S):
     """Shapes whose colours x replica quads fit a wavefront run gradient and update in one
-    launch under the automatic policy; the streaming policy keeps two launches."""
+    launch under the automatic policy; the streaming policy keeps two launches.  Mean degree
+    7 takes 8-neighbour load batches, queens 6 x 6 and mean degree 12 take 16."""
     q = qqa()
-    g = qi.erdos_renyi(2000, 7.0, 3) if gname == "er2000" else qi.queens(6)
+    g = {"er2000": lambda: qi.erdos_renyi(2000, 7.0, 3), "er2000d12": lambda: qi.erdos_renyi(2000, 12.0, 4),
+         "queen6": lambda: qi.queens(6)}[gname]()
     ctx = q.Context(0)
     gid = ctx.upload(g, "coloring")
     ctx.set_engine("auto")
