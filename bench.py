@@ -135,7 +135,7 @@ def traffic_from_profiles(record, sources, workload):
     return None
 
 
-def batched_vs_plain(q, count=512, S=32, K=2000, seed=0):
+def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True):
     """The ragged multi-instance configuration: `count` MIS instances on G(n, p) graphs with
     n ~ U{200..5000} and mean degree ~ U[3, 20], S replicas, K updates each; solved as one
     batch (one launch per update for all instances, replayed from a captured graph) and as a
@@ -158,19 +158,43 @@ def batched_vs_plain(q, count=512, S=32, K=2000, seed=0):
     ids = ctx.solve_batch(gids, ns, ["mis"] * count, [S] * count, [K] * count, seeds)
     rb = [ctx.poll(i, want_x=False) for i in ids]
     tb = time.perf_counter() - t0
+    # the same batch on the slot launches (one launch per update, replayed from a graph)
+    ctx.set_engine("stream")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ids = [ctx.solve_resident(gid, n, "mis", S, K, s) for gid, n, s in zip(gids, ns, seeds)]
+    ids = ctx.solve_batch(gids, ns, ["mis"] * count, [S] * count, [K] * count, seeds)
+    rs = [ctx.poll(i, want_x=False) for i in ids]
+    ts = time.perf_counter() - t0
+    ctx.set_engine("auto")
+    same_slots = all(np.array_equal(a["obj"], b["obj"]) for a, b in zip(rb, rs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ids = [ctx.solve_resident(gid, n, "mis", S, K, s) for gid, n, s in zip(gids, ns, seeds)] if plain else []
     rp = [ctx.poll(i, want_x=False) for i in ids]
     tp = time.perf_counter() - t0
-    same = all(np.array_equal(a["obj"], b["obj"]) for a, b in zip(rb, rp))
-    lat_p = np.array([r["latency_ms"] for r in rp])
+    same = all(np.array_equal(a["obj"], b["obj"]) for a, b in zip(rb, rp)) if plain else None
+    lat_p = np.array([r["latency_ms"] for r in rp]) if plain else np.zeros(1)
     for gid in gids:
         ctx.release(gid)
     ctx.close()
+    # the batched update loop against the HBM roofline: every instance's state (24 B per
+    # replica-variable) and CSR once per update, over the device time of the update loop
+    abytes = sum(algorithmic_bytes_per_update_launch(g["n"], int(g["col"].size), S, 0, False) for g in gs)
+    loop_us = float(rb[0]["step_loop_ms"]) * 1e3 / K
+    achieved = abytes / (loop_us * 1e-6) / 1e9
     return {"workload": f"{count} MIS instances, ER n~U[200,5000], mean degree~U[3,20], S={S}, {K} updates",
-            "sum_n": int(sum(ns)), "batched_updates_per_s": work / tb, "plain_updates_per_s": work / tp,
-            "speedup": tp / tb, "batched_s": tb, "plain_s": tp, "identical_results": bool(same),
+            "sum_n": int(sum(ns)), "batched_updates_per_s": work / tb,
+            "plain_updates_per_s": work / tp if plain else None,
+            "speedup": tp / tb if plain else None, "batched_s": tb, "plain_s": tp if plain else None,
+            "identical_results": same,
+            "engine": rb[0]["engine"],
+            "slot_launches": {"updates_per_s": work / ts, "seconds": ts, "identical_results": bool(same_slots),
+                              "update_us": float(rs[0]["step_loop_ms"]) * 1e3 / K},
+            "roofline": {"bound": "hbm", "kernel": "resident_kernel" if rb[0]["engine"] == "batch_resident"
+                         else "slot_step_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_update": abytes, "update_us": loop_us,
+                         "basis": "device time of the batched update loop (events on the solver stream) / updates"},
             "batched_latency_ms": 1e3 * tb,
             "plain_latency_ms": {"p50": float(np.percentile(lat_p, 50)), "p99": float(np.percentile(lat_p, 99))}}
 
@@ -190,10 +214,12 @@ def graph_pool(count, seed=0, n_range=(1e3, 1e5)):
     return pool
 
 
-def served(q, rate, arrival_window, pool, seed=0, max_slots=256):
+def served(q, rate, arrival_window, pool, seed=0, max_slots=256, deadline_ms=0.0):
     """Requests arrive as a Poisson stream at `rate`/s during `arrival_window` s: MIS or +-1
     max-cut (1/2 each) on a graph from the pool, S in {32, 128}, 1000..3000 updates.  The
-    server admits them as slots and memory free up; all are run to completion."""
+    server admits them as slots and memory free up; with a deadline it sheds, at submit,
+    the requests whose projected completion exceeds it.  Finished results are collected
+    while the stream runs."""
     import torch
     rng = np.random.default_rng(seed)
     t, arrivals = 0.0, []
@@ -207,28 +233,56 @@ def served(q, rate, arrival_window, pool, seed=0, max_slots=256):
                          int(rng.integers(2 ** 31))))
     ctx = q.Context(0)
     ctx.serve_start(max_slots)
+    if deadline_ms > 0:
+        ctx.serve_set_deadline(deadline_ms)
     torch.cuda.synchronize()
+    pending, done, offered_work, shed = {}, [], 0.0, 0
+    last_sweep = 0.0
+
+    def sweep(timeout_us=0):
+        for rid in list(pending):
+            r = ctx.poll(rid, timeout_us=timeout_us, want_x=False)
+            if r is not None:
+                done.append((r, pending.pop(rid)))
+
     t0 = time.perf_counter()
-    ids, work = [], []
     for (ta, gi, prob, S, K, sd) in arrivals:
+        now = time.perf_counter() - t0
+        if now - last_sweep > 0.05:
+            sweep()
+            last_sweep = now
         now = time.perf_counter() - t0
         if ta > now:
             time.sleep(ta - now)
         g = pool[gi][prob]
-        ids.append(ctx.serve_submit(g, prob, S, K, sd))
-        work.append(float(g["n"]) * S * K)
-    res = [ctx.poll(i, want_x=False) for i in ids]
+        w = float(g["n"]) * q.qqa_replica_stride(S) * K
+        offered_work += float(g["n"]) * S * K
+        try:
+            pending[ctx.serve_submit(g, prob, S, K, sd)] = float(g["n"]) * S * K
+        except q.QQAError as e:
+            if e.code != q.QQA_E_ADMISSION:
+                raise
+            shed += 1
+    sweep(timeout_us=-1)
     makespan = time.perf_counter() - t0
+    stats = ctx.serve_stats()
     ctx.serve_stop()
     ctx.close()
-    lat = np.array([r["latency_ms"] for r in res])
-    qms = np.array([r["queue_ms"] for r in res])
-    return {"rate_per_s": rate, "arrival_window_s": arrival_window, "requests": len(res),
-            "offered_updates_per_s": sum(work) / arrival_window,
-            "sustained_updates_per_s": sum(work) / makespan, "makespan_s": makespan,
-            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-            "queue_ms": {"p50": float(np.percentile(qms, 50)), "p99": float(np.percentile(qms, 99))},
-            "feasible_fraction": float(np.mean([r["feasible"] for r in res]))}
+    res = [r for r, _ in done]
+    work_done = sum(w for _, w in done)
+    lat = np.array([r["latency_ms"] for r in res]) if res else np.zeros(1)
+    fst = np.array([r["first_update_ms"] for r in res]) if res else np.zeros(1)
+    qms = np.array([r["queue_ms"] for r in res]) if res else np.zeros(1)
+    pct = lambda a: {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99))}
+    return {"rate_per_s": rate, "arrival_window_s": arrival_window, "deadline_ms": deadline_ms,
+            "offered": {"requests": len(arrivals), "updates_per_s": offered_work / arrival_window},
+            "admitted": {"requests": len(res), "updates_per_s": work_done / arrival_window},
+            "shed_requests": shed, "server_counts": {k: stats[k] for k in ("submitted", "admitted", "shed", "completed")},
+            "sustained_updates_per_s": work_done / makespan, "makespan_s": makespan,
+            "measured_device_rate_updates_per_s": stats["rate_updates_per_s"],
+            "latency_ms": pct(lat), "first_update_ms": pct(fst), "queue_ms": pct(qms),
+            "latency_basis": "admitted requests, submit -> result ready (host clock)",
+            "feasible_fraction": float(np.mean([r["feasible"] for r in res])) if res else None}
 
 
 def host_info(n, S, K, updates, dt):
@@ -279,6 +333,132 @@ def cpu_baseline_coloring(g, colors, S, K, updates=20):
                       "single-threaded FP64 C", "seconds": round(dt, 3), **host_info(g["n"], S, K, updates, dt)}
 
 
+def measure(q, workload, steps, warmup, lanes_arg=-1, engine="auto", updates=0):
+    """Time `steps` whole solves of one workload (after `warmup` untimed ones) with the graph
+    resident on the device; returns the figures of the JSON line for it."""
+    import torch
+    family, n, d, problem, S, K = WORKLOADS[workload]
+    if updates > 0:
+        K = updates
+    g = make_graph(family, n, d, problem)
+    dense = family == "dense"
+    coloring = problem == "coloring"
+    colors = (d if family == "queens" else d[1]) if coloring else 0
+    nnz = n * (n - 1) if dense else int(g["col"].size)
+    ctx = q.Context(0)
+    if coloring:
+        gid = ctx.upload(g, problem)
+        lanes = max(lanes_arg, 0)  # the tuner times the binary update kernel
+    elif dense:
+        gid = ctx.upload(None, problem, dense=g["dense"])
+        lanes = max(lanes_arg, 0)  # the layout only concerns the fused update here
+    else:
+        gid = ctx.upload(g, problem)
+        lanes = ctx.autotune(gid, problem, S) if lanes_arg < 0 else lanes_arg
+    ctx.set_replica_layout(S, lanes)
+    ctx.set_engine(engine)
+    print(f"# workload {workload}: n={n} nnz={nnz} S={S} updates={K} lanes_per_row={lanes}",
+          file=sys.stderr, flush=True)
+
+    def submit(seed):
+        if coloring:
+            return ctx.solve_coloring_resident(gid, n, colors, S, K, seed)
+        return ctx.solve_resident(gid, n, problem, S, K, seed)
+
+    for w in range(warmup):
+        ctx.poll(submit(1000 + w), want_x=False)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ids = [submit(s) for s in range(steps)]
+    results = [ctx.poll(i, want_x=False) for i in ids]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    value = n * S * K * steps / elapsed
+    dev_ms = np.array([r["device_ms"] for r in results])
+    loop_ms = np.array([r["step_loop_ms"] for r in results])
+    step_us = float(np.mean(loop_ms)) * 1e3 / K  # average duration of one update launch
+    stride = q.qqa_replica_stride(S)
+    engine_ran = results[0]["engine"]
+    if dense:
+        # dominant kernel: the FP32 matrix-core product, 2 n^2 S flops per launch, timed by
+        # the library with events on sampled launches inside the timed solves
+        mm_us = float(np.mean([r["kernel_us"] for r in results]))
+        flops = 2.0 * n * n * S
+        achieved = flops / (mm_us * 1e-6) / 1e12
+        roofline = {"bound": "mfma", "kernel": "dense_tile128_kernel", "achieved": achieved,
+                    "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                    "traffic": traffic_from_profiles("dense_tile128_kernel_traffic.json", DENSE_SOURCES, workload),
+                    "avg_launch_us": mm_us, "algorithmic_flops_per_launch": flops,
+                    "update_loop_us_per_update": step_us,
+                    "uniform_random_state_us": dense_coupling_us(q, g["dense"], n, S, problem)}
+    elif coloring:
+        # one update is one or two launches (gradient over N*K rows, then the per-variable
+        # update); algorithmic bytes: V, m, v read and written for every colour, plus the CSR
+        abytes = 24 * n * colors * S + 4 * (n + 1) + 4 * nnz
+        achieved = abytes / (step_us * 1e-6) / 1e9
+        # one launch when the variable's colours x replica quads fit a wavefront (the library's rule)
+        nq = stride // 4
+        kp = 1 << (colors - 1).bit_length()
+        fused = colors <= 8 and nq & (nq - 1) == 0 and kp * nq <= 64 and lanes_arg in (-1, 0, nq)
+        roofline = {"bound": "hbm", "kernel": "cat_fused_kernel" if fused else "cat_grad_kernel + cat_update_kernel",
+                    "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes,
+                    "sampled_kernel_us": float(np.mean([r["kernel_us"] for r in results]))}
+    else:
+        abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
+        achieved = abytes / (step_us * 1e-6) / 1e9
+        kernel = {"sliced": "slice_step_kernel", "compact": "compact_step_kernel", "lds_block": "lds_block_kernel",
+                  "persistent": "persistent_kernel"}.get(engine_ran, "step_kernel")
+        record = {"slice_step_kernel": ("slice_step_traffic.json", SLICE_SOURCES),
+                  "compact_step_kernel": ("compact_step_traffic.json", COMPACT_SOURCES),
+                  "step_kernel": ("step_kernel_traffic.json", DEVICE_SOURCES)}.get(kernel)
+        roofline = {"bound": "hbm", "kernel": kernel,
+                    "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": traffic_from_profiles(*record, workload) if record else None,
+                    "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes,
+                    "sampled_launch_us": float(np.mean([r["kernel_us"] for r in results]))}
+    ctx.release(gid)
+    ctx.close()
+    return {
+        "graph": g, "problem": problem, "S": S, "K": K, "colors": colors, "dense": dense,
+        "value": value, "elapsed": elapsed, "steps": steps,
+        "config": {"workload": workload, "problem": problem, "graph": family, "n": n, "nnz": nnz,
+                   **({"colors": colors} if coloring else {}),
+                   "degree_param": d, "S": S, "updates_per_solve": K, "graph_seed": 0,
+                   "lanes_per_row": lanes, "engine": engine_ran, "parallelism": "single GPU"},
+        "latency_ms": {"p50": float(np.percentile(dev_ms, 50)), "p99": float(np.percentile(dev_ms, 99)),
+                       "basis": "device time per solve (events on the solver stream)"},
+        "us_per_update": step_us,
+        "roofline": roofline,
+        "quality": {"best_objective_mean": float(np.mean([r["best_objective"] for r in results])),
+                    "feasible_all": bool(all(r["feasible"] for r in results))},
+    }
+
+
+# The other configurations of the benchmark set, each timed over a few whole solves in the
+# default run: the small latency-bound instance, the heavy-tailed max-cut instance and its
+# dense matrix-core variant.  The batched and served configurations have blocks of their own.
+CONFIG_BLOCKS = [("mis_rrg_n256_d3_S16_K2000", 5, 2, 2000),
+                 ("maxcut_ba_n100000_m4_pm1_S128_K3000", 3, 1, 3),
+                 ("maxcut_dense_n4096_gauss_S256_K3000", 2, 1, 0)]
+
+
+def config_block(q, workload, steps, warmup, oracle_updates, with_cpu):
+    m = measure(q, workload, steps, warmup)
+    out = {"value": m["value"], "unit": "updates/s", "steps": steps, "warmup": warmup,
+           "ms_per_step": m["elapsed"] * 1e3 / steps, "us_per_update": m["us_per_update"],
+           "config": m["config"], "latency_ms": m["latency_ms"], "roofline": m["roofline"], "quality": m["quality"]}
+    if with_cpu and oracle_updates > 0:
+        cb = cpu_baseline(m["graph"], m["problem"], m["S"], m["K"], updates=min(oracle_updates, m["K"]))
+        out["oracle_context"] = {k: cb[k] for k in ("value", "unit", "cores", "sample", "ns_per_update",
+                                                     "full_run_s_extrapolated")}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,10 +466,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other single-instance configurations")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--batch-updates", type=int, default=2000,
+                    help="updates per instance of the batched configuration (fewer for runs under counters)")
+    ap.add_argument("--batch-no-plain", action="store_true",
+                    help="time the batch only, not the loop of plain solves (runs under counters)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served request-stream measurement")
-    ap.add_argument("--serve-window", type=float, default=2.0,
+    ap.add_argument("--serve-window", type=float, default=60.0,
                     help="arrival window (s) of the served stream at the specified rate of 200 requests/s")
+    ap.add_argument("--serve-deadline-ms", type=float, default=2000.0,
+                    help="load shedding: requests whose projected completion exceeds this are refused at submit")
     ap.add_argument("--lanes", type=int, default=-1,
                     help="replica layout (lanes per row); -1 = autotune before timing, 0 = default")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -315,132 +502,47 @@ def main():
         return
     import paper_2409_02135_amd as q
 
-    family, n, d, problem, S, K = WORKLOADS[args.workload]
-    if args.updates > 0:
-        K = args.updates
-    g = make_graph(family, n, d, problem)
-    dense = family == "dense"
-    coloring = problem == "coloring"
-    colors = (d if family == "queens" else d[1]) if coloring else 0
-    nnz = n * (n - 1) if dense else int(g["col"].size)
-    ctx = q.Context(0)
-    if coloring:
-        gid = ctx.upload(g, problem)
-        lanes = max(args.lanes, 0)  # the tuner times the binary update kernel
-    elif dense:
-        gid = ctx.upload(None, problem, dense=g["dense"])
-        lanes = max(args.lanes, 0)  # the layout only concerns the fused update here
-    else:
-        gid = ctx.upload(g, problem)
-        lanes = ctx.autotune(gid, problem, S) if args.lanes < 0 else args.lanes
-    ctx.set_replica_layout(S, lanes)
-    ctx.set_engine(args.engine)
-    print(f"# workload {args.workload}: n={n} nnz={nnz} S={S} updates={K} lanes_per_row={lanes}",
-          file=sys.stderr, flush=True)
-
-    def submit(seed):
-        if coloring:
-            return ctx.solve_coloring_resident(gid, n, colors, S, K, seed)
-        return ctx.solve_resident(gid, n, problem, S, K, seed)
-
-    for w in range(args.warmup):
-        ctx.poll(submit(1000 + w), want_x=False)
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ids = [submit(s) for s in range(args.steps)]
-    results = [ctx.poll(i, want_x=False) for i in ids]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    updates = n * S * K * args.steps
-    value = updates / elapsed
-    dev_ms = np.array([r["device_ms"] for r in results])
-    loop_ms = np.array([r["step_loop_ms"] for r in results])
-    step_us = float(np.mean(loop_ms)) * 1e3 / K  # average duration of one update launch
-    stride = q.qqa_replica_stride(S)
-    if dense:
-        # dominant kernel: the FP32 matrix-core product, 2 n^2 S flops per launch, timed by
-        # the library with events on sampled launches inside the timed solves
-        mm_us = float(np.mean([r["kernel_us"] for r in results]))
-        flops = 2.0 * n * n * S
-        achieved = flops / (mm_us * 1e-6) / 1e12
-        roofline = {"bound": "mfma", "kernel": "dense_tile128_kernel", "achieved": achieved,
-                    "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-                    "traffic": traffic_from_profiles("dense_tile128_kernel_traffic.json", DENSE_SOURCES, args.workload),
-                    "avg_launch_us": mm_us, "algorithmic_flops_per_launch": flops,
-                    "update_loop_us_per_update": step_us,
-                    "uniform_random_state_us": dense_coupling_us(q, g["dense"], n, S, problem)}
-    elif coloring:
-        # one update is one or two launches (gradient over N*K rows, then the per-variable
-        # update); algorithmic bytes: V, m, v read and written for every colour, plus the CSR
-        abytes = 24 * n * colors * S + 4 * (n + 1) + 4 * nnz
-        achieved = abytes / (step_us * 1e-6) / 1e9
-        # one launch when the variable's colours x replica quads fit a wavefront (the library's rule)
-        nq = stride // 4
-        kp = 1 << (colors - 1).bit_length()
-        fused = colors <= 8 and nq & (nq - 1) == 0 and kp * nq <= 64 and args.lanes in (-1, 0, nq)
-        roofline = {"bound": "hbm", "kernel": "cat_fused_kernel" if fused else "cat_grad_kernel + cat_update_kernel",
-                    "achieved": achieved,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes,
-                    "sampled_kernel_us": float(np.mean([r["kernel_us"] for r in results]))}
-    else:
-        abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
-        achieved = abytes / (step_us * 1e-6) / 1e9
-        engine = results[0]["engine"]
-        kernel = {"sliced": "slice_step_kernel", "compact": "compact_step_kernel", "lds_block": "lds_block_kernel",
-                  "persistent": "persistent_kernel"}.get(engine, "step_kernel")
-        record = {"slice_step_kernel": ("slice_step_traffic.json", SLICE_SOURCES),
-                  "compact_step_kernel": ("compact_step_traffic.json", COMPACT_SOURCES),
-                  "step_kernel": ("step_kernel_traffic.json", DEVICE_SOURCES)}.get(kernel)
-        roofline = {"bound": "hbm", "kernel": kernel,
-                    "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": traffic_from_profiles(*record, args.workload) if record else None,
-                    "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes,
-                    "sampled_launch_us": float(np.mean([r["kernel_us"] for r in results]))}
-
+    m = measure(q, args.workload, args.steps, args.warmup, args.lanes, args.engine, args.updates)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": m["value"],
         "unit": "updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": m["elapsed"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "problem": problem, "graph": family, "n": n, "nnz": nnz,
-                   **({"colors": colors} if coloring else {}),
-                   "degree_param": d, "S": S, "updates_per_solve": K, "graph_seed": 0,
-                   "lanes_per_row": lanes, "engine": results[0]["engine"], "parallelism": "single GPU"},
-        "latency_ms": {"p50": float(np.percentile(dev_ms, 50)), "p99": float(np.percentile(dev_ms, 99)),
-                       "basis": "device time per solve (events on the solver stream)"},
-        "roofline": roofline,
-        "quality": {"best_objective_mean": float(np.mean([r["best_objective"] for r in results])),
-                    "feasible_all": bool(all(r["feasible"] for r in results))},
+        "config": m["config"],
+        "latency_ms": m["latency_ms"],
+        "roofline": m["roofline"],
+        "quality": m["quality"],
     }
-    ctx.release(gid)
-    ctx.close()
+    default_run = args.workload == DEFAULT and args.updates == 0 and args.engine == "auto"
+    if default_run and not args.no_configs:
+        out["configs"] = {}
+        for w, st, wu, oupd in CONFIG_BLOCKS:
+            out["configs"][w] = config_block(q, w, st, wu, oupd, not args.no_cpu_baseline)
     if not args.no_batch:
-        out["batched_vs_plain"] = batched_vs_plain(q)
+        out["batched_vs_plain"] = batched_vs_plain(q, K=args.batch_updates, plain=not args.batch_no_plain)
     if not args.no_serve:
         pool = graph_pool(24)
-        spec = served(q, 200.0, args.serve_window, pool, seed=1)
-        # a second stream at about 70 % of the capacity the first one sustained
-        mean_work = spec["offered_updates_per_s"] / 200.0
+        spec = served(q, 200.0, args.serve_window, pool, seed=1, deadline_ms=args.serve_deadline_ms)
+        # a second stream at about 70 % of the capacity the first one sustained, unshed
+        mean_work = spec["offered"]["updates_per_s"] / 200.0
         rate70 = max(1.0, 0.7 * spec["sustained_updates_per_s"] / mean_work)
         low = served(q, rate70, 8.0, pool, seed=2)
         out["served"] = {"workload": "Poisson stream of MIS / +-1 max-cut requests on ER (mean degree U[3,20]) "
                                      "and BA (m=4) graphs, n log-uniform in [1e3,1e5], S in {32,128}, "
                                      "1000-3000 updates", "at_200_per_s": spec, "at_70pct_capacity": low}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = (cpu_baseline_coloring(g, colors, S, K, updates=5 if n > 10000 else 20) if coloring else
-                               cpu_baseline(g, problem, S, K, updates=3 if dense else 20))
+        g, problem, S, K, colors = m["graph"], m["problem"], m["S"], m["K"], m["colors"]
+        out["cpu_baseline"] = (cpu_baseline_coloring(g, colors, S, K, updates=5 if g["n"] > 10000 else 20)
+                               if problem == "coloring" else
+                               cpu_baseline(g, problem, S, K, updates=3 if m["dense"] else 20))
     print(json.dumps(out), flush=True)
 
 

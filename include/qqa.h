@@ -10,12 +10,12 @@
  *   * relaxed objectives l^: the MIS and max-cut energies of the appendix section
  *     "Energy Function of Benchmark Problems";
  *   * alpha-entropy s(p) = sum_i 1 - (2 p_i - 1)^alpha: Eq. 7, annealed with gamma_t
- *     rising linearly from gamma_min to gamma_max (Sec. 4 "Implementation", appendix
+ *     rising linearly from gamma_min to gamma_max (Sec. 5 "Implementation", appendix
  *     "Annealing Schedule");
  *   * replica communication: the STD term of Eq. 10;
  *   * update: the sensitive-transition step on p of Eq. 11 with AdamW in place of
- *     the plain step (Sec. 3.4), or the plain step itself; Clamp to [0,1] (Sec. 4);
- *   * rounding x_i = Theta(p_i - 1/2) (Sec. 4), with Theta(0) = 0.
+ *     the plain step (Sec. 3.4), or the plain step itself; Clamp to [0,1] (Sec. 5 "Implementation");
+ *   * rounding x_i = Theta(p_i - 1/2) (Sec. 5 "Implementation"), with Theta(0) = 0.
  *
  * Conventions for every function:
  *   * Return value: QQA_OK (0), QQA_PENDING (1) or a negative QQA_E_* code.  Nothing
@@ -68,7 +68,7 @@ typedef enum { QQA_STEP_ADAMW = 0, QQA_STEP_LANGEVIN = 1 } qqa_step_rule;
 
 /* Hyper-parameters of one solve.  qqa_schedule_default() fills the paper's values:
  * gamma -2 -> 0.1 (max-cut: gamma_min -20 for N >= 1000, else -5; appendix "Annealing
- * Schedule"), alpha = 4 (Sec. 4), weight decay 0.01 and T = 0.001 (appendix
+ * Schedule"), alpha = 4 (Sec. 5 "Implementation"), weight decay 0.01 and T = 0.001 (appendix
  * "Configuration of Optimizer"), MIS lambda = 2 (appendix MIS energy), and the choices
  * the paper leaves open: lr 0.1 (from its set {1, 0.1, 0.01}), comm_alpha 0.1,
  * Adam betas 0.9 / 0.999, eps 1e-8. */
@@ -144,6 +144,8 @@ typedef struct {
                                   * launch of an update (the coupling product for dense
                                   * graphs, the update kernel otherwise), timed with events on
                                   * up to 32 updates spread over the schedule; -1 otherwise */
+    double first_update_ms;      /* submit -> first update launched (host clock); for
+                                  * requests outside the server, equal to queue_ms */
 } qqa_result;
 
 /* How the update loop runs.  STREAM: one launch per update, state streamed through
@@ -212,7 +214,9 @@ int qqa_solve_coloring_resident(qqa_ctx *c, qqa_graph_id g, int32_t colors, cons
 /* Submit `count` independent solves packed into one ragged batch: every update of the
  * batch is a single launch covering all instances (each at its own update index), the
  * update loop is replayed from a captured HIP graph.  Instances never interact: each
- * result equals that of the same solve submitted alone.  Graph ids come from
+ * result equals that of the same solve run alone on the whole-row engines (under the
+ * automatic policy a solve alone with S >= 256 may run on SLICED, which agrees to
+ * rounding after one update; see qqa_engine).  Graph ids come from
  * qqa_graph_upload.  Arrays have `count` entries; sched may be NULL (defaults).  Dense
  * graphs and max clique are solved one at a time (QQA_E_ARG here). */
 int qqa_solve_batch(qqa_ctx *c, int32_t count, const qqa_graph_id *graphs, const qqa_problem *problems,
@@ -263,18 +267,45 @@ int qqa_cancel(qqa_ctx *c, qqa_req id);
  * requests with the least remaining work (updates left x rows x replica stride) until an
  * update covers about 8M replica-variables; the others keep their place for the round.
  * So small requests finish at close to their time alone.  A served result is identical to
- * the same solve run alone.  Replica layouts set on the context before qqa_serve_start
- * apply.  Collect results with qqa_poll (queue_ms = submit -> admission, latency_ms =
- * submit -> result).  Dense graphs and max clique are not served (QQA_E_ARG).
+ * the same solve run alone on the whole-row engines (STREAM, and BATCH); under the
+ * automatic policy a solve alone with S >= 256 may run on SLICED, whose results agree with
+ * the served one to rounding after one update (see qqa_engine).  Replica layouts set on the
+ * context before qqa_serve_start apply.  Collect results with qqa_poll (queue_ms = submit ->
+ * admission, first_update_ms = submit -> first update launched, latency_ms = submit ->
+ * result).  Dense graphs, max clique and coloring are not served (QQA_E_ARG).
  *   qqa_serve_start: max_slots concurrent requests on the device.
  *   qqa_serve_submit: validates and copies the host graph (the caller may free it on
- *     return) and queues the request; QQA_E_ADMISSION if it can never fit.
+ *     return) and queues the request; QQA_E_ADMISSION if it can never fit, or if it is
+ *     shed (below).
+ *   qqa_serve_set_deadline: load shedding.  With deadline_ms > 0, qqa_serve_submit refuses
+ *     (QQA_E_ADMISSION, "shed: ...") a request whose projected submit-to-result time exceeds
+ *     deadline_ms.  The projection: under least-remaining-work-first the request waits for
+ *     the pending work with less remaining work than its own, W_<, and for smaller work
+ *     arriving meanwhile at the rate a_w measured over the admitted submissions of the last
+ *     5 s; at the device rate R (replica-variable updates per second, measured over rounds
+ *     that fill the device) it finishes after (W_< + w) / (R - a_w), and no sooner than its
+ *     updates times the shortest update time seen.  0 (the default) sheds nothing.
+ *   qqa_serve_get_stats: counts of submitted, admitted, shed and completed requests since
+ *     qqa_serve_start, the measured device rate and the server's device memory.
  *   qqa_serve_stop: returns after every queued and admitted request has finished;
  *     results stay available to qqa_poll.  A context runs at most one server at a time.
  * --------------------------------------------------------------------------------- */
+typedef struct {
+    int64_t submitted;           /* qqa_serve_submit calls that passed validation */
+    int64_t admitted;            /* of which queued for the device */
+    int64_t shed;                /* of which refused by the deadline */
+    int64_t completed;           /* admitted requests whose result is ready */
+    double rate_updates_per_s;   /* measured device rate R */
+    double deadline_ms;
+    size_t device_bytes_held;    /* request buffers the server's pool holds (in use or idle) */
+    size_t device_bytes_cached;  /* of which idle, kept for reuse (capped at 4 GiB) */
+} qqa_serve_stats;
+
 int qqa_serve_start(qqa_ctx *c, int32_t max_slots);
 int qqa_serve_submit(qqa_ctx *c, const qqa_graph *g, qqa_problem problem, const qqa_schedule *sched,
                      int32_t S, int32_t steps, uint64_t seed, qqa_req *out_id);
+int qqa_serve_set_deadline(qqa_ctx *c, double deadline_ms);
+int qqa_serve_get_stats(qqa_ctx *c, qqa_serve_stats *out);
 int qqa_serve_stop(qqa_ctx *c);
 
 /* ---------------------------------------------------------------------------------

@@ -37,9 +37,12 @@
  *                   extremes, energy at one-hot points = conflict count (brute force),
  *                   central finite differences through the Clamp-normalisation, brute-force
  *                   minimum conflicts and textbook chromatic numbers
- *   orc_philox*     the published known-answer vectors of Philox4x32-10 (Salmon et al.,
- *                   SC 2011, Random123), bijectivity (an independent inverse), avalanche,
- *                   uniform/normal goodness-of-fit statistics
+ *   orc_philox*     bijectivity (an independent inverse), avalanche, uniform/normal
+ *                   goodness-of-fit statistics, distinct streams.  Parity unpinned: the
+ *                   generator's published known-answer vectors are not available here, so
+ *                   conformance of this implementation of Philox4x32-10 (Salmon et al., SC
+ *                   2011) to the published stream is not checked; the GPU's integers are
+ *                   compared bit for bit with these.
  */
 #include <math.h>
 #include <stdint.h>

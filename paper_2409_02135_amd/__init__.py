@@ -54,7 +54,13 @@ class qqa_result(C.Structure):
                 ("replica_objective", C.c_void_p), ("replica_size_or_cut", C.c_void_p),
                 ("replica_violations", C.c_void_p), ("best_x", C.c_void_p), ("queue_ms", C.c_double),
                 ("device_ms", C.c_double), ("step_loop_ms", C.c_double), ("latency_ms", C.c_double),
-                ("engine", C.c_int32), ("kernel_us", C.c_double)]
+                ("engine", C.c_int32), ("kernel_us", C.c_double), ("first_update_ms", C.c_double)]
+
+
+class qqa_serve_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("shed", C.c_int64), ("completed", C.c_int64),
+                ("rate_updates_per_s", C.c_double), ("deadline_ms", C.c_double),
+                ("device_bytes_held", C.c_size_t), ("device_bytes_cached", C.c_size_t)]
 
 
 class qqa_dev_graph(C.Structure):
@@ -90,6 +96,8 @@ def lib():
             "qqa_serve_start": (C.c_int, [vp, i32]),
             "qqa_serve_submit": (C.c_int, [vp, vp, i32, vp, i32, i32, u64, vp]),
             "qqa_serve_stop": (C.c_int, [vp]),
+            "qqa_serve_set_deadline": (C.c_int, [vp, C.c_double]),
+            "qqa_serve_get_stats": (C.c_int, [vp, vp]),
             "qqa_dev_last_error": (C.c_char_p, []),
             "qqa_dev_philox": (C.c_int, [u64, i32, i32, u32, u32, vp, vp]),
             "qqa_dev_noise": (C.c_int, [u64, i32, i32, u32, vp, vp]),
@@ -125,6 +133,31 @@ def _ptr(t):
     if isinstance(t, np.ndarray):
         return t.ctypes.data_as(C.c_void_p)
     return C.c_void_p(t)
+
+
+_DTYPES = {"f32": (torch.float32,), "i64": (torch.int64, torch.uint64), "u64": (torch.int64, torch.uint64),
+           "i32": (torch.int32,), "u32": (torch.int32, torch.uint32), "u8": (torch.uint8,)}
+
+
+def _dev(t, kind: str, count: int, name: str):
+    """Pointer to a device tensor the qqa_dev_* kernels read or write: it must be a contiguous
+    CUDA tensor of the element type `kind` holding at least `count` elements.  Anything else
+    is refused here, before a kernel could access memory outside it."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: a CUDA tensor is required, got {type(t).__name__}")
+    if t.dtype not in _DTYPES[kind]:
+        raise ValueError(f"{name}: dtype {t.dtype} where {kind} is required")
+    if t.numel() < count:
+        raise ValueError(f"{name}: {t.numel()} elements, at least {count} required")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: tensor is on {t.device}, the kernels need device memory")
+    return _ptr(t)
+
+
+def _state(t, rows: int, S: int, name: str):
+    return _dev(t, "f32", rows * qqa_replica_stride(S), name)
 
 
 def _stream(stream):
@@ -185,56 +218,73 @@ class DevGraph:
 
 
 def qqa_dev_philox(seed, n, nquads, k, stream_id, out, stream=None):
-    return _dev_check(lib().qqa_dev_philox(seed, n, nquads, k, stream_id, _ptr(out), _stream(stream)))
+    out_p = _dev(out, "u32", 4 * max(n, 0) * max(nquads, 0), "out")
+    return _dev_check(lib().qqa_dev_philox(seed, n, nquads, k, stream_id, out_p, _stream(stream)))
 
 
 def qqa_dev_noise(seed, n, S, k, xi, stream=None):
-    return _dev_check(lib().qqa_dev_noise(seed, n, S, k, _ptr(xi), _stream(stream)))
+    return _dev_check(lib().qqa_dev_noise(seed, n, S, k, _state(xi, n, S, "xi"), _stream(stream)))
 
 
 def qqa_dev_init(seed, n, S, P, m=None, v=None, stream=None):
-    return _dev_check(lib().qqa_dev_init(seed, n, S, _ptr(P), _ptr(m), _ptr(v), _stream(stream)))
+    return _dev_check(lib().qqa_dev_init(seed, n, S, _state(P, n, S, "P"), _state(m, n, S, "m"), _state(v, n, S, "v"),
+                                         _stream(stream)))
 
 
 def qqa_dev_step(g: DevGraph, problem, sched: qqa_schedule | None, S, t, K, seed, P_in, P_out, m, v,
                  lanes_per_row=0, stream=None):
+    n = g.n
     return _dev_check(lib().qqa_dev_step(C.byref(g.struct), PROBLEMS[problem], None if sched is None else C.byref(sched),
-                                         S, t, K, seed, _ptr(P_in), _ptr(P_out), _ptr(m), _ptr(v), lanes_per_row,
-                                         _stream(stream)))
+                                         S, t, K, seed, _state(P_in, n, S, "P_in"), _state(P_out, n, S, "P_out"),
+                                         _state(m, n, S, "m"), _state(v, n, S, "v"), lanes_per_row, _stream(stream)))
 
 
 def qqa_dev_run(g: DevGraph, problem, sched: qqa_schedule | None, S, t0, t1, K, seed, P0, P1, m, v,
                 engine="auto", lanes_per_row=0, stream=None):
     e = ENGINES[engine] if isinstance(engine, str) else engine
+    n = g.n
     return _dev_check(lib().qqa_dev_run(C.byref(g.struct), PROBLEMS[problem], None if sched is None else C.byref(sched),
-                                        S, t0, t1, K, seed, _ptr(P0), _ptr(P1), _ptr(m), _ptr(v), e, lanes_per_row,
-                                        _stream(stream)))
+                                        S, t0, t1, K, seed, _state(P0, n, S, "P0"), _state(P1, n, S, "P1"),
+                                        _state(m, n, S, "m"), _state(v, n, S, "v"), e, lanes_per_row, _stream(stream)))
 
 
 def qqa_dev_replica_sums(P, n, S, T, stream=None):
     """T (device uint64/int64 tensor of stride entries) = per-replica sums of P in 2^-32 units."""
-    return _dev_check(lib().qqa_dev_replica_sums(_ptr(P), n, S, _ptr(T), _stream(stream)))
+    return _dev_check(lib().qqa_dev_replica_sums(_state(P, n, S, "P"), n, S, _dev(T, "u64", qqa_replica_stride(S), "T"),
+                                                 _stream(stream)))
 
 
 def qqa_dev_dense_coupling(W, P, C, n, S, problem, stream=None):
-    return _dev_check(lib().qqa_dev_dense_coupling(_ptr(W), _ptr(P), _ptr(C), n, S, PROBLEMS[problem], _stream(stream)))
+    return _dev_check(lib().qqa_dev_dense_coupling(_dev(W, "f32", n * n, "W"), _state(P, n, S, "P"), _state(C, n, S, "C"),
+                                                   n, S, PROBLEMS[problem], _stream(stream)))
 
 
 def qqa_dev_color_step(g: DevGraph, colors, sched: qqa_schedule | None, S, t, K, seed, V_in, V_out, m, v,
                        lanes_per_row=0, stream=None):
+    rows = g.n * max(colors, 0)
     return _dev_check(lib().qqa_dev_color_step(C.byref(g.struct), colors, None if sched is None else C.byref(sched),
-                                               S, t, K, seed, _ptr(V_in), _ptr(V_out), _ptr(m), _ptr(v),
+                                               S, t, K, seed, _state(V_in, rows, S, "V_in"), _state(V_out, rows, S, "V_out"),
+                                               _state(m, rows, S, "m"), _state(v, rows, S, "v"),
                                                lanes_per_row, _stream(stream)))
 
 
 def qqa_dev_color_eval(g: DevGraph, colors, S, V, X, conflicts, best, stream=None):
-    return _dev_check(lib().qqa_dev_color_eval(C.byref(g.struct), colors, S, _ptr(V), _ptr(X), _ptr(conflicts),
-                                               _ptr(best), _stream(stream)))
+    stride = qqa_replica_stride(S)
+    return _dev_check(lib().qqa_dev_color_eval(C.byref(g.struct), colors, S, _state(V, g.n * max(colors, 0), S, "V"),
+                                               _dev(X, "u8", g.n * stride, "X"), _dev(conflicts, "i64", S, "conflicts"),
+                                               _dev(best, "i32", 1, "best"), _stream(stream)))
+
+
+def _eval_args(g, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best, stream):
+    return (C.byref(g.struct), PROBLEMS[problem], penalty_lambda, S, _state(P, g.n, S, "P"),
+            _dev(size_or_cut, "i64", S, "size_or_cut"), _dev(viol, "i64", S, "viol"), _dev(obj, "i64", S, "obj"),
+            _dev(best, "i32", 1, "best"), _stream(stream))
 
 
 def qqa_dev_eval(g: DevGraph, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best, stream=None):
-    return _dev_check(lib().qqa_dev_eval(C.byref(g.struct), PROBLEMS[problem], penalty_lambda, S, _ptr(P),
-                                         _ptr(size_or_cut), _ptr(viol), _ptr(obj), _ptr(best), _stream(stream)))
+    return _dev_check(lib().qqa_dev_eval(*_eval_args(g, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best,
+                                                     stream)))
+
 
 
 # ---- request-level API ------------------------------------------------------------------------
@@ -365,6 +415,14 @@ class Context:
                                            None if sched is None else C.byref(sched), S, steps, seed, C.byref(rid)))
         return self._track(rid.value, st.n, S)
 
+    def serve_set_deadline(self, deadline_ms: float):
+        self._check(lib().qqa_serve_set_deadline(self._c, float(deadline_ms)))
+
+    def serve_stats(self) -> dict:
+        st = qqa_serve_stats()
+        self._check(lib().qqa_serve_get_stats(self._c, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in qqa_serve_stats._fields_}
+
     def serve_stop(self):
         self._check(lib().qqa_serve_stop(self._c))
 
@@ -392,4 +450,5 @@ class Context:
                       best_size_or_cut=res.best_size_or_cut, best_violations=res.best_violations, obj=objs,
                       size_or_cut=size, viol=viol, best_x=x, queue_ms=res.queue_ms, device_ms=res.device_ms,
                       step_loop_ms=res.step_loop_ms, latency_ms=res.latency_ms, kernel_us=res.kernel_us,
+                      first_update_ms=res.first_update_ms,
                       engine={v: k for k, v in ENGINES.items()}.get(res.engine, res.engine))

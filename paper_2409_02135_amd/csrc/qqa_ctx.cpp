@@ -22,9 +22,10 @@ namespace qqa {
 
 size_t request_footprint(int n, int S, int rule, int problem) {
   const size_t stride = (size_t)replica_shape(S).stride;
-  const size_t state = (size_t)n * stride * sizeof(float) * (rule == QQA_STEP_ADAMW ? 4 : 2);
+  // buffers as the pool rounds them
+  const size_t state = Pool::class_size((size_t)n * stride * sizeof(float)) * (rule == QQA_STEP_ADAMW ? 4 : 2);
   const size_t sums = problem == QQA_MAXCLIQUE ? stride * sizeof(unsigned long long) : 0;
-  return state + out_bytes(n, S) + 2 * stride * sizeof(unsigned long long) + sums + 4096;
+  return state + Pool::class_size(out_bytes(n, S)) + 2 * stride * sizeof(unsigned long long) + sums + 4096;
 }
 
 // result record: size_or_cut[S], viol[S], obj[S] (int64), best (int32) + pad, barrier
@@ -111,6 +112,13 @@ void graph_unref(qqa_ctx* c, int64_t gid) {
     free_graph(it->second);
     c->graphs.erase(it);
   }
+}
+
+// Idle pooled buffers count against the budget: when they would crowd out a new request,
+// they are freed first (hipFree waits for the device).
+bool budget_fits(qqa_ctx* c, size_t bytes) {
+  if (c->in_use + c->dpool.cached() + bytes > c->budget) c->dpool.trim();
+  return c->in_use + bytes <= c->budget;
 }
 
 int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks) {
@@ -318,7 +326,7 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
       r->footprint += r->table_bytes;
     }
   }
-  if (c->in_use + r->footprint > c->budget)
+  if (!budget_fits(c, r->footprint))
     return set_err(c, QQA_E_NOMEM, "HBM budget held by earlier requests; poll them first");
   int rc = alloc_request_buffers(c, r.get(), &c->err, g.nchunks);
   if (rc) return rc;
@@ -463,7 +471,7 @@ static int submit_coloring(qqa_ctx* c, int64_t gid, bool temp, int32_t colors, c
   r->footprint = state * (r->sched.rule == QQA_STEP_ADAMW ? 6 : 4) + (size_t)g.n * stride + out_bytes(g.n, S) +
                  2 * stride * sizeof(unsigned long long) + 4096;
   if (r->footprint + g.bytes > c->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the HBM budget");
-  if (c->in_use + r->footprint > c->budget)
+  if (!budget_fits(c, r->footprint))
     return set_err(c, QQA_E_NOMEM, "HBM budget held by earlier requests; poll them first");
   int rc = alloc_request_buffers(c, r.get(), &c->err, 0);
   if (rc) return rc;
@@ -709,7 +717,7 @@ int qqa_autotune(qqa_ctx* c, qqa_graph_id gid, qqa_problem problem, int32_t S, i
   if (compact) r.engine = kEngineCompact;
   const size_t fp = request_footprint(g.n, S, r.sched.rule, problem) + (size_t)g.nchunks * r.shape.stride * sizeof(float) +
                     (compact ? 4 * (size_t)g.n * sizeof(float) : 0);
-  if (c->in_use + fp > c->budget) return set_err(c, QQA_E_NOMEM, "no budget left for tuning state");
+  if (!budget_fits(c, fp)) return set_err(c, QQA_E_NOMEM, "no budget left for tuning state");
   int rc = alloc_request_buffers(c, &r, &c->err, g.nchunks);
   if (rc) return rc;
   const int warm = 3, timed = 12;
@@ -807,6 +815,7 @@ int qqa_poll(qqa_ctx* c, qqa_req id, qqa_result* out, int32_t timeout_us) {
     out->engine = r->engine;
     float ms = 0.f;
     out->queue_ms = r->queue_ms;
+    out->first_update_ms = r->queue_ms;
     out->device_ms = hipEventElapsedTime(&ms, r->ev[0], r->ev[3]) == hipSuccess ? ms : -1.0;
     out->step_loop_ms = hipEventElapsedTime(&ms, r->ev[1], r->ev[2]) == hipSuccess ? ms : -1.0;
     out->latency_ms = std::chrono::duration<double, std::milli>(t_done - r->t_submit).count();

@@ -97,8 +97,9 @@ struct qqa_ctx {
   size_t budget = 0;
   size_t in_use = 0;
   std::string err;
-  qqa::Pool dpool{false};
-  qqa::Pool hpool{true};
+  // idle buffers kept for reuse: up to 8 GiB of device memory, 1 GiB pinned
+  qqa::Pool dpool{false, size_t(8) << 30};
+  qqa::Pool hpool{true, size_t(1) << 30};
   std::unordered_map<int64_t, qqa::DevGraph> graphs;
   int64_t next_graph = 1;
   std::unordered_map<int64_t, std::unique_ptr<qqa::Request>> reqs;
@@ -126,6 +127,7 @@ int upload_graph_on(hipStream_t stream, const qqa_graph& g, int problem, DevGrap
                     bool validate);
 void free_graph(DevGraph& d);
 void graph_unref(qqa_ctx* c, int64_t gid);
+bool budget_fits(qqa_ctx* c, size_t bytes);  // frees idle pooled buffers when they crowd the budget
 int alloc_request_buffers(qqa_ctx* c, Request* r, std::string* why, int nchunks);
 void release_request_buffers(qqa_ctx* c, Request* r);
 StepParams request_step_params(const Request* r, const DevGraph& g);

@@ -181,35 +181,80 @@ void build_hub_plan(const int32_t* row_ptr, int n, std::vector<HubChunk>* chunks
 }
 
 // ---------------------------------------------------------------------------------------
-// device buffer pool: exact-size reuse, so repeated solves of one shape never call
-// hipMalloc / hipFree (both of which synchronise) after the first.
+// buffer pool: size-class reuse, so repeated solves of one shape, and of nearby shapes,
+// do not call hipMalloc / hipFree (both of which synchronise) after the first
 // ---------------------------------------------------------------------------------------
-hipError_t Pool::get(size_t bytes, void** out) {
+size_t Pool::class_size(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
-  auto it = free_.find(bytes);
-  if (it != free_.end()) {
-    *out = it->second;
-    free_.erase(it);
-    return hipSuccess;
+  if (bytes <= 4096) return bytes;
+  // eight classes between consecutive powers of two: m * 2^e with m in [8, 16)
+  int e = 63 - __builtin_clzll((unsigned long long)bytes) - 3;
+  const size_t step = size_t(1) << e;
+  return (bytes + step - 1) & ~(step - 1);
+}
+
+hipError_t Pool::get(size_t bytes, void** out) {
+  bytes = class_size(bytes);
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = free_.find(bytes);
+    if (it != free_.end()) {
+      *out = it->second;
+      cached_ -= bytes;
+      free_.erase(it);
+      return hipSuccess;
+    }
   }
   hipError_t e = pinned_ ? hipHostMalloc(out, bytes, hipHostMallocDefault) : hipMalloc(out, bytes);
-  if (e == hipSuccess) held_ += bytes;
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    trim();
+    e = pinned_ ? hipHostMalloc(out, bytes, hipHostMallocDefault) : hipMalloc(out, bytes);
+  }
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(mu_);
+    held_ += bytes;
+  }
   return e;
+}
+
+void Pool::release_locked(std::multimap<size_t, void*>::iterator it) {
+  if (pinned_) (void)hipHostFree(it->second);
+  else (void)hipFree(it->second);
+  held_ -= it->first;
+  cached_ -= it->first;
+  free_.erase(it);
 }
 
 void Pool::put(void* p, size_t bytes) {
   if (!p) return;
-  bytes = (bytes + 255) & ~size_t(255);
+  bytes = class_size(bytes);
+  std::lock_guard<std::mutex> lk(mu_);
   free_.emplace(bytes, p);
+  cached_ += bytes;
+  // over the cap: free the largest idle buffers first
+  while (cached_ > cap_ && !free_.empty()) release_locked(std::prev(free_.end()));
 }
 
 void Pool::trim() {
-  for (auto& kv : free_) {
-    if (pinned_) (void)hipHostFree(kv.second);
-    else (void)hipFree(kv.second);
-    held_ -= kv.first;
-  }
-  free_.clear();
+  std::lock_guard<std::mutex> lk(mu_);
+  while (!free_.empty()) release_locked(free_.begin());
+}
+
+size_t Pool::held() const {
+  std::lock_guard<std::mutex> lk(mu_);
+  return held_;
+}
+
+size_t Pool::cached() const {
+  std::lock_guard<std::mutex> lk(mu_);
+  return cached_;
+}
+
+void Pool::set_cap(size_t bytes) {
+  std::lock_guard<std::mutex> lk(mu_);
+  cap_ = bytes;
+  while (cached_ > cap_ && !free_.empty()) release_locked(std::prev(free_.end()));
 }
 
 }  // namespace qqa
@@ -679,16 +724,19 @@ int qqa_dev_replica_sums(const float* P, int32_t n, int32_t S, uint64_t* T, void
   return QQA_OK;
 }
 
-int qqa_dev_eval(const qqa_dev_graph* g, qqa_problem problem, int32_t penalty_lambda, int32_t S, const float* P,
-                 int64_t* size_or_cut, int64_t* viol, int64_t* obj, int32_t* best, void* stream) {
+static int eval_args(const qqa_dev_graph* g, qqa_problem problem, int32_t S, const float* P, int64_t* size_or_cut,
+                     int64_t* viol, int64_t* obj, int32_t* best) {
   if (!g || g->n < 0) return fail(&g_dev_error, QQA_E_ARG, "graph is NULL or n < 0");
   if (!g->dense && g->n > 0 && !g->row_ptr) return fail(&g_dev_error, QQA_E_ARG, "row_ptr missing");
   if (!known_problem(problem)) return fail(&g_dev_error, QQA_E_ARG, "unknown problem");
   if (S <= 0 || S > kMaxReplicas) return fail(&g_dev_error, QQA_E_ARG, "S must be in [1, 4096]");
   if (!size_or_cut || !viol || !obj || !best || (g->n > 0 && !P)) return fail(&g_dev_error, QQA_E_ARG, "output missing");
-  const ReplicaShape r = replica_shape(S);
-  unsigned long long* acc = nullptr;
-  DEV_CHECK(hipMallocAsync((void**)&acc, 2 * (size_t)r.stride * sizeof(unsigned long long), (hipStream_t)stream));
+  return QQA_OK;
+}
+
+static EvalParams eval_params(const qqa_dev_graph* g, qqa_problem problem, int32_t penalty_lambda, int32_t S,
+                              const float* P, int64_t* size_or_cut, int64_t* viol, int64_t* obj, int32_t* best,
+                              unsigned long long* acc) {
   EvalParams p{};
   p.row_ptr = g->row_ptr;
   p.col = g->col_idx;
@@ -697,7 +745,7 @@ int qqa_dev_eval(const qqa_dev_graph* g, qqa_problem problem, int32_t penalty_la
   p.P = P;
   p.n = g->n;
   p.S = S;
-  p.stride = r.stride;
+  p.stride = replica_shape(S).stride;
   p.problem = problem;
   p.lambda = penalty_lambda;
   p.acc = acc;
@@ -705,11 +753,23 @@ int qqa_dev_eval(const qqa_dev_graph* g, qqa_problem problem, int32_t penalty_la
   p.viol = viol;
   p.obj = obj;
   p.best = best;
+  return p;
+}
+
+int qqa_dev_eval(const qqa_dev_graph* g, qqa_problem problem, int32_t penalty_lambda, int32_t S, const float* P,
+                 int64_t* size_or_cut, int64_t* viol, int64_t* obj, int32_t* best, void* stream) {
+  int rc = eval_args(g, problem, S, P, size_or_cut, viol, obj, best);
+  if (rc) return rc;
+  const ReplicaShape r = replica_shape(S);
+  unsigned long long* acc = nullptr;
+  DEV_CHECK(hipMallocAsync((void**)&acc, 2 * (size_t)r.stride * sizeof(unsigned long long), (hipStream_t)stream));
+  const EvalParams p = eval_params(g, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best, acc);
   hipError_t e = launch_eval(p, (hipStream_t)stream);
   hipError_t e2 = hipFreeAsync(acc, (hipStream_t)stream);
   DEV_CHECK(e);
   DEV_CHECK(e2);
   return QQA_OK;
 }
+
 
 }  // extern "C"

@@ -216,7 +216,7 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
   run->footprint = arena;
   hipError_t e = hipSuccess;
   if (arena > c->budget) return set_err(c, QQA_E_ADMISSION, "batch footprint exceeds the HBM budget");
-  if (c->in_use + arena > c->budget) return set_err(c, QQA_E_NOMEM, "HBM budget held by earlier requests");
+  if (!budget_fits(c, arena)) return set_err(c, QQA_E_NOMEM, "HBM budget held by earlier requests");
   e = c->dpool.get(arena, (void**)&run->arena);
   if (e == hipSuccess) {
     run->arena_bytes = arena;

@@ -17,6 +17,15 @@
 // round boundary, so their work overlaps on the device.  Each slot runs the same row
 // arithmetic as a solve alone (the slot kernels share qqa_device.h), so a served result
 // equals the result of the same solve alone.
+//
+// Load shedding (optional, qqa_serve_set_deadline): a request is refused at submit when
+// its projected completion time exceeds the deadline.  Under least-remaining-work-first
+// a request of work w (rows x replica stride x updates) waits only for the pending work
+// W_< of requests with less remaining work, and for the work that arrives meanwhile in
+// requests no larger than w, at rate a_w; at a device rate R it then finishes after
+// (W_< + w) / (R - a_w) (the busy period of shortest-remaining-work scheduling), and no
+// sooner than its updates x the shortest update seen.  R is measured over rounds that fill
+// the device; a_w over the admitted submissions of the last few seconds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,6 +54,13 @@ constexpr int kRound = 16;
 // replica-variables per update launch beyond which more running slots add no throughput
 constexpr int64_t kRunElements = int64_t(8) << 20;
 constexpr int64_t kServerIdBase = int64_t(1) << 40;
+// the window over which the admitted work arriving per second is measured
+constexpr double kArrivalWindowS = 5.0;
+// device rate assumed before a round that fills the device has been measured
+constexpr double kInitialRate = 1e11;
+// idle buffers the server's pools keep for reuse
+constexpr size_t kDevicePoolCap = size_t(4) << 30;
+constexpr size_t kHostPoolCap = size_t(512) << 20;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 double ms_between(Clock::time_point a, Clock::time_point b) {
@@ -68,7 +84,10 @@ struct ServerReq {
   qqa_schedule sched{};
   uint64_t seed = 0;
   size_t footprint = 0;
-  Clock::time_point t_submit, t_admit, t_done;
+  double work = 0.0;      // rows x replica stride x updates
+  double rem_work = 0.0;  // the part not yet run (updated at round boundaries, under mu)
+  bool started = false;
+  Clock::time_point t_submit, t_admit, t_first, t_done;
   // while admitted
   DevGraph g;
   int slot = -1, lanes = 0, start = 0;
@@ -85,9 +104,16 @@ struct Server {
   int device = 0;
   int max_slots = 0;
   hipStream_t st = nullptr;
-  Pool dpool{false};
-  Pool hpool{true};
+  Pool dpool{false, kDevicePoolCap};
+  Pool hpool{true, kHostPoolCap};
   size_t budget = 0, in_use = 0;
+  // load shedding and its statistics (under mu)
+  double deadline_ms = 0.0;
+  double rate = kInitialRate;       // replica-variable updates per second, measured
+  double update_floor_s = 0.0;      // shortest time of one update seen
+  std::deque<std::pair<Clock::time_point, double>> recent;  // admitted submissions
+  int64_t n_submitted = 0, n_shed = 0, n_admitted = 0, n_completed = 0;
+  double projected_ms(const ServerReq& r, Clock::time_point now);
   std::unordered_map<int, int> layout;
   std::thread th;
   std::mutex mu;
@@ -116,7 +142,28 @@ size_t Server::footprint_of(const ServerReq& r) const {
   const SlotLayout L = slot_layout(r.n, r.S, r.sched.rule, r.nchunks);
   const size_t graph = 4 * (size_t)(r.n + 1) + 4 * (size_t)r.nnz + (r.problem == QQA_MAXCUT && !r.w.empty() ? 4 * r.nnz : 0) +
                        (size_t)r.nchunks * sizeof(HubChunk) + (r.nchunks ? 4 * (size_t)r.n : 0);
-  return L.bytes + align256(L.out_size) + align256((size_t)r.K * sizeof(float4)) + graph + 4096;
+  // the arena and the result buffer as the pool rounds them
+  return Pool::class_size(L.bytes + align256((size_t)r.K * sizeof(float4))) + Pool::class_size(L.out_size) + graph +
+         4096;
+}
+
+// Projected submit-to-result time of r if it were admitted now (see the header).  Under mu.
+double Server::projected_ms(const ServerReq& r, Clock::time_point now) {
+  double smaller = 0.0;
+  for (const auto& kv : all) {
+    const ServerReq& o = *kv.second;
+    if ((o.state == ServerReq::kQueued && !o.cancelled) || o.state == ServerReq::kActive)
+      if (o.rem_work <= r.work) smaller += o.rem_work;
+  }
+  while (!recent.empty() && std::chrono::duration<double>(now - recent.front().first).count() > kArrivalWindowS)
+    recent.pop_front();
+  double arriving = 0.0;
+  for (const auto& a : recent)
+    if (a.second <= r.work) arriving += a.second;
+  const double a_w = arriving / kArrivalWindowS;
+  const double alone = (double)r.K * update_floor_s;
+  if (a_w >= rate) return 1e300;
+  return 1e3 * std::max(alone, (smaller + r.work) / (rate - a_w));
 }
 
 void Server::fail_all(const std::string& msg) {
@@ -137,6 +184,8 @@ void Server::run() {
   std::vector<WorkItem> items, eval_items, init_items;
   std::vector<HubItem> hubs;
   std::vector<int32_t> ids;
+  Clock::time_point round_start{};
+  int64_t round_elements = 0;  // replica-variables per update of the last round
   for (;;) {
     hipError_t e = hipStreamSynchronize(st);  // round boundary: the device is idle
     if (e != hipSuccess) {
@@ -146,6 +195,15 @@ void Server::run() {
     std::vector<std::shared_ptr<ServerReq>> admit;
     {
       std::unique_lock<std::mutex> lk(mu);
+      if (round_elements > 0) {
+        const double dt = std::chrono::duration<double>(Clock::now() - round_start).count();
+        const double per_update = dt / kRound;
+        update_floor_s = update_floor_s > 0.0 ? std::min(update_floor_s, per_update) : per_update;
+        // the device rate, from rounds that fill the device
+        if (round_elements >= kRunElements / 2 && dt > 0.0)
+          rate = 0.8 * rate + 0.2 * ((double)round_elements * kRound / dt);
+        round_elements = 0;
+      }
       // retire slots whose evaluation and copy-back finished in the previous round
       for (auto& sp : slots) {
         if (!sp || sp->state != ServerReq::kFinishing) continue;
@@ -156,9 +214,13 @@ void Server::run() {
         sp->arena = sp->out_dev = nullptr;
         free_graph(sp->g);
         in_use -= sp->footprint;
+        ++n_completed;
         sp = nullptr;
       }
       cv_done.notify_all();
+      // idle pooled buffers count against the budget: free them when they would crowd out
+      // a queued request (the device is idle here, so freeing is safe)
+      if (!queue.empty() && in_use + dpool.cached() + queue.front()->footprint > budget) dpool.trim();
       // admit first-come-first-served while a slot is free and the footprint fits
       int free_slots = 0;
       for (auto& sp : slots) free_slots += sp == nullptr;
@@ -248,6 +310,7 @@ void Server::run() {
       }
     std::sort(by_work.begin(), by_work.end());
     std::map<std::pair<int, int>, std::vector<int>> cls_slots;
+    std::vector<int> running_slots;
     int64_t running = 0;
     int dirty0 = max_slots, dirty1 = -1;
     for (const auto& kv : by_work) {
@@ -255,6 +318,7 @@ void Server::run() {
       if (running < kRunElements) {
         running += (int64_t)r->n * qqa_replica_stride(r->S);
         cls_slots[{r->S, r->lanes}].push_back(kv.second);
+        running_slots.push_back(kv.second);
       } else {  // waits this round: its next update index is unchanged at the next boundary
         r->start += kRound;
         h_slots[kv.second].start = r->start;
@@ -329,6 +393,20 @@ void Server::run() {
       if (e == hipSuccess)
         e = launch_slot_init(d_slots, L_init + kv.second.first, (int)kv.second.second, kv.first.second, st);
     // kRound updates of every active slot
+    round_start = Clock::now();
+    round_elements = running;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (int s : running_slots) {
+        auto& r = slots[s];
+        if (!r->started) {
+          r->started = true;
+          r->t_first = round_start;
+        }
+        const int left = std::max(0, r->K - std::max(0, clock + kRound - r->start));
+        r->rem_work = (double)left * r->n * qqa_replica_stride(r->S);
+      }
+    }
     for (int r = 0; r < kRound && e == hipSuccess; ++r)
       for (auto& kv : item_range) {
         const auto hr = hub_range[kv.first];
@@ -388,6 +466,7 @@ int serve_poll(qqa_ctx* c, int64_t id, qqa_result* out, int32_t timeout_us) {
     view.out_host = r->out_host;
     fill_result(&view, out);
     out->queue_ms = ms_between(r->t_submit, r->t_admit);
+    out->first_update_ms = ms_between(r->t_submit, r->t_first);
     out->device_ms = ms_between(r->t_admit, r->t_done);
     out->step_loop_ms = out->device_ms;
     out->latency_ms = ms_between(r->t_submit, r->t_done);
@@ -524,18 +603,60 @@ int qqa_serve_submit(qqa_ctx* c, const qqa_graph* g, qqa_problem problem, const 
     r->nchunks = (int)chunks.size();
   }
   r->footprint = sv->footprint_of(*r);
+  r->work = (double)r->n * qqa_replica_stride(S) * steps;
+  r->rem_work = r->work;
   if (r->footprint > sv->budget) return set_err(c, QQA_E_ADMISSION, "request footprint exceeds the server's HBM budget");
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->failed) return set_err(c, QQA_E_DEVICE, sv->fail_msg);
     if (sv->stopping) return set_err(c, QQA_E_ARG, "server is stopping");
+    const auto now = Clock::now();
+    ++sv->n_submitted;
+    if (sv->deadline_ms > 0.0) {
+      const double ms = sv->projected_ms(*r, now);
+      if (ms > sv->deadline_ms) {
+        ++sv->n_shed;
+        char buf[160];
+        snprintf(buf, sizeof buf, "shed: projected completion %.0f ms exceeds the %.0f ms deadline", std::min(ms, 1e12),
+                 sv->deadline_ms);
+        return set_err(c, QQA_E_ADMISSION, buf);
+      }
+    }
+    ++sv->n_admitted;
+    sv->recent.emplace_back(now, r->work);
     r->id = sv->next_id++;
-    r->t_submit = Clock::now();
+    r->t_submit = now;
     sv->all.emplace(r->id, r);
     sv->queue.push_back(r);
   }
   sv->cv_work.notify_one();
   *out_id = r->id;
+  return QQA_OK;
+}
+
+int qqa_serve_set_deadline(qqa_ctx* c, double deadline_ms) {
+  if (!c) return QQA_E_ARG;
+  Server* sv = c->server.get();
+  if (!sv) return set_err(c, QQA_E_ARG, "server not started");
+  if (!(deadline_ms >= 0.0)) return set_err(c, QQA_E_ARG, "deadline must be >= 0");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  sv->deadline_ms = deadline_ms;
+  return QQA_OK;
+}
+
+int qqa_serve_get_stats(qqa_ctx* c, qqa_serve_stats* out) {
+  if (!c || !out) return QQA_E_ARG;
+  Server* sv = c->server.get();
+  if (!sv) return set_err(c, QQA_E_ARG, "server not started");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  out->submitted = sv->n_submitted;
+  out->admitted = sv->n_admitted;
+  out->shed = sv->n_shed;
+  out->completed = sv->n_completed;
+  out->rate_updates_per_s = sv->rate;
+  out->deadline_ms = sv->deadline_ms;
+  out->device_bytes_held = sv->dpool.held();
+  out->device_bytes_cached = sv->dpool.cached();
   return QQA_OK;
 }
 

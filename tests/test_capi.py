@@ -127,3 +127,27 @@ def test_maxcut_weight_rules(q):
     assert q.qqa_graph_validate(dense=W3, problem="maxcut")[0] == q.QQA_E_GRAPH
     assert q.qqa_graph_validate(dense=(W != 0).astype(np.float32), problem="mis")[0] == 0
     assert q.qqa_graph_validate(dense=W, problem="mis")[0] == q.QQA_E_GRAPH
+
+
+def test_device_entry_points_refuse_host_and_short_buffers(q):
+    # the binding checks every buffer a qqa_dev_* kernel would touch before any launch:
+    # host memory, a wrong element type or too few elements never reach the device
+    import torch
+    n, S = 10, 5  # stride 8
+    with pytest.raises(ValueError, match="device memory"):
+        q.qqa_dev_init(0, n, S, torch.zeros(n, 8))
+    with pytest.raises(ValueError, match="CUDA tensor"):
+        q.qqa_dev_init(0, n, S, np.zeros((n, 8), np.float32))
+    with pytest.raises(ValueError, match="dtype"):
+        q.qqa_dev_init(0, n, S, torch.zeros(n, 8, dtype=torch.float64))
+    with pytest.raises(ValueError, match="at least 80"):
+        q.qqa_dev_init(0, n, S, torch.zeros(n * 8 - 1))
+    g = q.DevGraph.__new__(q.DevGraph)
+    g.n = n
+    g.struct = q.qqa_dev_graph(n, 0, None, None, None, None)
+    with pytest.raises(ValueError, match="P_in: 79 elements"):
+        q.qqa_dev_step(g, "mis", None, S, 0, 10, 0, torch.zeros(79), torch.zeros(n, 8), None, None)
+    with pytest.raises(ValueError, match="P: dtype"):
+        q.qqa_dev_eval(g, "mis", 2, S, torch.zeros(n, 8, dtype=torch.int32), torch.zeros(S, dtype=torch.int64),
+                       torch.zeros(S, dtype=torch.int64), torch.zeros(S, dtype=torch.int32),
+                       torch.zeros(1, dtype=torch.int32))

@@ -64,6 +64,7 @@ def test_engine_matches_streaming_bitwise(name, make, problem, S, engine):
 
 
 def test_engine_one_update_matches_oracle(orc):
+    from test_gpu_parity import check_step, oracle_params, step_sensitivity  # the common per-step contract
     q = qqa()
     g = qi.erdos_renyi(3000, 5.0, 2)
     S, K, seed, t = 64, 100, 9, 17
@@ -76,11 +77,10 @@ def test_engine_one_update_matches_oracle(orc):
     sched = q.schedule("mis", g["n"])
     q.qqa_dev_run(q.DevGraph(g), "mis", sched, S, t, t + 1, K, seed, Pt[0], Pt[1], mt, vt, "persistent")
     torch.cuda.synchronize()
-    out = (Pt[(t + 1) & 1] if t % 2 == 0 else Pt[(t + 1) & 1]).cpu().numpy()
-    pr = orc.Params(lr=sched.lr, comm_alpha=sched.comm_alpha).as_float32()
-    ref = orc.step(pr, g, t, K, seed, P, m, v)
-    assert np.abs(out.astype(np.float64) - ref["P"]).max() <= 1e-5
-    assert np.allclose(mt.cpu().numpy(), ref["m"], rtol=1e-4, atol=1e-6)
+    out = Pt[(t + 1) & 1].cpu().numpy()
+    ref = orc.step(oracle_params(orc, q, sched, "mis"), g, t, K, seed, P, m, v)
+    sens = step_sensitivity(ref, m.astype(np.float64), v.astype(np.float64), t, sched, True)
+    check_step("persistent/t17", (out, mt.cpu().numpy(), vt.cpu().numpy()), ref, S, True, sched.beta1, sched.beta2, sens)
 
 
 def test_engine_rejections():

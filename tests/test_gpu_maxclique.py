@@ -124,6 +124,58 @@ def test_solve_consistent_and_repeatable():
     assert a["feasible"] and a["best_size_or_cut"] >= 15  # planted clique: 20
 
 
+def _clique_states(g, S, seed):
+    """Rounding-threshold values (exactly 1/2 rounds to 0, the next float up to 1), planted
+    cliques (feasible replicas), and duplicated replicas (tied objectives, which the lowest
+    index breaks)."""
+    rng = np.random.default_rng(seed)
+    n = g["n"]
+    half_up = np.nextafter(np.float32(0.5), np.float32(1))
+    vals = np.array([0.0, 1.0, 0.5, half_up, 0.2, 0.9], np.float32)
+    P = rng.choice(vals, size=(n, S), p=[0.55, 0.15, 0.1, 0.1, 0.05, 0.05]).astype(np.float32)
+    A = adjacency(g)
+    for s in range(0, S, 3):  # a greedy clique from a random start: no violations
+        P[:, s] = 0.0
+        order = rng.permutation(n)
+        chosen = []
+        for i in order[: min(n, 64)]:
+            if all(A[i, j] for j in chosen):
+                chosen.append(i)
+        P[chosen, s] = rng.choice(np.array([1.0, half_up], np.float32), size=len(chosen))
+        if s + 1 < S:
+            P[:, s + 1] = P[:, s]  # the same rounded solution: tied (violations, objective)
+    return P
+
+
+@pytest.mark.parametrize("gname", ["er300", "rb20x12"])
+@pytest.mark.parametrize("S", [1, 13, 64, 1000])
+def test_eval_bit_exact_against_oracle(orc, gname, S):
+    """Rounding and exact evaluation of max clique (selected pairs that are not adjacent,
+    l = -size + lambda * violations, the lexicographic best replica) against the oracle's,
+    every replica compared."""
+    q = qqa()
+    g = {"er300": lambda: qi.erdos_renyi(300, 60.0, 11), "rb20x12": lambda: qi.rb_model(20, 12, 2.6, 0.25, 0)}[gname]()
+    stride = q.qqa_replica_stride(S)
+    P = _clique_states(g, S, seed=S)
+    Pp = np.zeros((g["n"], stride), np.float32)
+    Pp[:, :S] = P
+    d = torch.device("cuda")
+    out = [torch.full((S,), -99, dtype=torch.int64, device=d) for _ in range(3)]
+    best = torch.full((1,), -5, dtype=torch.int32, device=d)
+    q.qqa_dev_eval(q.DevGraph(g), "maxclique", 2, S, torch.as_tensor(Pp, device=d), *out, best)
+    torch.cuda.synchronize()
+    got = [o.cpu().numpy() for o in out]
+    ref = orc.evaluate(2, 2, g, P)
+    for k, a in zip(("size_or_cut", "viol", "obj"), got):
+        assert np.array_equal(a, ref[k]), k
+    assert int(best.item()) == ref["best"]
+    assert ref["viol"].min() == 0  # feasible replicas exist, so the best is a clique
+    if S > 1:
+        # the duplicated replicas tie, and the lower index is the one reported
+        b = ref["best"]
+        assert not (b % 3 == 1 and ref["obj"][b - 1] == ref["obj"][b] and ref["viol"][b - 1] == ref["viol"][b])
+
+
 def test_ten_seed_quality_within_oracle_spread():
     q = qqa()
     wl = json.load(open(GOLD))["workloads"].get("rb20x12_maxclique_S32_K1000")

@@ -94,11 +94,10 @@ def check_step(label, gpu, ref, S, adam, beta1, beta2, sens=None, comm_alpha=0.1
     assert np.all(np.isfinite(Pg)) and Pg.min() >= 0 and Pg.max() <= 1, f"{label}: P out of box"
     g, gabs, sig = ref["g"], ref["gabs"], ref["sigma"][:, None]
     dg = ULPS * gabs
-    std_err = 0.0
     exempt = np.zeros(g.shape, bool)
     if sens is not None:
         # an update that leaves [0,1] by more than its own error bound clamps exactly
-        b = sens * (dg + std_err)
+        b = sens * dg
         pre = ref["pre_clamp"]
         exempt |= (b > TOL_P / 2) & (pre > -b) & (pre < 1.0 + b)
     n_ex = int(exempt.sum())
@@ -107,7 +106,7 @@ def check_step(label, gpu, ref, S, adam, beta1, beta2, sens=None, comm_alpha=0.1
     dP = dP_all[ok]
     stats = {"exempt": n_ex, "of": int(exempt.size), "max_dP": float(dP.max()) if dP.size else 0.0}
     if n_ex:
-        bound = TOL_P + 10 * (sens if sens is not None else 1.0) * (dg + std_err)
+        bound = TOL_P + 10 * (sens if sens is not None else 1.0) * dg
         stats["exempt_max_dP"] = float(dP_all[exempt].max())
         assert np.all(dP_all[exempt] <= np.minimum(bound, 1.0)[exempt]), f"{label}: exempt outside bound {stats}"
     if adam:

@@ -115,3 +115,60 @@ def test_cancel_and_drain():
     assert ctx.poll(first, timeout_us=0) is not None
     assert ctx.poll(later, timeout_us=0) is not None
     ctx.close()
+
+
+def test_shedding_refuses_by_projected_completion_and_admitted_equal_alone():
+    """With a deadline, a burst of large requests is admitted only while the projected
+    completion (the pending smaller work plus the request's own, at the measured device
+    rate) stays within it; the rest are refused at submit with QQA_E_ADMISSION.  Admitted
+    requests still equal their solves alone, and the counts add up."""
+    q = qqa()
+    ctx = q.Context(0)
+    ctx.serve_start(64)
+    ctx.serve_set_deadline(60.0)
+    g = qi.erdos_renyi(30000, 5.0, 7)  # 3.84 M replica-variables per update at S = 128
+    admitted, shed = [], 0
+    for k in range(20):
+        try:
+            admitted.append((ctx.serve_submit(g, "mis", 128, 500, 100 + k), 100 + k))
+        except q.QQAError as e:
+            assert e.code == q.QQA_E_ADMISSION and "shed" in str(e)
+            shed += 1
+    res = [(ctx.poll(i), sd) for i, sd in admitted]
+    st = ctx.serve_stats()
+    ctx.serve_stop()
+    assert shed > 0 and admitted
+    assert st["submitted"] == 20 and st["admitted"] == len(admitted) and st["shed"] == shed
+    assert st["completed"] == len(admitted) and st["rate_updates_per_s"] > 0
+    for r, sd in res[:3]:
+        alone = ctx.poll(ctx.solve(g, "mis", 128, 500, sd))
+        assert np.array_equal(r["obj"], alone["obj"]) and np.array_equal(r["best_x"], alone["best_x"])
+        assert 0 <= r["queue_ms"] <= r["first_update_ms"] <= r["latency_ms"]
+    # without a deadline nothing is shed
+    ctx.serve_start(64)
+    ids = [ctx.serve_submit(g, "mis", 128, 50, 300 + k) for k in range(6)]
+    for i in ids:
+        ctx.poll(i, want_x=False)
+    st = ctx.serve_stats()
+    assert st["shed"] == 0 and st["admitted"] == 6
+    ctx.serve_stop()
+    ctx.close()
+
+
+def test_server_pool_reuses_buffers_across_many_sizes():
+    """Requests of many distinct sizes one after another: the server's device pool reuses
+    buffers by size class, so what it holds stays far below the sum of the requests."""
+    q = qqa()
+    ctx = q.Context(0)
+    ctx.serve_start(8)
+    total = 0
+    for k in range(120):
+        n = 1000 + 33 * k
+        K = 20 + 3 * k
+        ctx.poll(ctx.serve_submit(qi.erdos_renyi(n, 4.0, 200 + k), "mis", 32, K, k), want_x=False)
+        total += 16 * n * 32 + 16 * K  # P twice, m, v and the schedule table
+    st = ctx.serve_stats()
+    ctx.serve_stop()
+    ctx.close()
+    print("held", st["device_bytes_held"], "cached", st["device_bytes_cached"], "sum", total)
+    assert st["device_bytes_held"] < total / 4
