@@ -390,6 +390,20 @@ int qqa_dev_eval(const qqa_dev_graph *g, qqa_problem problem, int32_t penalty_la
                  const float *P, int64_t *size_or_cut, int64_t *viol, int64_t *obj, int32_t *best,
                  void *stream);
 
+/* qqa_dev_eval for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, results
+ * and errors as qqa_dev_eval, but its per-replica accumulators live in a fixed 64 KiB
+ * device array of the library (2 x 4096 uint64, enough for every S <= 4096) instead of
+ * stream-ordered scratch, so it calls no allocator; it is launched as three kernels (a fill
+ * that clears the accumulators, the counts, the objectives) and no memset, copy or
+ * synchronisation.  Each GPU holds its own copy of the array from the first call on that
+ * device until the process ends.  Every call on one GPU shares that array: calls that may
+ * overlap on one GPU (different streams without ordering between them) race and must be
+ * serialised by the caller.  QQA_E_ARG for S outside [1, 4096]. */
+int qqa_dev_eval_noalloc(const qqa_dev_graph *g, qqa_problem problem, int32_t penalty_lambda, int32_t S,
+                         const float *P, int64_t *size_or_cut, int64_t *viol, int64_t *obj, int32_t *best,
+                         void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -108,6 +108,7 @@ def lib():
             "qqa_dev_run": (C.c_int, [vp, i32, vp, i32, i32, i32, i32, u64, vp, vp, vp, vp, i32, i32, vp]),
             "qqa_autotune": (C.c_int, [vp, i64, i32, i32, vp]),
             "qqa_dev_eval": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
+            "qqa_dev_eval_noalloc": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
             "qqa_dev_dense_coupling": (C.c_int, [vp, vp, vp, i32, i32, i32, vp]),
             "qqa_dev_replica_sums": (C.c_int, [vp, i32, i32, vp, vp]),
             "qqa_solve_coloring": (C.c_int, [vp, vp, i32, vp, i32, i32, u64, vp]),
@@ -285,6 +286,11 @@ def qqa_dev_eval(g: DevGraph, problem, penalty_lambda, S, P, size_or_cut, viol, 
     return _dev_check(lib().qqa_dev_eval(*_eval_args(g, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best,
                                                      stream)))
 
+
+def qqa_dev_eval_noalloc(g: DevGraph, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best, stream=None):
+    """qqa_dev_eval on the library's fixed device scratch (no allocation)."""
+    return _dev_check(lib().qqa_dev_eval_noalloc(*_eval_args(g, problem, penalty_lambda, S, P, size_or_cut, viol, obj,
+                                                             best, stream)))
 
 
 # ---- request-level API ------------------------------------------------------------------------

@@ -241,5 +241,7 @@ hipError_t launch_hub_partials(const StepParams& p, const HubChunk* chunks, int 
 hipError_t launch_eval(const EvalParams& p, hipStream_t st);
 hipError_t launch_extract(const float* P, int n, int stride, const int32_t* best, uint8_t* x, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, size_t count, hipStream_t st);
+// the evaluation's fixed device scratch on the current device: address and size in words
+hipError_t eval_scratch(unsigned long long** out, size_t* words);
 
 }  // namespace qqa

@@ -771,5 +771,21 @@ int qqa_dev_eval(const qqa_dev_graph* g, qqa_problem problem, int32_t penalty_la
   return QQA_OK;
 }
 
+int qqa_dev_eval_noalloc(const qqa_dev_graph* g, qqa_problem problem, int32_t penalty_lambda, int32_t S,
+                         const float* P, int64_t* size_or_cut, int64_t* viol, int64_t* obj, int32_t* best,
+                         void* stream) {
+  int rc = eval_args(g, problem, S, P, size_or_cut, viol, obj, best);
+  if (rc) return rc;
+  unsigned long long* acc = nullptr;
+  size_t words = 0;
+  DEV_CHECK(eval_scratch(&acc, &words));
+  const ReplicaShape r = replica_shape(S);
+  if (2 * (size_t)r.stride > words)
+    return fail(&g_dev_error, QQA_E_ARG, "replica stride exceeds the fixed evaluation scratch (2 x 4096 words)");
+  // launch_eval clears the accumulators with a fill kernel before the counts
+  DEV_CHECK(launch_eval(eval_params(g, problem, penalty_lambda, S, P, size_or_cut, viol, obj, best, acc),
+                        (hipStream_t)stream));
+  return QQA_OK;
+}
 
 }  // extern "C"
