@@ -184,7 +184,7 @@ void Server::run() {
   std::vector<WorkItem> items, eval_items, init_items;
   std::vector<HubItem> hubs;
   std::vector<int32_t> ids;
-  Clock::time_point round_start{};
+  Clock::time_point round_start{}, boundary = Clock::now();
   int64_t round_elements = 0;  // replica-variables per update of the last round
   for (;;) {
     hipError_t e = hipStreamSynchronize(st);  // round boundary: the device is idle
@@ -195,15 +195,18 @@ void Server::run() {
     std::vector<std::shared_ptr<ServerReq>> admit;
     {
       std::unique_lock<std::mutex> lk(mu);
+      const auto now = Clock::now();
       if (round_elements > 0) {
-        const double dt = std::chrono::duration<double>(Clock::now() - round_start).count();
-        const double per_update = dt / kRound;
+        const double per_update = std::chrono::duration<double>(now - round_start).count() / kRound;
         update_floor_s = update_floor_s > 0.0 ? std::min(update_floor_s, per_update) : per_update;
-        // the device rate, from rounds that fill the device
+        // the device rate, from rounds that fill the device, over the whole loop from one
+        // round boundary to the next (admission, uploads and list building included)
+        const double dt = std::chrono::duration<double>(now - boundary).count();
         if (round_elements >= kRunElements / 2 && dt > 0.0)
           rate = 0.8 * rate + 0.2 * ((double)round_elements * kRound / dt);
         round_elements = 0;
       }
+      boundary = now;
       // retire slots whose evaluation and copy-back finished in the previous round
       for (auto& sp : slots) {
         if (!sp || sp->state != ServerReq::kFinishing) continue;

@@ -15,11 +15,12 @@ def test_traffic_records_match_workload_and_source():
     cases = [("step_kernel_traffic.json", bench.DEVICE_SOURCES),
              ("slice_step_traffic.json", bench.SLICE_SOURCES),
              ("compact_step_traffic.json", bench.COMPACT_SOURCES),
-             ("dense_tile128_kernel_traffic.json", bench.DENSE_SOURCES)]
+             ("dense_tile128_kernel_traffic.json", bench.DENSE_SOURCES),
+             ("slot_step_traffic.json", bench.SLOT_SOURCES)]
     for name, sources in cases:
         recs = json.load(open(os.path.join(ROOT, "profiles", name)))
         for rec in recs if isinstance(recs, list) else [recs]:
-            assert rec["workload"] in bench.WORKLOADS, (name, rec["workload"])
+            assert rec["workload"] in bench.WORKLOADS or rec["workload"] == bench.BATCH_WORKLOAD, (name, rec["workload"])
             got = bench.traffic_from_profiles(name, sources, rec["workload"])
             if rec["kernel_source_sha256"] == bench.source_hash(sources):
                 assert got == rec["bytes_per_launch"]
