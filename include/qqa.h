@@ -165,7 +165,15 @@ typedef struct {
  * roundings of the method do.  It is deterministic and resumable like the others.
  * COMPACT: one replica per variable (S = 1, sparse MIS or max-cut): P, m, v held as one
  * float per variable instead of a padded quad, one lane per variable, one launch per
- * update; bitwise STREAM's results at one lane per row (the default layout for S = 1). */
+ * update; bitwise STREAM's results at one lane per row (the default layout for S = 1).
+ * BATCH_RESIDENT: a ragged batch (qqa_solve_batch) in one cooperative launch for all of its
+ * updates: each instance is run by a team of workgroups on one XCD whose lane groups keep
+ * their rows' p, m, v in registers, the new P of every update is shared through that XCD's
+ * L2, and the team meets at a barrier between updates.  Used by qqa_solve_batch under the
+ * automatic policy when all instances share one replica layout with one quad per lane
+ * (S = 4 x lanes per row), none has rows split into chunks, and each instance's rows fit
+ * the registers of one XCD's workgroups; otherwise, and under QQA_ENGINE_STREAM, a batch
+ * runs as BATCH.  Same arithmetic per row as STREAM: identical results. */
 typedef enum {
     QQA_ENGINE_AUTO = -1,
     QQA_ENGINE_STREAM = 0,
@@ -173,7 +181,8 @@ typedef enum {
     QQA_ENGINE_LDS_BLOCK = 2,
     QQA_ENGINE_BATCH = 3,
     QQA_ENGINE_SLICED = 4,
-    QQA_ENGINE_COMPACT = 5
+    QQA_ENGINE_COMPACT = 5,
+    QQA_ENGINE_BATCH_RESIDENT = 6
 } qqa_engine;
 
 /* device: HIP ordinal.  hbm_budget_bytes: cap on the device memory the context may

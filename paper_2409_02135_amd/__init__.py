@@ -23,8 +23,9 @@ QQA_E_DEVICE, QQA_E_UNKNOWN_REQ, QQA_E_CANCELLED = -5, -6, -7
 QQA_MIS, QQA_MAXCUT, QQA_MAXCLIQUE, QQA_COLORING = 0, 1, 2, 3
 QQA_STEP_ADAMW, QQA_STEP_LANGEVIN = 0, 1
 QQA_ENGINE_AUTO, QQA_ENGINE_STREAM, QQA_ENGINE_PERSISTENT, QQA_ENGINE_LDS_BLOCK, QQA_ENGINE_BATCH = -1, 0, 1, 2, 3
-QQA_ENGINE_SLICED, QQA_ENGINE_COMPACT = 4, 5
-ENGINES = {"auto": -1, "stream": 0, "persistent": 1, "lds_block": 2, "batch": 3, "sliced": 4, "compact": 5}
+QQA_ENGINE_SLICED, QQA_ENGINE_COMPACT, QQA_ENGINE_BATCH_RESIDENT = 4, 5, 6
+ENGINES = {"auto": -1, "stream": 0, "persistent": 1, "lds_block": 2, "batch": 3, "sliced": 4, "compact": 5,
+           "batch_resident": 6}
 
 PROBLEMS = {"mis": QQA_MIS, "maxcut": QQA_MAXCUT, "maxclique": QQA_MAXCLIQUE, "coloring": QQA_COLORING,
             QQA_MIS: QQA_MIS, QQA_MAXCUT: QQA_MAXCUT, QQA_MAXCLIQUE: QQA_MAXCLIQUE, QQA_COLORING: QQA_COLORING}

@@ -15,7 +15,7 @@ LIB = os.path.join(PKG, "libqqa.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["qqa_kernels.hip", "qqa_scratch.hip", "qqa_slots.hip", "qqa_persist.hip", "qqa_dense.hip", "qqa_color.hip", "qqa_slice.hip", "qqa_compact.hip", "qqa_runtime.cpp", "qqa_ctx.cpp", "qqa_serve.cpp", "qqa_server.cpp"]
+SOURCES = ["qqa_kernels.hip", "qqa_scratch.hip", "qqa_slots.hip", "qqa_persist.hip", "qqa_dense.hip", "qqa_color.hip", "qqa_slice.hip", "qqa_compact.hip", "qqa_resident.hip", "qqa_runtime.cpp", "qqa_ctx.cpp", "qqa_serve.cpp", "qqa_server.cpp"]
 HEADERS = ["qqa_internal.h", "qqa_runtime.h", "qqa_ctx.h", "qqa_device.h", "qqa_batch.h"]
 
 FLAGS = [

@@ -810,6 +810,8 @@ int qqa_poll(qqa_ctx* c, qqa_req id, qqa_result* out, int32_t timeout_us) {
     rc = set_err(c, QQA_E_CANCELLED, "request was cancelled");
   } else if ((r->engine == kEnginePersistent || r->engine == kEngineLdsBlock) && out_bar(r->out_host, r->S)[1] != 0u) {
     rc = set_err(c, QQA_E_DEVICE, "persistent engine: grid barrier timed out");
+  } else if (r->engine == kEngineResident && out_bar(r->out_host, r->S)[1] != 0u) {
+    rc = set_err(c, QQA_E_DEVICE, "resident batch engine: a team barrier timed out");
   } else if (out) {
     fill_result(r, out);
     out->engine = r->engine;

@@ -144,12 +144,50 @@ struct PersistParams {
   int32_t t0, t1;
   unsigned* bar;                // [0] arrivals (zero before the launch), [1] abort flag
 };
-enum PersistEngine { kEngineStream = 0, kEnginePersistent = 1, kEngineLdsBlock = 2, kEngineSliced = 4, kEngineCompact = 5 };
+enum PersistEngine {
+  kEngineStream = 0, kEnginePersistent = 1, kEngineLdsBlock = 2, kEngineBatch = 3, kEngineSliced = 4, kEngineCompact = 5,
+  kEngineResident = 6
+};
 // Which engine can run this instance (FULL layouts with one quad per lane, no split
 // rows); `allow` is a mask (1: one workgroup with P in LDS, 2: many workgroups with state
 // in registers).  Fills rows per group and the grid for the chosen one.
 int persistent_plan(const StepParams& a, bool has_hubs, int allow, int* rows_per_group, int* grid);
 hipError_t launch_persistent(const PersistParams& pp, int engine, int rows_per_group, int grid, hipStream_t st);
+
+// ---- resident batch engine -----------------------------------------------------------------
+// One cooperative launch runs every update of a batch whose instances all use one layout
+// with one quad per lane and have no split rows.  Each instance (job) is run by a team of
+// `team` workgroups on one XCD, p, m, v in registers, P shared through that XCD's L2; the
+// team meets at a barrier between updates (bounded by timeout_ticks of the 100 MHz wall
+// clock; on time-out *abort is raised and every workgroup returns).
+constexpr int kResidentXcds = 8;
+constexpr int kResidentRowsPerGroup = 2;  // rows whose state each lane group holds
+struct ResidentJob {
+  int32_t slot;         // slot descriptor of the instance
+  int32_t team;         // workgroups that run it (at most 128)
+  int32_t first_place;  // its first team place among the places of its XCD
+  int32_t flag_base;    // its members' barrier flags: flags[(flag_base + member) * kFlagWords]
+};
+constexpr int kFlagWords = 16;  // one 64-byte line per barrier flag
+constexpr int kResidentMaxTeam = 128;
+struct ResidentParams {
+  const SlotDesc* slots;
+  const ResidentJob* jobs;    // grouped by XCD, in claim order
+  const int32_t* xcd_jobs;    // [kResidentXcds + 1]: XCD x runs jobs [xcd_jobs[x], xcd_jobs[x + 1])
+  const int32_t* xcd_places;  // [kResidentXcds]: team places of XCD x (its jobs' teams summed)
+  unsigned* claim;            // [kResidentXcds] places claimed (zero before the launch)
+  unsigned* flags;            // barrier flags, kFlagWords per team member (zero before the launch)
+  unsigned* abort;            // [1] raised when a barrier times out (zero before the launch)
+  unsigned* done;             // [1] jobs completed (zero before the launch)
+  long long timeout_ticks;    // longest wait at one barrier, in wall-clock ticks
+};
+// Co-resident workgroups of the kernel for a (lanes per row, rows per lane group) shape,
+// 0 if the shape is not built.
+int resident_workgroups(int lanes_per_row, int rows_per_group);
+// The launch, then a kernel that writes each slot's outcome into its result record's
+// barrier word [1] (0: every job ran to completion).
+hipError_t launch_resident(const ResidentParams& rp, int lanes_per_row, int rows_per_group, int grid, int nslots,
+                           int njobs, hipStream_t st);
 
 // Dense coupling product C = W f(P) on the matrix cores (W symmetric n x n, P and C
 // n x stride; f(p) = 2p - 1 for max-cut, p for MIS).

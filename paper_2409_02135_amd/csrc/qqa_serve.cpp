@@ -190,6 +190,61 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     append_items(i, *inst[i].g, inst[i].lanes, &lc.items, &lc.hubs);
     lc.ids.push_back(i);
   }
+  // The resident engine runs the batch when every instance shares one layout with one quad
+  // per lane, none has split rows, and each instance's team fits the workgroups one XCD
+  // holds; the automatic policy uses it then, QQA_ENGINE_STREAM keeps the slot launches.
+  bool resident = c->engine_policy < 0 && classes.size() == 1;
+  int res_lanes = 0, res_grid = 0, rows_per_wg = 0;
+  if (resident) {
+    const LayoutClass& lc = classes.begin()->second;
+    const ReplicaShape sh = replica_shape(lc.S, lc.lanes);
+    res_lanes = sh.lpr;
+    resident = sh.qpl == 1 && lc.S == 4 * sh.lpr;
+    for (int i = 0; i < count && resident; ++i) resident = inst[i].g->nchunks == 0;
+    if (resident) {
+      res_grid = resident_workgroups(res_lanes, kResidentRowsPerGroup);
+      rows_per_wg = (kBlock / res_lanes) * kResidentRowsPerGroup;
+      int max_team = 0;
+      for (int i = 0; i < count; ++i) max_team = std::max(max_team, (inst[i].g->n + rows_per_wg - 1) / rows_per_wg);
+      resident = res_grid >= kResidentXcds && max_team <= std::min(kResidentMaxTeam, res_grid / kResidentXcds);
+    }
+  }
+  std::vector<ResidentJob> jobs;
+  std::vector<int32_t> xcd_jobs(kResidentXcds + 1, 0), xcd_places(kResidentXcds, 0);
+  double longest_xcd_updates = 0.0;
+  if (resident) {
+    // longest processing time first: each instance, largest team x updates first, goes to
+    // the XCD with the least work so far; an XCD claims its jobs in that order
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    auto team_of = [&](int i) { return (inst[i].g->n + rows_per_wg - 1) / rows_per_wg; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return (int64_t)team_of(a) * inst[a].K > (int64_t)team_of(b) * inst[b].K;
+    });
+    std::vector<std::vector<int>> per(kResidentXcds);
+    std::vector<int64_t> load(kResidentXcds, 0);
+    std::vector<double> updates(kResidentXcds, 0.0);
+    for (int i : order) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      per[x].push_back(i);
+      load[x] += (int64_t)team_of(i) * inst[i].K;
+      updates[x] += inst[i].K;
+    }
+    int32_t flag = 0;
+    for (int x = 0; x < kResidentXcds; ++x) {
+      xcd_jobs[x] = (int32_t)jobs.size();
+      int32_t place = 0;
+      for (int i : per[x]) {
+        jobs.push_back(ResidentJob{i, team_of(i), place, flag});
+        place += team_of(i);
+        flag += team_of(i);
+      }
+      xcd_places[x] = place;
+      longest_xcd_updates = std::max(longest_xcd_updates, updates[x]);
+    }
+    xcd_jobs[kResidentXcds] = (int32_t)jobs.size();
+  }
+
   // arena tail: tables, slot descriptors, work lists, clock, then the result records
   std::vector<size_t> table_off(tables.size());
   for (size_t k = 0; k < tables.size(); ++k) {
@@ -209,6 +264,17 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
   }
   const size_t off_clock = arena;
   arena += 256;
+  // resident engine tables and counters (zero in the uploaded image)
+  const size_t off_jobs = arena;
+  arena += align256(jobs.size() * sizeof(ResidentJob));
+  const size_t off_xcd = arena;
+  arena += align256((2 * kResidentXcds + 1) * sizeof(int32_t));
+  size_t flag_count = 0;
+  for (const ResidentJob& j : jobs) flag_count += (size_t)j.team;
+  const size_t off_counters = arena;
+  arena += align256((kResidentXcds + 2) * sizeof(unsigned));
+  const size_t off_flags = arena;
+  arena += align256(flag_count * kFlagWords * sizeof(unsigned));
   const size_t off_out = arena;
   arena += out_total;
 
@@ -245,6 +311,12 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     std::memcpy(image.data() + lc.off_hubs, lc.hubs.data(), lc.hubs.size() * sizeof(HubItem));
     std::memcpy(image.data() + lc.off_ids, lc.ids.data(), lc.ids.size() * sizeof(int32_t));
   }
+  if (resident) {
+    std::memcpy(image.data() + off_jobs, jobs.data(), jobs.size() * sizeof(ResidentJob));
+    std::memcpy(image.data() + off_xcd, xcd_jobs.data(), xcd_jobs.size() * sizeof(int32_t));
+    std::memcpy(image.data() + off_xcd + xcd_jobs.size() * sizeof(int32_t), xcd_places.data(),
+                xcd_places.size() * sizeof(int32_t));
+  }
   const SlotDesc* d_slots = reinterpret_cast<const SlotDesc*>(A + off_slots);
   int32_t* d_clock = reinterpret_cast<int32_t*>(A + off_clock);
   hipStream_t st = c->stream;
@@ -263,10 +335,28 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
   }
   if (e == hipSuccess) e = hipEventRecord(run->ev[1], st);
   // the update loop: R launches per layout class and a clock advance, captured once and
-  // replayed until the longest instance has run all of its updates
+  // replayed until the longest instance has run all of its updates; or one resident launch
   const int R = std::min(maxK, 64);
-  if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
+  if (resident && e == hipSuccess) {
+    ResidentParams rp{};
+    rp.slots = d_slots;
+    rp.jobs = reinterpret_cast<const ResidentJob*>(A + off_jobs);
+    rp.xcd_jobs = reinterpret_cast<const int32_t*>(A + off_xcd);
+    rp.xcd_places = rp.xcd_jobs + kResidentXcds + 1;
+    unsigned* counters = reinterpret_cast<unsigned*>(A + off_counters);
+    rp.claim = counters;
+    rp.abort = counters + kResidentXcds;
+    rp.done = counters + kResidentXcds + 1;
+    rp.flags = reinterpret_cast<unsigned*>(A + off_flags);
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || khz <= 0)
+      khz = 100000;
+    // a barrier may wait for the XCD's earlier jobs to free workgroups: allow 10 s plus
+    // 100 us for every update those jobs run
+    rp.timeout_ticks = (long long)((10.0 + 1e-4 * longest_xcd_updates) * 1e3 * khz);
+    e = launch_resident(rp, res_lanes, kResidentRowsPerGroup, res_grid, count, count, st);
+  } else if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (!resident && e == hipSuccess) {
     hipError_t ce = hipSuccess;
     for (int r = 0; r < R && ce == hipSuccess; ++r)
       for (auto& kv : classes) {
@@ -282,8 +372,8 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     e = hipStreamEndCapture(st, &run->graph);
     if (e == hipSuccess) e = ce;
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&run->exec, run->graph, nullptr, nullptr, 0);
-  for (int done = 0; done < maxK && e == hipSuccess; done += R) e = hipGraphLaunch(run->exec, st);
+  if (!resident && e == hipSuccess) e = hipGraphInstantiate(&run->exec, run->graph, nullptr, nullptr, 0);
+  for (int done = 0; !resident && done < maxK && e == hipSuccess; done += R) e = hipGraphLaunch(run->exec, st);
   if (e == hipSuccess) e = hipEventRecord(run->ev[2], st);
   for (auto& kv : classes) {
     const LayoutClass& lc = kv.second;
@@ -311,7 +401,7 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     r->seed = I.seed;
     r->shape = replica_shape(I.S);
     r->lanes_per_row = I.lanes;
-    r->engine = 3;
+    r->engine = resident ? kEngineResident : kEngineBatch;
     r->out_host = run->host_out + I.out_off;
     r->out_size = I.L.out_size;
     for (int k = 0; k < 4; ++k) r->ev[k] = run->ev[k];

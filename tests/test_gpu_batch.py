@@ -99,3 +99,77 @@ def test_batch_equals_alone_with_edge_split_layouts():
     for gid in gids:
         c.release(gid)
     c.close()
+
+
+def _one_width(count, S, seed, n_range=(30, 5000)):
+    """`count` ER instances with ragged n, mean degree and update counts, MIS and +-1 max-cut;
+    every row below the split threshold, so one replica layout serves all of them."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n = int(rng.integers(*n_range))
+        g = qi.erdos_renyi(n, float(rng.uniform(3, 20)), seed * 1000 + k)
+        problem = "maxcut" if k % 3 == 1 else "mis"
+        if problem == "maxcut":
+            g = qi.pm1_weights(g, k)
+        out.append((g, problem, S, int(rng.integers(30, 200)), 500 + k))
+    return out
+
+
+def _run_batch(c, inst):
+    gids = [c.upload(g, p) for g, p, *_ in inst]
+    ids = c.solve_batch(gids, [g["n"] for g, *_ in inst], [p for _, p, *_ in inst], [i[2] for i in inst],
+                        [i[3] for i in inst], [i[4] for i in inst])
+    return gids, [c.poll(i) for i in ids]
+
+
+def _check_alone(c, inst, gids, batched):
+    for (g, p, S, K, seed), gid, b in zip(inst, gids, batched):
+        alone = c.poll(c.solve_resident(gid, g["n"], p, S, K, seed))
+        assert np.array_equal(b["obj"], alone["obj"]), (g["n"], p, S, K)
+        assert np.array_equal(b["size_or_cut"], alone["size_or_cut"])
+        assert np.array_equal(b["viol"], alone["viol"])
+        assert np.array_equal(b["best_x"], alone["best_x"])
+        assert b["best_replica"] == alone["best_replica"]
+    for gid in gids:
+        c.release(gid)
+
+
+@pytest.mark.parametrize("S", [32, 16, 128])
+def test_resident_batch_equals_alone_bitwise(ctx, S):
+    """One layout, one quad per lane, no split rows: the whole batch runs in one resident
+    launch (teams of workgroups on one XCD, state in registers, P through the XCD's L2), and
+    every instance ends with the bits of its solve alone."""
+    # at 128 replicas a lane group holds two rows of 32 lanes: about 2,000 rows fit one XCD
+    inst = _one_width(40 if S == 32 else 12, S, S, n_range=(30, 2000) if S == 128 else (30, 5000))
+    gids, batched = _run_batch(ctx, inst)
+    assert all(b["engine"] == "batch_resident" for b in batched), batched[0]["engine"]
+    print("S", S, "update loop ms", batched[0]["step_loop_ms"], flush=True)
+    _check_alone(ctx, inst, gids, batched)
+
+
+def test_resident_batch_repeatable_and_policy_fallbacks(ctx):
+    inst = _one_width(10, 32, 7)
+    gids, a = _run_batch(ctx, inst)
+    gb, b = _run_batch(ctx, inst)
+    for x, y in zip(a, b):
+        assert np.array_equal(x["obj"], y["obj"]) and np.array_equal(x["best_x"], y["best_x"])
+    # the slot launches give the same bits
+    ctx.set_engine("stream")
+    gs, s = _run_batch(ctx, inst)
+    ctx.set_engine("auto")
+    for gid in gb + gs:
+        ctx.release(gid)
+    assert all(r["engine"] == "batch" for r in s)
+    for x, y in zip(a, s):
+        assert np.array_equal(x["obj"], y["obj"]) and np.array_equal(x["best_x"], y["best_x"])
+    for gid in gids:
+        ctx.release(gid)
+    # split rows, several layouts, or an instance beyond one XCD's registers: slot launches
+    hub = [(qi.pm1_weights(qi.barabasi_albert(3000, 4, 1), 2), "maxcut", 32, 40, 1)] + _one_width(3, 32, 8)
+    mixed = _one_width(3, 32, 9) + _one_width(3, 16, 10)
+    big = [(qi.erdos_renyi(20000, 4.0, 11), "mis", 32, 30, 3)] + _one_width(2, 32, 12)
+    for inst in (hub, mixed, big):
+        gids, res = _run_batch(ctx, inst)
+        assert all(r["engine"] == "batch" for r in res)
+        _check_alone(ctx, inst, gids, res)
