@@ -109,6 +109,7 @@ DENSE_SOURCES = ["qqa_dense.hip"]
 SLICE_SOURCES = ["qqa_device.h", "qqa_slice.hip"]
 COMPACT_SOURCES = ["qqa_device.h", "qqa_compact.hip"]
 SLOT_SOURCES = ["qqa_device.h", "qqa_slots.hip"]
+RESIDENT_SOURCES = ["qqa_device.h", "qqa_resident.hip"]
 BATCH_WORKLOAD = "batch512_er_n200-5000_d3-20_S32_K2000"
 
 
@@ -194,8 +195,11 @@ def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True):
                               "update_us": float(rs[0]["step_loop_ms"]) * 1e3 / K},
             "roofline": {"bound": "hbm", "kernel": "resident_kernel" if rb[0]["engine"] == "batch_resident"
                          else "slot_step_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                         "traffic": (traffic_from_profiles("slot_step_traffic.json", SLOT_SOURCES, BATCH_WORKLOAD)
-                                     if rb[0]["engine"] == "batch" and count == 512 and K == 2000 and S == 32 else None),
+                         # measured bytes per update, from the counter record of the engine that ran
+                         "traffic": (traffic_from_profiles(*({"batch": ("slot_step_traffic.json", SLOT_SOURCES),
+                                                              "batch_resident": ("resident_traffic.json", RESIDENT_SOURCES)}
+                                                             [rb[0]["engine"]]), BATCH_WORKLOAD)
+                                     if count == 512 and K == 2000 and S == 32 else None),
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "algorithmic_bytes_per_update": abytes, "update_us": loop_us,
                          "basis": "device time of the batched update loop (events on the solver stream) / updates"},

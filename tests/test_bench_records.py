@@ -16,7 +16,8 @@ def test_traffic_records_match_workload_and_source():
              ("slice_step_traffic.json", bench.SLICE_SOURCES),
              ("compact_step_traffic.json", bench.COMPACT_SOURCES),
              ("dense_tile128_kernel_traffic.json", bench.DENSE_SOURCES),
-             ("slot_step_traffic.json", bench.SLOT_SOURCES)]
+             ("slot_step_traffic.json", bench.SLOT_SOURCES),
+             ("resident_traffic.json", bench.RESIDENT_SOURCES)]
     for name, sources in cases:
         recs = json.load(open(os.path.join(ROOT, "profiles", name)))
         for rec in recs if isinstance(recs, list) else [recs]:
@@ -27,7 +28,8 @@ def test_traffic_records_match_workload_and_source():
                 # FETCH_SIZE scaled by what a plain copy reads back, WRITE_SIZE as counted (KiB)
                 f = rec.get("fetch_kib_per_dispatch", rec.get("fetch_kib_per_dispatch_raw"))
                 w = rec.get("write_kib_per_dispatch", rec.get("write_kib_per_dispatch_raw"))
-                assert abs(1024 * (f * rec["fetch_scale"] + w * rec["write_scale"]) - got) < 2.0, name
+                per = rec.get("updates_per_dispatch", 1)
+                assert abs(1024 * (f * rec["fetch_scale"] + w * rec["write_scale"]) / per - got) < 2.0, name
             else:
                 assert got is None
         # another workload never borrows a record
