@@ -292,7 +292,7 @@ int qqa_cancel(qqa_ctx *c, qqa_req id);
  *     the pending work with less remaining work than its own, W_<, and for smaller work
  *     arriving meanwhile at the rate a_w measured over the admitted submissions of the last
  *     5 s; at the device rate R (replica-variable updates per second, measured over rounds
- *     that fill the device) it finishes after (W_< + w) / (R - a_w), and no sooner than its
+ *     that leave work waiting) it finishes after (W_< + w) / (R - a_w), and no sooner than its
  *     updates times the shortest update time seen.  0 (the default) sheds nothing.
  *   qqa_serve_get_stats: counts of submitted, admitted, shed and completed requests since
  *     qqa_serve_start, the measured device rate and the server's device memory.

@@ -24,8 +24,9 @@
 // W_< of requests with less remaining work, and for the work that arrives meanwhile in
 // requests no larger than w, at rate a_w; at a device rate R it then finishes after
 // (W_< + w) / (R - a_w) (the busy period of shortest-remaining-work scheduling), and no
-// sooner than its updates x the shortest update seen.  R is measured over rounds that fill
-// the device; a_w over the admitted submissions of the last few seconds.
+// sooner than its updates x the shortest update seen.  R is measured over rounds that leave
+// work waiting (so the device could do no more); a_w over the admitted submissions of the
+// last few seconds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -186,6 +187,7 @@ void Server::run() {
   std::vector<int32_t> ids;
   Clock::time_point round_start{}, boundary = Clock::now();
   int64_t round_elements = 0;  // replica-variables per update of the last round
+  bool round_backlogged = false;  // work was left waiting during the last round
   for (;;) {
     hipError_t e = hipStreamSynchronize(st);  // round boundary: the device is idle
     if (e != hipSuccess) {
@@ -199,10 +201,11 @@ void Server::run() {
       if (round_elements > 0) {
         const double per_update = std::chrono::duration<double>(now - round_start).count() / kRound;
         update_floor_s = update_floor_s > 0.0 ? std::min(update_floor_s, per_update) : per_update;
-        // the device rate, from rounds that fill the device, over the whole loop from one
-        // round boundary to the next (admission, uploads and list building included)
+        // the device rate: the work done per second in rounds that left work waiting (so the
+        // device could not have done more), over the whole loop from one round boundary to the
+        // next (admission, uploads and list building included)
         const double dt = std::chrono::duration<double>(now - boundary).count();
-        if (round_elements >= kRunElements / 2 && dt > 0.0)
+        if (round_backlogged && dt > 0.0)
           rate = 0.8 * rate + 0.2 * ((double)round_elements * kRound / dt);
         round_elements = 0;
       }
@@ -398,6 +401,11 @@ void Server::run() {
     // kRound updates of every active slot
     round_start = Clock::now();
     round_elements = running;
+    round_backlogged = dirty1 >= dirty0;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      round_backlogged = round_backlogged || !queue.empty();
+    }
     {
       std::lock_guard<std::mutex> lk(mu);
       for (int s : running_slots) {
