@@ -138,7 +138,24 @@ def traffic_from_profiles(record, sources, workload):
     return None
 
 
-def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True):
+def cpu_baseline_batch(gs, S, K, updates=2):
+    """The FP64 oracle on a bounded sample of the batched workload: the first `updates`
+    updates of every instance from its start, one thread, one instance after another."""
+    import oracle
+    pr = oracle.Params().as_float32()
+    work, dt = 0.0, 0.0
+    for k, g in enumerate(gs):
+        P = oracle.init(k, g["n"], S)
+        z = np.zeros_like(P)
+        t0 = time.perf_counter()
+        oracle.run(pr, g, 0, updates, K, k, P, z, z)
+        dt += time.perf_counter() - t0
+        work += float(g["n"]) * S * updates
+    return {"value": work / dt, "unit": "updates/s", "cores": 1, "kind": "oracle", "seconds": round(dt, 3),
+            "sample": f"the first {updates} of {K} updates of each of the {len(gs)} instances, single-threaded FP64 C"}
+
+
+def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True, with_cpu=False):
     """The ragged multi-instance configuration: `count` MIS instances on G(n, p) graphs with
     n ~ U{200..5000} and mean degree ~ U[3, 20], S replicas, K updates each; solved as one
     batch (one launch per update for all instances, replayed from a captured graph) and as a
@@ -203,6 +220,7 @@ def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True):
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "algorithmic_bytes_per_update": abytes, "update_us": loop_us,
                          "basis": "device time of the batched update loop (events on the solver stream) / updates"},
+            **({"oracle_context": cpu_baseline_batch(gs, S, K)} if with_cpu else {}),
             "batched_latency_ms": 1e3 * tb,
             "plain_latency_ms": {"p50": float(np.percentile(lat_p, 50)), "p99": float(np.percentile(lat_p, 99))}}
 
@@ -535,7 +553,8 @@ def main():
         for w, st, wu, oupd in CONFIG_BLOCKS:
             out["configs"][w] = config_block(q, w, st, wu, oupd, not args.no_cpu_baseline)
     if not args.no_batch:
-        out["batched_vs_plain"] = batched_vs_plain(q, K=args.batch_updates, plain=not args.batch_no_plain)
+        out["batched_vs_plain"] = batched_vs_plain(q, K=args.batch_updates, plain=not args.batch_no_plain,
+                                                   with_cpu=not args.no_cpu_baseline)
     if not args.no_serve:
         pool = graph_pool(24)
         spec = served(q, 200.0, args.serve_window, pool, seed=1, deadline_ms=args.serve_deadline_ms)
