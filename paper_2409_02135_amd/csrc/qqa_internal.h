@@ -241,10 +241,11 @@ hipError_t launch_noise(uint64_t seed, int n, int S, uint32_t k, float* xi, hipS
 hipError_t launch_init(uint64_t seed, int n, int S, float* P, float* m, float* v, hipStream_t st);
 hipError_t launch_step(const StepParams& p, hipStream_t st);
 
-// Sliced streaming update: the replica axis is cut into kReplicaSlices slices of at most sq
-// quads (sizes differ by at most one), one per XCD, each served by ls lanes x qs quads
-// (sq == 0: S is not sliceable, i.e. fewer than 2 quads per slice).  Partial statistics
-// {mean, M2} per (slice, row), kReplicaSlices x n entries, ping-pong between updates:
+// Sliced streaming update: the replica axis is cut into nsl slices of at most sq quads
+// (sizes differ by at most one), each served by ls lanes x qs quads: kReplicaSlices slices,
+// one per XCD, or half as many, one per XCD pair, when only that makes each slice a whole
+// 128-byte line (sq == 0: S is not sliceable, i.e. fewer than 2 quads per slice of eight).
+// Partial statistics {mean, M2} per (slice, row), nsl x n entries, ping-pong between updates:
 // launch_slice_stats forms them from p.P_in before the first update; each launch_slice_step
 // reads part_in (of P_in) and writes part_out (of P_out).  Same arithmetic per element as
 // launch_step, except that mu and sigma are combined from the slices' partials.
@@ -261,6 +262,7 @@ inline bool slice_by_default(int n, int S) {
 }
 struct SliceShape {
   int sq, ls, qs;
+  int nsl;  // slices: kReplicaSlices, or kReplicaSlices / 2 (XCD pairs) when that makes each a whole line
 };
 SliceShape slice_shape(int S);
 hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st);

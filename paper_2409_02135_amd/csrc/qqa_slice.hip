@@ -2,6 +2,9 @@
 // and slice s of every row is updated by workgroups on XCD s.  The coupling product
 // gathers, for each edge, only the neighbour's slice, so the rows an XCD gathers from are
 // 1/kReplicaSlices of P_in and mostly stay in that XCD's L2 instead of crossing the fabric.
+// Where an eighth of a row would be narrower than a 128-byte line, the row is cut into four
+// slices instead, and slice s is served by the XCD pair 2s, 2s + 1, each taking every other
+// block of rows.
 //
 // The replica statistics mu_i, sigma_i (Eq. 10) need all S replicas of a row.  Each slice
 // kernel therefore also writes, for the next update, its slice's partial statistics of the
@@ -15,17 +18,19 @@
 // are rounded differently from the whole-row kernels.
 //
 // Workgroup-to-XCD placement: consecutive workgroup ids of a launch are dispatched to
-// consecutive XCDs, round robin, so workgroup b runs on XCD b mod 8.  Slice = b mod 8.
+// consecutive XCDs, round robin, so workgroup b runs on XCD b mod 8.  Slice = b mod 8 (eight
+// slices) or (b mod 8) / 2 (four).
 #include "qqa_device.h"
 
 namespace qqa {
 
 // The slice of `row` served by this workgroup, as a row of its own: pointers at the slice's
-// first replica, S = its valid replicas.  Slice s holds quads [s nq / 8, (s + 1) nq / 8) of
-// the row's nq quads.
+// first replica, S = its valid replicas.  Slice s of NSL holds quads [s nq / NSL,
+// (s + 1) nq / NSL) of the row's nq quads.
+template <int NSL>
 __device__ __forceinline__ StepParams slice_view(const StepParams& a, const int slice, int* q0_out) {
   const int nq = (a.S + 3) >> 2;
-  const int q0 = slice * nq / kReplicaSlices, q1 = (slice + 1) * nq / kReplicaSlices;
+  const int q0 = slice * nq / NSL, q1 = (slice + 1) * nq / NSL;
   const size_t off = 4 * (size_t)q0;
   StepParams b = a;
   b.P_in = a.P_in + off;
@@ -73,21 +78,21 @@ __device__ __forceinline__ float2 slice_partial(const StepParams& b, const int g
 // XCD writes one contiguous array.  Lane gl of the LS-lane group reads slices gl, gl + LS,
 // ... (one load for the group when LS >= kReplicaSlices) and adds them in that order; a
 // butterfly over the group then adds the lanes (a fixed tree, the same bits in every lane).
-template <int LS>
+template <int LS, int NSL>
 __device__ __forceinline__ void combine_partials(const StepParams& a, const float2* __restrict__ part, const int row,
                                                  const int gl, float& mu, float& cg) {
-  constexpr int PER = LS >= kReplicaSlices ? 1 : kReplicaSlices / LS;  // slices per lane
+  constexpr int PER = LS >= NSL ? 1 : NSL / LS;  // slices per lane
   const int nq = (a.S + 3) >> 2;
   float2 ps[PER];
   float ns[PER];  // valid replicas of each slice; 0 for lanes past the last slice
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int sl = gl + LS * j;
-    const bool ok = sl < kReplicaSlices;
-    const int sc = ok ? sl : kReplicaSlices - 1;  // unconditional load, no join
+    const bool ok = sl < NSL;
+    const int sc = ok ? sl : NSL - 1;  // unconditional load, no join
     const float2 x = part[(size_t)sc * a.n + row];
     ps[j] = ok ? x : make_float2(0.f, 0.f);
-    ns[j] = ok ? (float)(min(a.S, 4 * ((sc + 1) * nq / kReplicaSlices)) - 4 * (sc * nq / kReplicaSlices)) : 0.f;
+    ns[j] = ok ? (float)(min(a.S, 4 * ((sc + 1) * nq / NSL)) - 4 * (sc * nq / NSL)) : 0.f;
   }
   float sum = 0.f;
 #pragma unroll
@@ -105,15 +110,30 @@ __device__ __forceinline__ void combine_partials(const StepParams& a, const floa
   cg = sigma > 0.f ? -a.comm_alpha * __builtin_amdgcn_rcpf(sigma) : 0.f;
 }
 
+// The slice and the first row of workgroup b.  Eight slices: slice b mod 8 (its XCD), row
+// block b / 8.  Four slices: XCDs 2s and 2s + 1 serve slice s, each every other row block.
+template <int NSL>
+__device__ __forceinline__ void slice_of_block(const int b, int* slice, int* row_block) {
+  const int xcd = b % kReplicaSlices;
+  if (NSL == kReplicaSlices) {
+    *slice = xcd;
+    *row_block = b / kReplicaSlices;
+  } else {  // NSL == kReplicaSlices / 2
+    *slice = xcd >> 1;
+    *row_block = (b / kReplicaSlices) * 2 + (xcd & 1);
+  }
+}
+
 // Partials of P (= a.P_in) for every (row, slice): the first update's statistics.
-template <int LS, int QS, bool FULL>
+template <int LS, int QS, bool FULL, int NSL>
 __global__ __launch_bounds__(kBlock) void slice_stats_kernel(StepParams a, float2* __restrict__ part) {
-  const int slice = (int)(blockIdx.x % kReplicaSlices);
-  const int row = (int)(blockIdx.x / kReplicaSlices) * (kBlock / LS) + (int)(threadIdx.x / LS);
+  int slice, rb;
+  slice_of_block<NSL>((int)blockIdx.x, &slice, &rb);
+  const int row = rb * (kBlock / LS) + (int)(threadIdx.x / LS);
   if (row >= a.n) return;  // whole lane groups leave together
   const int gl = threadIdx.x & (LS - 1);
   int q0;
-  const StepParams b = slice_view(a, slice, &q0);
+  const StepParams b = slice_view<NSL>(a, slice, &q0);
   float4 p[QS], mm[QS], vv[QS];
   load_row<LS, QS, FULL>(b, b.P_in, row, gl, p, mm, vv);
   const float2 pt = slice_partial<LS, QS, FULL>(b, gl, p);
@@ -125,19 +145,20 @@ __global__ __launch_bounds__(kBlock) void slice_stats_kernel(StepParams a, float
 // One quad per lane: eight waves per SIMD, the register budget held to 64 (at most 62 used, no
 // spills; 80 unbounded, six waves).  Measured: 30.3 against 30.7 us at S = 256, 29.2 against
 // 30.4 at S = 512.  Two quads per lane would spill under that budget and keep theirs.
-template <int LS, int QS, bool FULL, bool SUMS>
+template <int LS, int QS, bool FULL, bool SUMS, int NSL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QS == 1 ? 8 : 1, 8))) void slice_step_kernel(StepParams a, const float2* __restrict__ part_in,
                                                             float2* __restrict__ part_out) {
-  const int slice = (int)(blockIdx.x % kReplicaSlices);
-  const int row = (int)(blockIdx.x / kReplicaSlices) * (kBlock / LS) + (int)(threadIdx.x / LS);
+  int slice, rb;
+  slice_of_block<NSL>((int)blockIdx.x, &slice, &rb);
+  const int row = rb * (kBlock / LS) + (int)(threadIdx.x / LS);
   if (row >= a.n) return;  // whole lane groups leave together
   const int gl = threadIdx.x & (LS - 1);
   int q0;
-  const StepParams b = slice_view(a, slice, &q0);
+  const StepParams b = slice_view<NSL>(a, slice, &q0);
   float4 p[QS], mm[QS], vv[QS], acc[QS], po[QS], mo[QS], vo[QS];
   const RowMeta rm = row_meta(b, row);
   float mu, cg;
-  combine_partials<LS>(a, part_in, row, gl, mu, cg);
+  combine_partials<LS, NSL>(a, part_in, row, gl, mu, cg);
   load_row<LS, QS, FULL>(b, b.P_in, row, gl, p, mm, vv);
   // gather batches of 6 edges at up to 8 lanes per slice row (one quad each): most rows of a
   // sparse graph take one memory round trip (measured: 30.7 against 31.9 us with 4 at S = 256,
@@ -154,13 +175,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QS == 1 
 static unsigned blocks_of(long long threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
 
 SliceShape slice_shape(int S) {
-  SliceShape r{0, 0, 0};
+  SliceShape r{0, 0, 0, 0};
   const int nq = (S + 3) / 4;
-  const int sq = (nq + kReplicaSlices - 1) / kReplicaSlices;  // the largest slice
-  // every slice holds at least two quads (32 bytes)
-  if (S <= 0 || S > kMaxReplicas || nq < 2 * kReplicaSlices) return r;
+  if (S <= 0 || S > kMaxReplicas) return r;
+  // eight slices (one XCD each) when each is at least a 128-byte line; else four (an XCD pair
+  // each) when those are; else eight of at least two quads (32 bytes)
+  int nsl = 0;
+  if (nq >= 8 * kReplicaSlices) nsl = kReplicaSlices;
+  else if (nq >= 8 * (kReplicaSlices / 2)) nsl = kReplicaSlices / 2;
+  else if (nq >= 2 * kReplicaSlices) nsl = kReplicaSlices;
+  if (!nsl) return r;
+  const int sq = (nq + nsl - 1) / nsl;  // the largest slice
   int ls = 2;
   while (ls < sq && ls < 64) ls *= 2;
+  r.nsl = nsl;
   r.sq = sq;
   r.ls = ls;
   r.qs = (sq + ls - 1) / ls;
@@ -170,38 +198,49 @@ SliceShape slice_shape(int S) {
   return r;
 }
 
-template <int LS, int QS>
+// workgroups of a launch: every slice covers all row blocks, eight slices one XCD each,
+// four slices an XCD pair each (every other row block per XCD)
+static dim3 slice_grid(int n, int LS, int nsl) {
+  const unsigned rb = blocks_of((long long)n * LS);
+  return dim3(nsl == kReplicaSlices ? kReplicaSlices * rb : kReplicaSlices * ((rb + 1) / 2));
+}
+
+template <int LS, int QS, int NSL>
 static void launch_slice_stats_t(const StepParams& p, float2* part, hipStream_t st) {
-  const dim3 grid((unsigned)kReplicaSlices * blocks_of((long long)p.n * LS)), block(kBlock);
-  if (p.S == 4 * kReplicaSlices * LS * QS)  // equal slices, every lane's quads valid
-    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, true>), grid, block, 0, st, p, part);
+  const dim3 grid = slice_grid(p.n, LS, NSL), block(kBlock);
+  if (p.S == 4 * NSL * LS * QS)  // equal slices, every lane's quads valid
+    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, true, NSL>), grid, block, 0, st, p, part);
   else
-    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, false>), grid, block, 0, st, p, part);
+    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, false, NSL>), grid, block, 0, st, p, part);
 }
 
-template <int LS, int QS>
+template <int LS, int QS, int NSL>
 static void launch_slice_t(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st) {
-  const dim3 grid((unsigned)kReplicaSlices * blocks_of((long long)p.n * LS)), block(kBlock);
-  const bool full = p.S == 4 * kReplicaSlices * LS * QS;  // equal slices, every lane's quads valid
+  const dim3 grid = slice_grid(p.n, LS, NSL), block(kBlock);
+  const bool full = p.S == 4 * NSL * LS * QS;  // equal slices, every lane's quads valid
   const bool sums = p.problem == kMAXCLIQUE;
+#define L(FU, SU) hipLaunchKernelGGL((slice_step_kernel<LS, QS, FU, SU, NSL>), grid, block, 0, st, p, part_in, part_out)
   if (sums) {
-    if (full) hipLaunchKernelGGL((slice_step_kernel<LS, QS, true, true>), grid, block, 0, st, p, part_in, part_out);
-    else hipLaunchKernelGGL((slice_step_kernel<LS, QS, false, true>), grid, block, 0, st, p, part_in, part_out);
+    if (full) L(true, true);
+    else L(false, true);
   } else {
-    if (full) hipLaunchKernelGGL((slice_step_kernel<LS, QS, true, false>), grid, block, 0, st, p, part_in, part_out);
-    else hipLaunchKernelGGL((slice_step_kernel<LS, QS, false, false>), grid, block, 0, st, p, part_in, part_out);
+    if (full) L(true, false);
+    else L(false, false);
   }
+#undef L
 }
 
-#define QQA_FOR_EACH_SLICE_LAYOUT(X) X(2, 1) X(4, 1) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(64, 2)
+// (lanes, quads per lane, slices) of the kernels built: four slices serve 8 to 15 quads each
+#define QQA_FOR_EACH_SLICE_LAYOUT(X) \
+  X(2, 1, 8) X(4, 1, 8) X(8, 1, 8) X(16, 1, 8) X(32, 1, 8) X(64, 1, 8) X(64, 2, 8) X(8, 1, 4) X(16, 1, 4)
 
 hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st) {
   if (p.n == 0) return hipSuccess;
   const SliceShape s = slice_shape(p.S);
   if (s.sq == 0) return hipErrorInvalidValue;
-#define X(L, Q)                                \
-  if (s.ls == L && s.qs == Q) {                \
-    launch_slice_stats_t<L, Q>(p, part, st);   \
+#define X(L, Q, N)                                     \
+  if (s.ls == L && s.qs == Q && s.nsl == N) {          \
+    launch_slice_stats_t<L, Q, N>(p, part, st);        \
     return hipGetLastError();                  \
   }
   QQA_FOR_EACH_SLICE_LAYOUT(X)
@@ -213,9 +252,9 @@ hipError_t launch_slice_step(const StepParams& p, const float2* part_in, float2*
   if (p.n == 0) return hipSuccess;
   const SliceShape s = slice_shape(p.S);
   if (s.sq == 0) return hipErrorInvalidValue;
-#define X(L, Q)                                          \
-  if (s.ls == L && s.qs == Q) {                          \
-    launch_slice_t<L, Q>(p, part_in, part_out, st);      \
+#define X(L, Q, N)                                       \
+  if (s.ls == L && s.qs == Q && s.nsl == N) {            \
+    launch_slice_t<L, Q, N>(p, part_in, part_out, st);   \
     return hipGetLastError();                            \
   }
   QQA_FOR_EACH_SLICE_LAYOUT(X)

@@ -1,4 +1,5 @@
-"""The sliced streaming engine (replica axis cut into 8 slices, one per XCD; replica statistics
+"""The sliced streaming engine (replica axis cut into 8 slices, one per XCD, or below 256
+replicas into 4 slices, one per XCD pair; replica statistics
 combined from the slices' partials, which each update leaves for the next): one update
 matches the oracle, from a given state and from a state the engine reached itself (so the
 partials it wrote are checked); a run interrupted and resumed gives the same bits as one
@@ -47,7 +48,8 @@ def rb_graph():
 CASES = [
     # name, graph, problem, S
     ("er20000_S256_mis", lambda: qi.erdos_renyi(20000, 5.0, 0), "mis", 256),
-    ("ba5000_S128_maxcut_hubs", lambda: qi.pm1_weights(qi.barabasi_albert(5000, 4, 1), 1), "maxcut", 128),
+    ("ba5000_S128_maxcut_hubs_four_slices", lambda: qi.pm1_weights(qi.barabasi_albert(5000, 4, 1), 1), "maxcut", 128),
+    ("er3000_S200_mis_four_slices_ragged", lambda: qi.erdos_renyi(3000, 7.0, 6), "mis", 200),
     ("er4000_S100_mis_ragged", lambda: qi.erdos_renyi(4000, 8.0, 2), "mis", 100),
     ("er4000_S61_mis_narrowest", lambda: qi.erdos_renyi(4000, 8.0, 3), "mis", 61),
     ("er3000_S1000_maxcut", lambda: qi.pm1_weights(qi.erdos_renyi(3000, 6.0, 4), 2), "maxcut", 1000),
