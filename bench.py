@@ -157,10 +157,11 @@ def cpu_baseline_batch(gs, S, K, updates=2):
 
 def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True, with_cpu=False):
     """The ragged multi-instance configuration: `count` MIS instances on G(n, p) graphs with
-    n ~ U{200..5000} and mean degree ~ U[3, 20], S replicas, K updates each; solved as one
-    batch (one launch per update for all instances, replayed from a captured graph) and as a
-    loop of single solves on the same GPU.  Both use the same replica layout, so their
-    results must be identical."""
+    n ~ U{200..5000} and mean degree ~ U[3, 20], S replicas, K updates each; tuned by the
+    batch autotuner, then solved as one batch (the engine it kept), on the slot launches (one
+    launch per update for all instances, replayed from a captured graph) and as a loop of
+    single solves on the same GPU.  All use the same replica layout, so their results must
+    be identical."""
     import qqa_inputs as qi
     import torch
     gs = qi.instance_batch(count, seed, n_range=(200, 5000), deg_range=(3.0, 20.0))
@@ -173,6 +174,12 @@ def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True, with_cpu=Fa
     for r in ctx.solve_batch(gids[:2], ns[:2], ["mis"] * 2, [S] * 2, [50] * 2, [0, 1]):
         ctx.poll(r, want_x=False)
     ctx.poll(ctx.solve_resident(gids[0], ns[0], "mis", S, 50, 0), want_x=False)
+    # the batch autotuner: replica layouts on the slot launches, then the resident engine,
+    # on shortened copies of this batch; the runs below use what it kept
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tuned_resident, tuned_lanes = ctx.autotune_batch(gids, ["mis"] * count, [S] * count, [K] * count)
+    t_tune = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ids = ctx.solve_batch(gids, ns, ["mis"] * count, [S] * count, [K] * count, seeds)
@@ -208,6 +215,7 @@ def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True, with_cpu=Fa
             "speedup": tp / tb if plain else None, "batched_s": tb, "plain_s": tp if plain else None,
             "identical_results": same,
             "engine": rb[0]["engine"],
+            "autotune": {"resident_kept": tuned_resident, "lanes_per_row": tuned_lanes[0], "seconds": t_tune},
             "slot_launches": {"updates_per_s": work / ts, "seconds": ts, "identical_results": bool(same_slots),
                               "update_us": float(rs[0]["step_loop_ms"]) * 1e3 / K},
             "roofline": {"bound": "hbm", "kernel": "resident_kernel" if rb[0]["engine"] == "batch_resident"

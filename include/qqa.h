@@ -232,6 +232,24 @@ int qqa_solve_batch(qqa_ctx *c, int32_t count, const qqa_graph_id *graphs, const
                     const qqa_schedule *sched, const int32_t *S, const int32_t *steps,
                     const uint64_t *seeds, qqa_req *out_ids);
 
+/* Batch autotuner: runs shortened copies of the batch described (arguments as for
+ * qqa_solve_batch; the longest instance runs 64 updates, the others their share of that,
+ * seeds 1..count, each candidate twice, results discarded) and keeps what is fastest:
+ * for every S in the batch, the replica layout (as qqa_autotune) on the slot launches,
+ * timed over that S's instances; and, when all instances share one S under the automatic
+ * policy, whether the resident engine (at the default layout) or the slot launches (at the
+ * layout found) run the batch in less device time per update.  Later batches and plain
+ * solves of this context use those layouts, and later batches of one layout class with
+ * that S use that engine.  lanes_out (count entries, may be NULL): the lanes per row each
+ * instance's S now runs with.  *resident_out (may be NULL): 1 if the resident engine was kept.
+ * The layout decides the summation order of the replica statistics, so results after
+ * tuning equal those of the same solves under the same layouts.  QQA_E_ARG under a policy
+ * other than AUTO or STREAM; errors of the timed batches are returned, with the context's
+ * layouts and engine choices left as they were. */
+int qqa_autotune_batch(qqa_ctx *c, int32_t count, const qqa_graph_id *graphs, const qqa_problem *problems,
+                       const qqa_schedule *sched, const int32_t *S, const int32_t *steps,
+                       int32_t *lanes_out, int32_t *resident_out);
+
 /* Replica layout: how many adjacent lanes of a 64-lane wavefront serve the S replicas of
  * one variable (a power of two <= 64; each lane then owns ceil(S / (4 * lanes)) float4
  * quads, and a wavefront serves 64 / lanes variables).  The layout changes only the

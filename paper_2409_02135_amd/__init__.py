@@ -108,6 +108,7 @@ def lib():
             "qqa_set_engine": (C.c_int, [vp, i32]),
             "qqa_dev_run": (C.c_int, [vp, i32, vp, i32, i32, i32, i32, u64, vp, vp, vp, vp, i32, i32, vp]),
             "qqa_autotune": (C.c_int, [vp, i64, i32, i32, vp]),
+            "qqa_autotune_batch": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp]),
             "qqa_dev_eval": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
             "qqa_dev_eval_noalloc": (C.c_int, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]),
             "qqa_dev_dense_coupling": (C.c_int, [vp, vp, vp, i32, i32, i32, vp]),
@@ -363,6 +364,23 @@ class Context:
         out = C.c_int32()
         self._check(lib().qqa_autotune(self._c, gid, PROBLEMS[problem], S, C.byref(out)))
         return out.value
+
+    def autotune_batch(self, gids, problems, S, steps, sched=None) -> tuple[bool, list[int]]:
+        """Tune replica layouts, and the resident-or-slot choice, on shortened copies of this
+        batch; returns whether the resident engine was kept and each instance's lanes per row."""
+        cnt = len(gids)
+        g = np.asarray(gids, np.int64)
+        pr = np.asarray([PROBLEMS[p] for p in problems], np.int32)
+        Ss = np.asarray(S, np.int32)
+        ks = np.asarray(steps, np.int32)
+        if not (len(pr) == len(Ss) == len(ks) == cnt) or (sched is not None and len(sched) != cnt):
+            raise ValueError("batch arrays must have one entry per instance")
+        sch = None if sched is None else (qqa_schedule * cnt)(*sched)
+        out = C.c_int32()
+        lanes = np.zeros(cnt, np.int32)
+        self._check(lib().qqa_autotune_batch(self._c, cnt, _ptr(g), _ptr(pr), sch, _ptr(Ss), _ptr(ks), _ptr(lanes),
+                                             C.byref(out)))
+        return bool(out.value), [int(x) for x in lanes]
 
     def release(self, gid: int):
         self._check(lib().qqa_graph_release(self._c, gid))

@@ -107,6 +107,9 @@ struct qqa_ctx {
   std::unique_ptr<qqa::Server> server;
   std::unordered_map<int, int> layout;  // S -> lanes per row (absent: default)
   int engine_policy = -1;                // qqa_engine: -1 auto, 0 stream only
+  // S -> what the batch autotuner found faster for a batch of one layout class under the
+  // automatic policy: 1 the resident engine, 0 the slot launches (absent: resident if it fits)
+  std::unordered_map<int, int> batch_resident;
   int layout_for(int S) const {
     auto it = layout.find(S);
     return it == layout.end() ? 0 : it->second;

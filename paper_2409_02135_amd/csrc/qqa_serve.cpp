@@ -194,6 +194,10 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
   // per lane, none has split rows, and each instance's team fits the workgroups one XCD
   // holds; the automatic policy uses it then, QQA_ENGINE_STREAM keeps the slot launches.
   bool resident = c->engine_policy < 0 && classes.size() == 1;
+  if (resident) {
+    auto pref = c->batch_resident.find(classes.begin()->second.S);
+    resident = pref == c->batch_resident.end() || pref->second != 0;
+  }
   int res_lanes = 0, res_grid = 0, rows_per_wg = 0;
   if (resident) {
     const LayoutClass& lc = classes.begin()->second;
@@ -333,9 +337,10 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
       e = launch_slot_init(d_slots, reinterpret_cast<const WorkItem*>(A + lc.off_items), (int)lc.items.size(), lc.lanes,
                            st);
   }
-  if (e == hipSuccess) e = hipEventRecord(run->ev[1], st);
   // the update loop: R launches per layout class and a clock advance, captured once and
-  // replayed until the longest instance has run all of its updates; or one resident launch
+  // replayed until the longest instance has run all of its updates; or one resident launch.
+  // Its start event is recorded once the graph is built, so the loop's device time does not
+  // include the host's capture.
   const int R = std::min(maxK, 64);
   if (resident && e == hipSuccess) {
     ResidentParams rp{};
@@ -354,7 +359,8 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     // a barrier may wait for the XCD's earlier jobs to free workgroups: allow 10 s plus
     // 100 us for every update those jobs run
     rp.timeout_ticks = (long long)((10.0 + 1e-4 * longest_xcd_updates) * 1e3 * khz);
-    e = launch_resident(rp, res_lanes, kResidentRowsPerGroup, res_grid, count, count, st);
+    e = hipEventRecord(run->ev[1], st);
+    if (e == hipSuccess) e = launch_resident(rp, res_lanes, kResidentRowsPerGroup, res_grid, count, count, st);
   } else if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (!resident && e == hipSuccess) {
     hipError_t ce = hipSuccess;
@@ -373,6 +379,7 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     if (e == hipSuccess) e = ce;
   }
   if (!resident && e == hipSuccess) e = hipGraphInstantiate(&run->exec, run->graph, nullptr, nullptr, 0);
+  if (!resident && e == hipSuccess) e = hipEventRecord(run->ev[1], st);
   for (int done = 0; !resident && done < maxK && e == hipSuccess; done += R) e = hipGraphLaunch(run->exec, st);
   if (e == hipSuccess) e = hipEventRecord(run->ev[2], st);
   for (auto& kv : classes) {
@@ -412,6 +419,133 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     out_ids[i] = r->id;
     c->reqs.emplace(r->id, std::move(r));
   }
+  return QQA_OK;
+}
+
+// Device time of one batch's update loop per update of its longest instance, and the engine
+// that ran it.  Seeds 1..count; results are discarded.
+static int time_batch(qqa_ctx* c, const std::vector<qqa_graph_id>& g, const std::vector<qqa_problem>& prob,
+                      const std::vector<qqa_schedule>& sched, const std::vector<int32_t>& S,
+                      const std::vector<int32_t>& K, double* us, int* engine) {
+  const int count = (int)g.size();
+  std::vector<uint64_t> seeds((size_t)count);
+  for (int i = 0; i < count; ++i) seeds[i] = (uint64_t)i + 1;
+  std::vector<qqa_req> ids((size_t)count);
+  int rc = qqa_solve_batch(c, count, g.data(), prob.data(), sched.empty() ? nullptr : sched.data(), S.data(), K.data(),
+                           seeds.data(), ids.data());
+  if (rc) return rc;
+  qqa_result first{};
+  for (int i = 0; i < count; ++i) {
+    qqa_result r{};
+    const int prc = qqa_poll(c, ids[i], &r, -1);
+    if (prc != QQA_OK && rc == QQA_OK) rc = prc;
+    if (i == 0) first = r;
+  }
+  if (rc) return rc;
+  *us = first.step_loop_ms * 1e3 / *std::max_element(K.begin(), K.end());
+  *engine = first.engine;
+  return QQA_OK;
+}
+
+int qqa_autotune_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const qqa_problem* problems,
+                       const qqa_schedule* sched, const int32_t* S, const int32_t* steps, int32_t* lanes_out,
+                       int32_t* resident_out) {
+  if (!c) return QQA_E_ARG;
+  if (count <= 0 || !graphs || !problems || !S || !steps) return set_err(c, QQA_E_ARG, "batch arguments missing");
+  if (c->engine_policy >= 0 && c->engine_policy != QQA_ENGINE_STREAM)
+    return set_err(c, QQA_E_ARG, "the batch autotuner runs under the automatic or STREAM policy");
+  int maxK = 0;
+  for (int i = 0; i < count; ++i) {
+    if (S[i] <= 0 || S[i] > kMaxReplicas || steps[i] <= 0)
+      return set_err(c, QQA_E_ARG, "need 1 <= S <= 4096 and steps > 0");
+    maxK = std::max(maxK, steps[i]);
+  }
+  // a shortened copy of the batch: the longest instance runs kProbe updates, the others
+  // keep their share of it, so that the work of the resident engine's teams keeps its mix
+  constexpr int kProbe = 64, kRepeats = 2;
+  std::map<int, std::vector<int>> by_S;
+  for (int i = 0; i < count; ++i) by_S[S[i]].push_back(i);
+  const auto saved_layout = c->layout;
+  const auto saved_resident = c->batch_resident;
+  const int saved_policy = c->engine_policy;
+  auto sub = [&](const std::vector<int>& idx, std::vector<qqa_graph_id>* g, std::vector<qqa_problem>* pr,
+                 std::vector<qqa_schedule>* sc, std::vector<int32_t>* s, std::vector<int32_t>* k) {
+    for (int i : idx) {
+      g->push_back(graphs[i]);
+      pr->push_back(problems[i]);
+      if (sched) sc->push_back(sched[i]);
+      s->push_back(S[i]);
+      k->push_back(std::max(2, (int)(((int64_t)steps[i] * kProbe + maxK - 1) / maxK)));
+    }
+  };
+  auto best_of = [&](const std::vector<qqa_graph_id>& g, const std::vector<qqa_problem>& pr,
+                     const std::vector<qqa_schedule>& sc, const std::vector<int32_t>& s, const std::vector<int32_t>& k,
+                     double* us, int* engine) {
+    *us = 1e300;
+    for (int rep = 0; rep < kRepeats; ++rep) {  // the first run also loads the kernels
+      double t = 0.0;
+      const int rc = time_batch(c, g, pr, sc, s, k, &t, engine);
+      if (rc) return rc;
+      *us = std::min(*us, t);
+    }
+    return (int)QQA_OK;
+  };
+  auto fail = [&](int rc) {
+    const std::string why = c->err;
+    c->layout = saved_layout;
+    c->batch_resident = saved_resident;
+    c->engine_policy = saved_policy;
+    return set_err(c, rc, "batch autotune: " + why);
+  };
+  // each S: every replica layout on the slot launches, over that S's instances alone (the
+  // layout classes of a batch run one after another, so their times add)
+  c->engine_policy = QQA_ENGINE_STREAM;
+  std::map<int, std::pair<int, double>> best;  // S -> (lanes per row, us per update)
+  for (const auto& kv : by_S) {
+    std::vector<qqa_graph_id> g;
+    std::vector<qqa_problem> pr;
+    std::vector<qqa_schedule> sc;
+    std::vector<int32_t> s, k;
+    sub(kv.second, &g, &pr, &sc, &s, &k);
+    std::pair<int, double> b{0, 1e300};
+    int last = -1;
+    for (int want = 1; want <= 64; want <<= 1) {
+      const ReplicaShape sh = replica_shape(kv.first, want);
+      if (sh.lpr == last || !layout_supported(kv.first, want)) continue;
+      last = sh.lpr;
+      c->layout[kv.first] = sh.lpr;
+      double us = 0.0;
+      int engine = 0;
+      const int rc = best_of(g, pr, sc, s, k, &us, &engine);
+      if (rc) return fail(rc);
+      if (us < b.second) b = {sh.lpr, us};
+    }
+    best[kv.first] = b;
+    c->layout[kv.first] = b.first;
+  }
+  c->engine_policy = saved_policy;
+  // one layout class under the automatic policy: the resident engine at the default layout
+  int resident = 0;
+  if (saved_policy < 0 && by_S.size() == 1) {
+    const int s0 = by_S.begin()->first;
+    std::vector<qqa_graph_id> g;
+    std::vector<qqa_problem> pr;
+    std::vector<qqa_schedule> sc;
+    std::vector<int32_t> s, k;
+    sub(by_S.begin()->second, &g, &pr, &sc, &s, &k);
+    c->layout.erase(s0);
+    c->batch_resident.erase(s0);
+    double us = 0.0;
+    int engine = 0;
+    const int rc = best_of(g, pr, sc, s, k, &us, &engine);
+    if (rc) return fail(rc);
+    resident = engine == QQA_ENGINE_BATCH_RESIDENT && us < best[s0].second;
+    c->batch_resident[s0] = resident;
+    if (!resident) c->layout[s0] = best[s0].first;
+  }
+  if (lanes_out)
+    for (int i = 0; i < count; ++i) lanes_out[i] = replica_shape(S[i], c->layout_for(S[i])).lpr;
+  if (resident_out) *resident_out = resident;
   return QQA_OK;
 }
 

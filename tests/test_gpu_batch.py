@@ -173,3 +173,45 @@ def test_resident_batch_repeatable_and_policy_fallbacks(ctx):
         gids, res = _run_batch(ctx, inst)
         assert all(r["engine"] == "batch" for r in res)
         _check_alone(ctx, inst, gids, res)
+
+
+def test_batch_autotune_keeps_results_and_applies_its_choice():
+    """The batch autotuner times every replica layout on the slot launches and, for a batch of
+    one layout class, the resident engine; later batches run what it kept, and every instance
+    still ends with the bits of its solve alone under the same layout."""
+    import paper_2409_02135_amd as q
+    c = q.Context(0)
+    try:
+        inst = _one_width(24, 32, 31)
+        gids = [c.upload(g, p) for g, p, *_ in inst]
+        resident, lanes = c.autotune_batch(gids, [p for _, p, *_ in inst], [32] * len(inst), [i[3] for i in inst])
+        print("resident", resident, "lanes", lanes[0], flush=True)
+        assert len(set(lanes)) == 1 and lanes[0] in (1, 2, 4, 8, 16, 32, 64)
+        assert not resident or lanes[0] == 8  # the resident engine runs one quad per lane
+        ids = c.solve_batch(gids, [g["n"] for g, *_ in inst], [p for _, p, *_ in inst], [32] * len(inst),
+                            [i[3] for i in inst], [i[4] for i in inst])
+        res = [c.poll(i) for i in ids]
+        assert all(r["engine"] == ("batch_resident" if resident else "batch") for r in res)
+        _check_alone(c, inst, gids, res)
+        # two replica counts: a layout per S on the slot launches, never the resident engine
+        mixed = _one_width(4, 32, 32) + _one_width(4, 128, 33, n_range=(30, 2000))
+        gids = [c.upload(g, p) for g, p, *_ in mixed]
+        resident, lanes = c.autotune_batch(gids, [p for _, p, *_ in mixed], [i[2] for i in mixed],
+                                           [i[3] for i in mixed])
+        assert not resident and len(set(lanes[:4])) == 1 and len(set(lanes[4:])) == 1
+        ids = c.solve_batch(gids, [g["n"] for g, *_ in mixed], [p for _, p, *_ in mixed], [i[2] for i in mixed],
+                            [i[3] for i in mixed], [i[4] for i in mixed])
+        res = [c.poll(i) for i in ids]
+        assert all(r["engine"] == "batch" for r in res)
+        _check_alone(c, mixed, gids, res)
+        # refused under a forced single-solve engine
+        g = qi.erdos_renyi(100, 3.0, 1)
+        gid = c.upload(g, "mis")
+        c.set_engine("sliced")
+        with pytest.raises(q.QQAError) as e:
+            c.autotune_batch([gid], ["mis"], [32], [10])
+        assert e.value.code == q.QQA_E_ARG
+        c.set_engine("auto")
+        c.release(gid)
+    finally:
+        c.close()
