@@ -155,7 +155,7 @@ def cpu_baseline_batch(gs, S, K, updates=2):
             "sample": f"the first {updates} of {K} updates of each of the {len(gs)} instances, single-threaded FP64 C"}
 
 
-def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True, with_cpu=False):
+def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True, with_cpu=False, tune=True):
     """The ragged multi-instance configuration: `count` MIS instances on G(n, p) graphs with
     n ~ U{200..5000} and mean degree ~ U[3, 20], S replicas, K updates each; tuned by the
     batch autotuner, then solved as one batch (the engine it kept), on the slot launches (one
@@ -178,7 +178,7 @@ def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True, with_cpu=Fa
     # on shortened copies of this batch; the runs below use what it kept
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tuned_resident, tuned_lanes = ctx.autotune_batch(gids, ["mis"] * count, [S] * count, [K] * count)
+    tuned = ctx.autotune_batch(gids, ["mis"] * count, [S] * count, [K] * count) if tune else None
     t_tune = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -215,7 +215,8 @@ def batched_vs_plain(q, count=512, S=32, K=2000, seed=0, plain=True, with_cpu=Fa
             "speedup": tp / tb if plain else None, "batched_s": tb, "plain_s": tp if plain else None,
             "identical_results": same,
             "engine": rb[0]["engine"],
-            "autotune": {"resident_kept": tuned_resident, "lanes_per_row": tuned_lanes[0], "seconds": t_tune},
+            "autotune": ({"resident_kept": tuned[0], "lanes_per_row": tuned[1][0], "seconds": t_tune}
+                         if tuned else None),
             "slot_launches": {"updates_per_s": work / ts, "seconds": ts, "identical_results": bool(same_slots),
                               "update_us": float(rs[0]["step_loop_ms"]) * 1e3 / K},
             "roofline": {"bound": "hbm", "kernel": "resident_kernel" if rb[0]["engine"] == "batch_resident"
@@ -506,6 +507,9 @@ def main():
                     help="updates per instance of the batched configuration (fewer for runs under counters)")
     ap.add_argument("--batch-no-plain", action="store_true",
                     help="time the batch only, not the loop of plain solves (runs under counters)")
+    ap.add_argument("--batch-no-tune", action="store_true",
+                    help="skip the batch autotuner: the automatic policy's engine at the default layout "
+                         "(the resident engine when the batch fits it; runs under counters)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served request-stream measurement")
     ap.add_argument("--serve-window", type=float, default=60.0,
                     help="arrival window (s) of the served stream at the specified rate of 200 requests/s")
@@ -562,7 +566,7 @@ def main():
             out["configs"][w] = config_block(q, w, st, wu, oupd, not args.no_cpu_baseline)
     if not args.no_batch:
         out["batched_vs_plain"] = batched_vs_plain(q, K=args.batch_updates, plain=not args.batch_no_plain,
-                                                   with_cpu=not args.no_cpu_baseline)
+                                                   with_cpu=not args.no_cpu_baseline, tune=not args.batch_no_tune)
     if not args.no_serve:
         pool = graph_pool(24)
         spec = served(q, 200.0, args.serve_window, pool, seed=1, deadline_ms=args.serve_deadline_ms)
