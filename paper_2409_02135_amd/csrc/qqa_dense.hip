@@ -116,14 +116,18 @@ __global__ __launch_bounds__(kDenseThreads) void dense_tile128_kernel(const floa
     if (s + 1 < c_end) fetch((s + 1) * kBK);
     const float* As = smem + buf * kStage;
     const float* Bs = As + kBK * kTile;
+    // the next chunk goes to the other buffer halfway through this one's matrix-core work:
+    // that buffer's last readers passed the barrier that ended the previous chunk, and by
+    // then its global loads have returned (measured: 78.0 against 79.4 us when written after
+    // the loop, n = 4,096, S = 256)
 #pragma unroll
     for (int jj = 0; jj < kBK / 2; ++jj) {
+      if (jj == kBK / 4 && s + 1 < c_end) stash(buf ^ 1, (s + 1) * kBK);
       const int j = 2 * jj + lk;
       const float a = As[j * kTile + wr + li];  // A[wr + li][k0 + j] = W[k0 + j][row0 + wr + li]
       const float b = Bs[j * kTile + wc + li];  // B[k0 + j][wc + li]
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
     }
-    if (s + 1 < c_end) stash(buf ^ 1, (s + 1) * kBK);
     __syncthreads();
   }
 
