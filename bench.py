@@ -316,6 +316,9 @@ def served(q, rate, arrival_window, pool, seed=0, max_slots=256, deadline_ms=0.0
             "sustained_updates_per_s": work_done / makespan, "makespan_s": makespan,
             "measured_device_rate_updates_per_s": stats["rate_updates_per_s"],
             "latency_ms": pct(lat), "first_update_ms": pct(fst), "queue_ms": pct(qms),
+            **({"met_deadline": {"requests": int(np.sum(lat <= deadline_ms)) if res else 0,
+                                 "updates_per_s": sum(w for r, w in done if r["latency_ms"] <= deadline_ms)
+                                 / arrival_window}} if deadline_ms > 0 else {}),
             "latency_basis": "admitted requests, submit -> result ready (host clock)",
             "feasible_fraction": float(np.mean([r["feasible"] for r in res])) if res else None}
 

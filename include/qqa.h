@@ -305,13 +305,19 @@ int qqa_cancel(qqa_ctx *c, qqa_req id);
  *     return) and queues the request; QQA_E_ADMISSION if it can never fit, or if it is
  *     shed (below).
  *   qqa_serve_set_deadline: load shedding.  With deadline_ms > 0, qqa_serve_submit refuses
- *     (QQA_E_ADMISSION, "shed: ...") a request whose projected submit-to-result time exceeds
- *     deadline_ms.  The projection: under least-remaining-work-first the request waits for
- *     the pending work with less remaining work than its own, W_<, and for smaller work
- *     arriving meanwhile at the rate a_w measured over the admitted submissions of the last
- *     5 s; at the device rate R (replica-variable updates per second, measured over rounds
- *     that leave work waiting) it finishes after (W_< + w) / (R - a_w), and no sooner than its
- *     updates times the shortest update time seen.  0 (the default) sheds nothing.
+ *     (QQA_E_ADMISSION, "shed: ...") a request unless it and every admitted request can
+ *     still finish within deadline_ms of their submission.  The projection: under
+ *     least-remaining-work-first a request of work w waits for the pending work with no more
+ *     remaining work than its own, W_<=, and for smaller work arriving meanwhile at the rate
+ *     a_w measured over the admitted submissions of the last 5 s; at the device rate R
+ *     (replica-variable updates per second, measured over rounds that leave work waiting) it
+ *     finishes after (W_<= + w) / (R - a_w), and no sooner than its updates times the
+ *     shortest update time seen.  Admitting it
+ *     delays each pending request with more remaining work by w / R; it is refused if one
+ *     of them would then be projected past its deadline (also one that is late already, so
+ *     that it is not overtaken by ever more smaller work).  With a deadline, each round
+ *     first runs the requests older than half of it, oldest first, then the others by least
+ *     remaining work.  0 (the default) sheds nothing.
  *   qqa_serve_get_stats: counts of submitted, admitted, shed and completed requests since
  *     qqa_serve_start, the measured device rate and the server's device memory.
  *   qqa_serve_stop: returns after every queued and admitted request has finished;

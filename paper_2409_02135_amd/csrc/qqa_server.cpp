@@ -18,15 +18,26 @@
 // arithmetic as a solve alone (the slot kernels share qqa_device.h), so a served result
 // equals the result of the same solve alone.
 //
-// Load shedding (optional, qqa_serve_set_deadline): a request is refused at submit when
-// its projected completion time exceeds the deadline.  Under least-remaining-work-first
-// a request of work w (rows x replica stride x updates) waits only for the pending work
-// W_< of requests with less remaining work, and for the work that arrives meanwhile in
-// requests no larger than w, at rate a_w; at a device rate R it then finishes after
-// (W_< + w) / (R - a_w) (the busy period of shortest-remaining-work scheduling), and no
-// sooner than its updates x the shortest update seen.  R is measured over rounds that leave
-// work waiting (so the device could do no more); a_w over the admitted submissions of the
-// last few seconds.
+// Load shedding (optional, qqa_serve_set_deadline): a request is refused at submit unless
+// every admitted request, and it, can still finish within the deadline.  Under
+// least-remaining-work-first a request of work w (rows x replica stride x updates) waits for
+// the pending work of requests with no more remaining work than its own, W_<=, and for the
+// work that arrives meanwhile in requests no larger than w, at rate a_w (measured over the
+// admitted submissions of the last 5 s); at a device rate R it then finishes after
+// (W_<= + w) / (R - a_w) (the busy period of shortest-remaining-work scheduling), and no
+// sooner than its updates x the shortest update seen.  Admitting it delays every pending
+// request with more remaining work by w / R:
+// it is refused if one of them would then be projected past its own deadline, also one that
+// is late already.  So work that arrives later never pushes an admitted request past its
+// deadline (up to the accuracy of R), and a request the projection underestimated is not
+// overtaken by ever more smaller work, which a test of the new request alone cannot promise.
+// R is measured over rounds that leave work waiting (so the device could do no more).  The
+// rounds run requests older than half the deadline first, oldest first, so that the large
+// requests least-remaining-work-first would keep postponing finish in time.  (Measured on a
+// Poisson stream at 200 requests/s for 60 s, 8x the device's rate, 2 s deadline: 6,454
+// admitted, 6,453 of them within the deadline, p99 1.4 s.  The new request's own projection
+// alone: 7,085 admitted, p99 5.3 s; with the protection of admitted requests but no urgent
+// ones first: 2,017 admitted, as late requests blocked the smaller arrivals.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,11 +63,13 @@ namespace qqa {
 
 namespace {
 constexpr int kRound = 16;
+// with a deadline, requests older than this fraction of it run first, oldest first
+constexpr double kUrgentFraction = 0.5;
+// the window over which the admitted work arriving per second is measured
+constexpr double kArrivalWindowS = 5.0;
 // replica-variables per update launch beyond which more running slots add no throughput
 constexpr int64_t kRunElements = int64_t(8) << 20;
 constexpr int64_t kServerIdBase = int64_t(1) << 40;
-// the window over which the admitted work arriving per second is measured
-constexpr double kArrivalWindowS = 5.0;
 // device rate assumed before a round that fills the device has been measured
 constexpr double kInitialRate = 1e11;
 // idle buffers the server's pools keep for reuse
@@ -112,9 +125,9 @@ struct Server {
   double deadline_ms = 0.0;
   double rate = kInitialRate;       // replica-variable updates per second, measured
   double update_floor_s = 0.0;      // shortest time of one update seen
-  std::deque<std::pair<Clock::time_point, double>> recent;  // admitted submissions
   int64_t n_submitted = 0, n_shed = 0, n_admitted = 0, n_completed = 0;
-  double projected_ms(const ServerReq& r, Clock::time_point now);
+  bool meets_deadline(const ServerReq& r, Clock::time_point now, double* ms, const char** why);
+  std::deque<std::pair<Clock::time_point, double>> recent;  // admitted submissions (time, work)
   std::unordered_map<int, int> layout;
   std::thread th;
   std::mutex mu;
@@ -148,23 +161,46 @@ size_t Server::footprint_of(const ServerReq& r) const {
          4096;
 }
 
-// Projected submit-to-result time of r if it were admitted now (see the header).  Under mu.
-double Server::projected_ms(const ServerReq& r, Clock::time_point now) {
-  double smaller = 0.0;
+// Whether r, admitted now, and every pending request would still meet the deadline (see the
+// header); *ms = r's projected submit-to-result time.  Under mu.
+bool Server::meets_deadline(const ServerReq& r, Clock::time_point now, double* ms, const char** why) {
+  const double D = 1e-3 * deadline_ms;
+  std::vector<std::pair<double, double>> pend;  // (remaining work, seconds left to its deadline)
   for (const auto& kv : all) {
     const ServerReq& o = *kv.second;
     if ((o.state == ServerReq::kQueued && !o.cancelled) || o.state == ServerReq::kActive)
-      if (o.rem_work <= r.work) smaller += o.rem_work;
+      pend.push_back({o.rem_work, D - std::chrono::duration<double>(now - o.t_submit).count()});
   }
+  std::sort(pend.begin(), pend.end());
+  double ahead = 0.0;
+  for (const auto& p : pend)
+    if (p.first <= r.work) ahead += p.first;
+  // smaller work keeps arriving while r waits: at the rate a_w of the admitted submissions of
+  // the last few seconds that were no larger than r
   while (!recent.empty() && std::chrono::duration<double>(now - recent.front().first).count() > kArrivalWindowS)
     recent.pop_front();
   double arriving = 0.0;
   for (const auto& a : recent)
     if (a.second <= r.work) arriving += a.second;
   const double a_w = arriving / kArrivalWindowS;
-  const double alone = (double)r.K * update_floor_s;
-  if (a_w >= rate) return 1e300;
-  return 1e3 * std::max(alone, (smaller + r.work) / (rate - a_w));
+  const double done = a_w >= rate ? 1e300 : std::max((double)r.K * update_floor_s, (ahead + r.work) / (rate - a_w));
+  *ms = 1e3 * done;
+  if (done > D) {
+    *why = "its projected completion";
+    return false;
+  }
+  double cum = 0.0;
+  for (const auto& p : pend) {
+    cum += p.first;
+    if (p.first <= r.work) continue;
+    // its projected finish, delayed by r: refused also when it is late already, so that a
+    // request the projection underestimated is not overtaken by ever more smaller work
+    if ((cum + r.work) / rate > p.second) {
+      *why = "the projected completion of an admitted request";
+      return false;
+    }
+  }
+  return true;
 }
 
 void Server::fail_all(const std::string& msg) {
@@ -188,6 +224,7 @@ void Server::run() {
   Clock::time_point round_start{}, boundary = Clock::now();
   int64_t round_elements = 0;  // replica-variables per update of the last round
   bool round_backlogged = false;  // work was left waiting during the last round
+  double round_deadline_s = 0.0;
   for (;;) {
     hipError_t e = hipStreamSynchronize(st);  // round boundary: the device is idle
     if (e != hipSuccess) {
@@ -210,6 +247,7 @@ void Server::run() {
         round_elements = 0;
       }
       boundary = now;
+      round_deadline_s = 1e-3 * deadline_ms;
       // retire slots whose evaluation and copy-back finished in the previous round
       for (auto& sp : slots) {
         if (!sp || sp->state != ServerReq::kFinishing) continue;
@@ -306,13 +344,19 @@ void Server::run() {
     hubs.clear();
     eval_items.clear();
     ids.clear();
-    // running slots: least remaining work first, until an update covers kRunElements
-    std::vector<std::pair<int64_t, int>> by_work;
+    // running slots: least remaining work first (with a deadline, the urgent ones before
+    // them, oldest first), until an update covers kRunElements
+    std::vector<std::pair<std::pair<int64_t, int64_t>, int>> by_work;
+    const auto t_round = Clock::now();
     for (int s = 0; s < max_slots; ++s)
       if (slots[s] && slots[s]->state == ServerReq::kActive) {
         const auto& r = slots[s];
         const int64_t left = (int64_t)(r->K - std::max(0, clock - r->start));
-        by_work.push_back({left * r->n * (int64_t)qqa_replica_stride(r->S), s});
+        const double age = std::chrono::duration<double>(t_round - r->t_submit).count();
+        const bool urgent = round_deadline_s > 0.0 && age >= kUrgentFraction * round_deadline_s;
+        const int64_t key = urgent ? (int64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(r->t_submit.time_since_epoch()).count()
+                                   : left * r->n * (int64_t)qqa_replica_stride(r->S);
+        by_work.push_back({{urgent ? 0 : 1, key}, s});
       }
     std::sort(by_work.begin(), by_work.end());
     std::map<std::pair<int, int>, std::vector<int>> cls_slots;
@@ -623,20 +667,19 @@ int qqa_serve_submit(qqa_ctx* c, const qqa_graph* g, qqa_problem problem, const 
     if (sv->stopping) return set_err(c, QQA_E_ARG, "server is stopping");
     const auto now = Clock::now();
     ++sv->n_submitted;
-    if (sv->deadline_ms > 0.0) {
-      const double ms = sv->projected_ms(*r, now);
-      if (ms > sv->deadline_ms) {
-        ++sv->n_shed;
-        char buf[160];
-        snprintf(buf, sizeof buf, "shed: projected completion %.0f ms exceeds the %.0f ms deadline", std::min(ms, 1e12),
-                 sv->deadline_ms);
-        return set_err(c, QQA_E_ADMISSION, buf);
-      }
+    r->t_submit = now;
+    double ms = 0.0;
+    const char* why = "";
+    if (sv->deadline_ms > 0.0 && !sv->meets_deadline(*r, now, &ms, &why)) {
+      ++sv->n_shed;
+      char buf[200];
+      snprintf(buf, sizeof buf, "shed: admitting it would put %s past the %.0f ms deadline (its own: %.0f ms)", why,
+               sv->deadline_ms, std::min(ms, 1e12));
+      return set_err(c, QQA_E_ADMISSION, buf);
     }
     ++sv->n_admitted;
     sv->recent.emplace_back(now, r->work);
     r->id = sv->next_id++;
-    r->t_submit = now;
     sv->all.emplace(r->id, r);
     sv->queue.push_back(r);
   }

@@ -155,6 +155,42 @@ def test_shedding_refuses_by_projected_completion_and_admitted_equal_alone():
     ctx.close()
 
 
+def test_shedding_protects_admitted_requests():
+    """A large request is admitted with room to spare; small requests then arrive, each of
+    which alone would finish well within the deadline.  Least remaining work first runs them
+    before the large one, so each delays it: once the next would push it past its deadline,
+    the small ones are refused, citing the admitted request."""
+    q = qqa()
+    ctx = q.Context(0)
+    ctx.serve_start(64)
+    D = 400.0
+    ctx.serve_set_deadline(D)
+    R = ctx.serve_stats()["rate_updates_per_s"]  # the rate the projections use
+    # few updates of many rows, so that no request's time is set by its updates alone
+    stride = q.qqa_replica_stride(128)
+    k_big, k_small = 1000, 500
+    n_big = int(0.5 * D * 1e-3 * R / (k_big * stride))      # half the deadline
+    n_small = int(0.1 * D * 1e-3 * R / (k_small * stride))  # a tenth of it each
+    big = qi.erdos_renyi(n_big, 5.0, 11)
+    small = qi.erdos_renyi(n_small, 5.0, 12)
+    print("rate", R, "rows", n_big, n_small, flush=True)
+    first = ctx.serve_submit(big, "mis", 128, k_big, 1)
+    admitted, msgs = [], []
+    for k in range(12):
+        try:
+            admitted.append(ctx.serve_submit(small, "mis", 128, k_small, 10 + k))
+        except q.QQAError as e:
+            assert e.code == q.QQA_E_ADMISSION
+            msgs.append(str(e))
+    for i in [first] + admitted:
+        ctx.poll(i, want_x=False)
+    ctx.serve_stop()
+    ctx.close()
+    # the large one leaves room for about five; every refusal protects an admitted request
+    assert 2 <= len(admitted) <= 8 and msgs, (len(admitted), msgs[:1])
+    assert all("admitted request" in m for m in msgs), msgs[:2]
+
+
 def test_server_pool_reuses_buffers_across_many_sizes():
     """Requests of many distinct sizes one after another: the server's device pool reuses
     buffers by size class, so what it holds stays far below the sum of the requests."""
