@@ -161,9 +161,8 @@ hipError_t launch_persistent(const PersistParams& pp, int engine, int rows_per_g
 // team meets at a barrier between updates (bounded by timeout_ticks of the 100 MHz wall
 // clock; on time-out *abort is raised and every workgroup returns).
 constexpr int kResidentXcds = 8;
-// rows whose state each lane group holds (measured on the 512-instance batch: 4 rows, 338 us
-// per update; 2 rows, 350 us at more waves per SIMD)
-constexpr int kResidentRowsPerGroup = 4;
+// rows whose state each lane group holds (three rows fit four waves per SIMD without spills)
+constexpr int kResidentRowsPerGroup = 3;
 struct ResidentJob {
   int32_t slot;         // slot descriptor of the instance
   int32_t team;         // workgroups that run it (at most 128)

@@ -140,7 +140,7 @@ def test_resident_batch_equals_alone_bitwise(ctx, S):
     """One layout, one quad per lane, no split rows: the whole batch runs in one resident
     launch (teams of workgroups on one XCD, state in registers, P through the XCD's L2), and
     every instance ends with the bits of its solve alone."""
-    # at 128 replicas a lane group holds four rows of 32 lanes: about 3,000 rows fit one XCD
+    # at 128 replicas a lane group holds three rows of 32 lanes: about 3,000 rows fit one XCD
     inst = _one_width(40 if S == 32 else 12, S, S, n_range=(30, 2000) if S == 128 else (30, 5000))
     gids, batched = _run_batch(ctx, inst)
     assert all(b["engine"] == "batch_resident" for b in batched), batched[0]["engine"]
