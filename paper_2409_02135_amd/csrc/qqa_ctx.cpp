@@ -375,14 +375,23 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   } else if (r->engine == kEngineStream || r->engine == kEngineSliced) {
     const bool sliced = r->engine == kEngineSliced;
     float2* part[2] = {r->stats, r->stats + (size_t)g.n * kReplicaSlices};
+    // the sliced engine keeps the state slice-major where it can (each XCD's slice of P, m and
+    // v contiguous): P starts in P[1] and the loop's ping-pong begins there; m and v start at
+    // zero, and only P is converted back, for the evaluation
+    const bool sm = sliced && slice_major_ok(p, g.nchunks > 0);
+    float* Ps[2] = {r->P[0], r->P[1]};
+    if (sm) {
+      std::swap(Ps[0], Ps[1]);
+      if (e == hipSuccess) e = launch_slice_permute(r->P[0], Ps[0], g.n, S, true, c->stream);
+    }
     if (sliced && e == hipSuccess) {
-      p.P_in = r->P[0];
-      e = launch_slice_stats(p, part[0], c->stream);
+      p.P_in = Ps[0];
+      e = launch_slice_stats(p, part[0], c->stream, sm);
     }
     const int every = r->probe_every;
     for (int t = 0; t < steps && e == hipSuccess; ++t) {
-      p.P_in = r->P[t & 1];
-      p.P_out = r->P[(t + 1) & 1];
+      p.P_in = Ps[t & 1];
+      p.P_out = Ps[(t + 1) & 1];
       fill_step_scalars(p, r->sched, t, steps);
       if (r->colsum) {
         p.colsum = r->colsum;
@@ -399,12 +408,14 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
       if (g.nchunks && e == hipSuccess) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
       if (!g.dense && probe && e == hipSuccess) e = hipEventRecord(r->probe[pi], c->stream);
       if (sliced) {
-        if (e == hipSuccess) e = launch_slice_step(p, part[t & 1], part[(t + 1) & 1], c->stream);
+        if (e == hipSuccess) e = launch_slice_step(p, part[t & 1], part[(t + 1) & 1], c->stream, sm);
       } else if (e == hipSuccess) {
         e = launch_step(p, c->stream);
       }
       if (!g.dense && probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
     }
+    // the final P, row-major, in the buffer the evaluation reads (P[steps & 1])
+    if (sm && e == hipSuccess) e = launch_slice_permute(Ps[steps & 1], r->P[steps & 1], g.n, S, false, c->stream);
   } else {
     unsigned* bar = out_bar(r->out_dev, S);
     if (e == hipSuccess)

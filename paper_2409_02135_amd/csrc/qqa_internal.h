@@ -266,7 +266,12 @@ struct SliceShape {
   int nsl;  // slices: kReplicaSlices, or kReplicaSlices / 2 (XCD pairs) when that makes each a whole line
 };
 SliceShape slice_shape(int S);
-hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st);
+// slice_major: P (both buffers), m and v hold the state slice-major, [slice][row][slice
+// width] (equal slices, stride == S, no split rows, no max clique or dense product:
+// slice_major_ok); launch_slice_permute converts between that and the row-major n x stride.
+hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st, bool slice_major = false);
+bool slice_major_ok(const StepParams& p, bool split_rows);
+hipError_t launch_slice_permute(const float* src, float* dst, int n, int S, bool to_slice_major, hipStream_t st);
 
 // Compact engine (S = 1, sparse MIS or max-cut): P, m, v as n floats each.  pack takes
 // replica 0 of every row of a padded n x stride array; unpack writes rows {x, 0, 0, 0}
@@ -275,7 +280,8 @@ hipError_t launch_compact_step(const StepParams& p, const float* Pc_in, float* P
                                hipStream_t st);
 hipError_t launch_compact_pack(const float* src, int stride, int n, float* dst, hipStream_t st);
 hipError_t launch_compact_unpack(const float* src, int n, int stride, float* dst, hipStream_t st);
-hipError_t launch_slice_step(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st);
+hipError_t launch_slice_step(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st,
+                             bool slice_major = false);
 
 // Partial coupling sums of every chunk into p.hub_partial (reads P_in, row_ptr, col, w).
 hipError_t launch_hub_partials(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st);

@@ -27,16 +27,21 @@ namespace qqa {
 // The slice of `row` served by this workgroup, as a row of its own: pointers at the slice's
 // first replica, S = its valid replicas.  Slice s of NSL holds quads [s nq / NSL,
 // (s + 1) nq / NSL) of the row's nq quads.
-template <int NSL>
+// SM (slice-major state, equal slices, no split rows, sums or dense product): P, m and v
+// hold slice s's rows contiguously, [slice][row][its 4 (q1 - q0) replicas], so the row of
+// the view is 4 (q1 - q0) floats apart.
+template <int NSL, bool SM = false>
 __device__ __forceinline__ StepParams slice_view(const StepParams& a, const int slice, int* q0_out) {
   const int nq = (a.S + 3) >> 2;
   const int q0 = slice * nq / NSL, q1 = (slice + 1) * nq / NSL;
   const size_t off = 4 * (size_t)q0;
   StepParams b = a;
-  b.P_in = a.P_in + off;
-  b.P_out = a.P_out + off;
-  b.m = a.m ? a.m + off : nullptr;
-  b.v = a.v ? a.v + off : nullptr;
+  const size_t soff = SM ? (size_t)slice * a.n * 4 * (size_t)(q1 - q0) : off;
+  if (SM) b.stride = 4 * (q1 - q0);
+  b.P_in = a.P_in + soff;
+  b.P_out = a.P_out + soff;
+  b.m = a.m ? a.m + soff : nullptr;
+  b.v = a.v ? a.v + soff : nullptr;
   b.coupling = a.coupling ? a.coupling + off : nullptr;
   b.hub_partial = a.hub_partial ? a.hub_partial + off : nullptr;
   b.colsum = a.colsum ? a.colsum + off : nullptr;
@@ -125,7 +130,7 @@ __device__ __forceinline__ void slice_of_block(const int b, int* slice, int* row
 }
 
 // Partials of P (= a.P_in) for every (row, slice): the first update's statistics.
-template <int LS, int QS, bool FULL, int NSL>
+template <int LS, int QS, bool FULL, int NSL, bool SM>
 __global__ __launch_bounds__(kBlock) void slice_stats_kernel(StepParams a, float2* __restrict__ part) {
   int slice, rb;
   slice_of_block<NSL>((int)blockIdx.x, &slice, &rb);
@@ -133,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void slice_stats_kernel(StepParams a, float
   if (row >= a.n) return;  // whole lane groups leave together
   const int gl = threadIdx.x & (LS - 1);
   int q0;
-  const StepParams b = slice_view<NSL>(a, slice, &q0);
+  const StepParams b = slice_view<NSL, SM>(a, slice, &q0);
   float4 p[QS], mm[QS], vv[QS];
   load_row<LS, QS, FULL>(b, b.P_in, row, gl, p, mm, vv);
   const float2 pt = slice_partial<LS, QS, FULL>(b, gl, p);
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void slice_stats_kernel(StepParams a, float
 // One quad per lane: eight waves per SIMD, the register budget held to 64 (at most 62 used, no
 // spills; 80 unbounded, six waves).  Measured: 30.3 against 30.7 us at S = 256, 29.2 against
 // 30.4 at S = 512.  Two quads per lane would spill under that budget and keep theirs.
-template <int LS, int QS, bool FULL, bool SUMS, int NSL>
+template <int LS, int QS, bool FULL, bool SUMS, int NSL, bool SM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QS == 1 ? 8 : 1, 8))) void slice_step_kernel(StepParams a, const float2* __restrict__ part_in,
                                                             float2* __restrict__ part_out) {
   int slice, rb;
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QS == 1 
   if (row >= a.n) return;  // whole lane groups leave together
   const int gl = threadIdx.x & (LS - 1);
   int q0;
-  const StepParams b = slice_view<NSL>(a, slice, &q0);
+  const StepParams b = slice_view<NSL, SM>(a, slice, &q0);
   float4 p[QS], mm[QS], vv[QS], acc[QS], po[QS], mo[QS], vo[QS];
   const RowMeta rm = row_meta(b, row);
   float mu, cg;
@@ -206,41 +211,75 @@ static dim3 slice_grid(int n, int LS, int nsl) {
 }
 
 template <int LS, int QS, int NSL>
-static void launch_slice_stats_t(const StepParams& p, float2* part, hipStream_t st) {
+static void launch_slice_stats_t(const StepParams& p, float2* part, bool sm, hipStream_t st) {
   const dim3 grid = slice_grid(p.n, LS, NSL), block(kBlock);
-  if (p.S == 4 * NSL * LS * QS)  // equal slices, every lane's quads valid
-    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, true, NSL>), grid, block, 0, st, p, part);
+  if (sm)
+    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, true, NSL, true>), grid, block, 0, st, p, part);
+  else if (p.S == 4 * NSL * LS * QS)  // equal slices, every lane's quads valid
+    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, true, NSL, false>), grid, block, 0, st, p, part);
   else
-    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, false, NSL>), grid, block, 0, st, p, part);
+    hipLaunchKernelGGL((slice_stats_kernel<LS, QS, false, NSL, false>), grid, block, 0, st, p, part);
 }
 
 template <int LS, int QS, int NSL>
-static void launch_slice_t(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st) {
+static void launch_slice_t(const StepParams& p, const float2* part_in, float2* part_out, bool sm, hipStream_t st) {
   const dim3 grid = slice_grid(p.n, LS, NSL), block(kBlock);
   const bool full = p.S == 4 * NSL * LS * QS;  // equal slices, every lane's quads valid
   const bool sums = p.problem == kMAXCLIQUE;
-#define L(FU, SU) hipLaunchKernelGGL((slice_step_kernel<LS, QS, FU, SU, NSL>), grid, block, 0, st, p, part_in, part_out)
-  if (sums) {
-    if (full) L(true, true);
-    else L(false, true);
+#define L(FU, SU, M) \
+  hipLaunchKernelGGL((slice_step_kernel<LS, QS, FU, SU, NSL, M>), grid, block, 0, st, p, part_in, part_out)
+  if (sm) L(true, false, true);
+  else if (sums) {
+    if (full) L(true, true, false);
+    else L(false, true, false);
   } else {
-    if (full) L(true, false);
-    else L(false, false);
+    if (full) L(true, false, false);
+    else L(false, false, false);
   }
 #undef L
+}
+
+bool slice_major_ok(const StepParams& p, bool split_rows) {
+  const SliceShape s = slice_shape(p.S);
+  return s.sq != 0 && p.S == 4 * s.nsl * s.ls * s.qs && p.stride == p.S && !split_rows && !p.colsum &&
+         !p.coupling && p.problem != kMAXCLIQUE;
+}
+
+__global__ void slice_permute_kernel(const float4* __restrict__ src, float4* __restrict__ dst, int n, int nsl,
+                                     int wq, bool to_slice_major) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;  // quad index, row-major
+  const long long total = (long long)n * nsl * wq;
+  if (i >= total) return;
+  const long long row = i / ((long long)nsl * wq);
+  const int rest = (int)(i - row * nsl * wq), slice = rest / wq, k = rest - slice * wq;
+  const long long j = ((long long)slice * n + row) * wq + k;  // its quad index, slice-major
+  if (to_slice_major) dst[j] = src[i];
+  else dst[i] = src[j];
+}
+
+hipError_t launch_slice_permute(const float* src, float* dst, int n, int S, bool to_slice_major, hipStream_t st) {
+  const SliceShape s = slice_shape(S);
+  if (s.sq == 0 || S != 4 * s.nsl * s.ls * s.qs) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
+  const int wq = S / 4 / s.nsl;
+  hipLaunchKernelGGL(slice_permute_kernel, dim3(blocks_of((long long)n * s.nsl * wq)), dim3(kBlock), 0, st,
+                     reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n, s.nsl, wq,
+                     to_slice_major);
+  return hipGetLastError();
 }
 
 // (lanes, quads per lane, slices) of the kernels built: four slices serve 8 to 15 quads each
 #define QQA_FOR_EACH_SLICE_LAYOUT(X) \
   X(2, 1, 8) X(4, 1, 8) X(8, 1, 8) X(16, 1, 8) X(32, 1, 8) X(64, 1, 8) X(64, 2, 8) X(8, 1, 4) X(16, 1, 4)
 
-hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st) {
+hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st, bool slice_major) {
   if (p.n == 0) return hipSuccess;
   const SliceShape s = slice_shape(p.S);
   if (s.sq == 0) return hipErrorInvalidValue;
+  if (slice_major && !slice_major_ok(p, false)) return hipErrorInvalidValue;
 #define X(L, Q, N)                                     \
   if (s.ls == L && s.qs == Q && s.nsl == N) {          \
-    launch_slice_stats_t<L, Q, N>(p, part, st);        \
+    launch_slice_stats_t<L, Q, N>(p, part, slice_major, st); \
     return hipGetLastError();                  \
   }
   QQA_FOR_EACH_SLICE_LAYOUT(X)
@@ -248,13 +287,15 @@ hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st)
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_slice_step(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st) {
+hipError_t launch_slice_step(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st,
+                             bool slice_major) {
   if (p.n == 0) return hipSuccess;
   const SliceShape s = slice_shape(p.S);
   if (s.sq == 0) return hipErrorInvalidValue;
+  if (slice_major && !slice_major_ok(p, false)) return hipErrorInvalidValue;
 #define X(L, Q, N)                                       \
   if (s.ls == L && s.qs == Q && s.nsl == N) {            \
-    launch_slice_t<L, Q, N>(p, part_in, part_out, st);   \
+    launch_slice_t<L, Q, N>(p, part_in, part_out, slice_major, st); \
     return hipGetLastError();                            \
   }
   QQA_FOR_EACH_SLICE_LAYOUT(X)

@@ -190,6 +190,39 @@ def test_sliced_rejects_narrow_replica_counts():
     assert e.value.code == q.QQA_E_ARG
 
 
+@pytest.mark.parametrize("n,S,problem", [(4000, 256, "mis"), (3000, 512, "maxcut"), (2500, 128, "mis"),
+                                         (3000, 200, "mis")])
+def test_context_slice_major_state_equals_row_major(n, S, problem):
+    """A context's sliced solve keeps its state slice-major where the slices are equal (each
+    XCD's slice of P, m, v contiguous) and converts P back for the evaluation; the per-stage
+    path runs the same engine on row-major buffers.  Same seed, schedule and updates: every
+    replica's exact objective, the best replica and its solution agree bit for bit (S = 200
+    has unequal slices and stays row-major in both)."""
+    q = qqa()
+    g = qi.erdos_renyi(n, 6.0, 40 + S)
+    if problem == "maxcut":
+        g = qi.pm1_weights(g, 3)
+    K, seed = 120, 17
+    ctx = q.Context(0)
+    gid = ctx.upload(g, problem)
+    ctx.set_engine("sliced")
+    r = ctx.poll(ctx.solve_resident(gid, n, problem, S, K, seed))
+    ctx.release(gid)
+    ctx.close()
+    assert r["engine"] == "sliced"
+    P, _, _ = run(q, g, problem, S, 0, K, K, seed, "sliced")
+    d = torch.device("cuda")
+    out = [torch.zeros((S,), dtype=torch.int64, device=d) for _ in range(3)]
+    best = torch.zeros((1,), dtype=torch.int32, device=d)
+    q.qqa_dev_eval(q.DevGraph(g), problem, q.schedule(problem, n).penalty_lambda, S, P[K & 1], *out, best)
+    torch.cuda.synchronize()
+    assert np.array_equal(r["obj"], out[2].cpu().numpy()), (n, S)
+    assert np.array_equal(r["size_or_cut"], out[0].cpu().numpy())
+    assert r["best_replica"] == int(best.item())
+    x = (P[K & 1][:, r["best_replica"]] > 0.5).to(torch.uint8).cpu().numpy()
+    assert np.array_equal(r["best_x"], x)
+
+
 def test_context_sliced_policy():
     from test_gpu_solve import objective_of
     q = qqa()
