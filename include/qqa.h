@@ -224,7 +224,7 @@ int qqa_solve_coloring_resident(qqa_ctx *c, qqa_graph_id g, int32_t colors, cons
  * batch is a single launch covering all instances (each at its own update index), the
  * update loop is replayed from a captured HIP graph.  Instances never interact: each
  * result equals that of the same solve run alone on the whole-row engines (under the
- * automatic policy a solve alone with S >= 256 may run on SLICED, which agrees to
+ * automatic policy a solve alone with S >= 128 may run on SLICED, which agrees to
  * rounding after one update; see qqa_engine).  Graph ids come from
  * qqa_graph_upload.  Arrays have `count` entries; sched may be NULL (defaults).  Dense
  * graphs and max clique are solved one at a time (QQA_E_ARG here). */
@@ -269,7 +269,10 @@ int qqa_autotune(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, int32_t S, int
  * on LDS_BLOCK when it qualifies (one quad per lane in a full-width layout, no rows split
  * into chunks, P fits in one workgroup's LDS), else COMPACT for S = 1 (sparse MIS or
  * max-cut), else SLICED when the graph is sparse, S >= 256 and P (n x stride floats) is at
- * most 24 MiB, else STREAM;
+ * most 24 MiB, or when the solve can keep its state slice-major (S a multiple of the slice
+ * count times the slice's lanes, no rows split into chunks, not max clique) and S >= 256
+ * with P at most 64 MiB, or S >= 128 with P at most 32 MiB; else STREAM.  (The per-stage
+ * qqa_dev_run keeps the row-major rule alone);
  * QQA_ENGINE_PERSISTENT runs the register-resident engine when the instance fits on chip
  * (else STREAM); QQA_ENGINE_LDS_BLOCK / QQA_ENGINE_SLICED / QQA_ENGINE_COMPACT /
  * QQA_ENGINE_STREAM force those engines where possible.  QQA_E_ARG for BATCH or an unknown
@@ -295,7 +298,7 @@ int qqa_cancel(qqa_ctx *c, qqa_req id);
  * update covers about 8M replica-variables; the others keep their place for the round.
  * So small requests finish at close to their time alone.  A served result is identical to
  * the same solve run alone on the whole-row engines (STREAM, and BATCH); under the
- * automatic policy a solve alone with S >= 256 may run on SLICED, whose results agree with
+ * automatic policy a solve alone with S >= 128 may run on SLICED, whose results agree with
  * the served one to rounding after one update (see qqa_engine).  Replica layouts set on the
  * context before qqa_serve_start apply.  Collect results with qqa_poll (queue_ms = submit ->
  * admission, first_update_ms = submit -> first update launched, latency_ms = submit ->

@@ -315,9 +315,14 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
       r->footprint += 4 * (size_t)g.n * sizeof(float);
     }
     // a streaming sparse solve runs sliced when asked for, or by default when its slices
-    // are whole cache lines and fit the XCDs' L2
+    // are whole cache lines and fit the XCDs' L2 (further when its state can be slice-major)
+    StepParams shape{};
+    shape.S = S;
+    shape.stride = r->shape.stride;
+    shape.problem = problem;
+    const bool sm = slice_major_ok(shape, g.nchunks > 0);
     if (r->engine == kEngineStream && !g.dense && slice_shape(S).sq > 0 &&
-        (c->engine_policy == QQA_ENGINE_SLICED || (c->engine_policy < 0 && slice_by_default(g.n, S)))) {
+        (c->engine_policy == QQA_ENGINE_SLICED || (c->engine_policy < 0 && slice_by_default(g.n, S, sm)))) {
       r->engine = kEngineSliced;
       r->footprint += 2 * (size_t)g.n * kReplicaSlices * sizeof(float2);
     }

@@ -502,7 +502,7 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
     if (engine >= 0 && use != engine) return fail(&g_dev_error, QQA_E_ARG, "engine cannot run this instance");
   }
   if (engine < 0 && use == kEngineStream && compactable) use = kEngineCompact;
-  if (engine < 0 && use == kEngineStream && sliceable && slice_by_default(g->n, S)) use = kEngineSliced;
+  if (engine < 0 && use == kEngineStream && sliceable && slice_by_default(g->n, S, false)) use = kEngineSliced;
   float* P[2] = {P0, P1};
   if (use == kEngineCompact) {
     const size_t n = (size_t)g->n;

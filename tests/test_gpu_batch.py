@@ -45,8 +45,8 @@ def test_batch_equals_alone_bitwise(ctx):
                           [i[3] for i in inst], [i[4] for i in inst])
     batched = [ctx.poll(i) for i in ids]
     for (g, p, S, K, seed), gid, b in zip(inst, gids, batched):
-        # the sliced engine (automatic at S >= 256) rounds the replica statistics differently
-        ctx.set_engine("stream" if S >= 256 else "auto")
+        # the sliced engine (automatic from S = 128) rounds the replica statistics differently
+        ctx.set_engine("stream")
         alone = ctx.poll(ctx.solve_resident(gid, g["n"], p, S, K, seed))
         assert np.array_equal(b["obj"], alone["obj"]), (g["n"], p, S, K)
         assert np.array_equal(b["size_or_cut"], alone["size_or_cut"])
@@ -124,6 +124,7 @@ def _run_batch(c, inst):
 
 
 def _check_alone(c, inst, gids, batched):
+    c.set_engine("stream")  # the whole-row engines (the automatic policy may slice from S = 128)
     for (g, p, S, K, seed), gid, b in zip(inst, gids, batched):
         alone = c.poll(c.solve_resident(gid, g["n"], p, S, K, seed))
         assert np.array_equal(b["obj"], alone["obj"]), (g["n"], p, S, K)
@@ -131,6 +132,7 @@ def _check_alone(c, inst, gids, batched):
         assert np.array_equal(b["viol"], alone["viol"])
         assert np.array_equal(b["best_x"], alone["best_x"])
         assert b["best_replica"] == alone["best_replica"]
+    c.set_engine("auto")
     for gid in gids:
         c.release(gid)
 

@@ -107,9 +107,9 @@ def test_context_engine_policy_same_results():
     ctx.release(gid)
     assert a["engine"] == "persistent" and np.array_equal(a["obj"], b["obj"])
     # automatic: the LDS engine for an instance that fits one workgroup (same bits as
-    # streaming), whole-row streaming for S = 128, slices for S = 256 (its own tests)
-    for g, S, engine in [(qi.random_regular(256, 3, 0), 16, "lds_block"), (qi.erdos_renyi(20000, 5.0, 0), 128, "stream"),
-                         (qi.erdos_renyi(20000, 5.0, 0), 256, "sliced")]:
+    # streaming), whole-row streaming for S = 64, slices for S = 128 and 256 (their own tests)
+    for g, S, engine in [(qi.random_regular(256, 3, 0), 16, "lds_block"), (qi.erdos_renyi(20000, 5.0, 0), 64, "stream"),
+                         (qi.erdos_renyi(20000, 5.0, 0), 128, "sliced"), (qi.erdos_renyi(20000, 5.0, 0), 256, "sliced")]:
         gid = ctx.upload(g, "mis")
         ctx.set_engine("auto")
         a = ctx.poll(ctx.solve_resident(gid, g["n"], "mis", S, 150, 3))

@@ -47,6 +47,7 @@ def test_served_results_equal_alone_and_overlap():
             time.sleep(0.01)  # later requests arrive while earlier ones run
     served = [ctx.poll(i) for i in ids]
     ctx.serve_stop()
+    ctx.set_engine("stream")  # the whole-row engines (the automatic policy may slice from S = 128)
     for (g, p, S, K, seed), r in zip(reqs, served):
         alone = ctx.poll(ctx.solve(g, p, S, K, seed))
         assert np.array_equal(r["obj"], alone["obj"]), (g["n"], p, S, K)
@@ -72,6 +73,7 @@ def test_requests_beyond_one_launch_wait_their_turn_and_equal_alone():
     ids += [ctx.serve_submit(*r) for r in small]
     served = [ctx.poll(i) for i in ids]
     ctx.serve_stop()
+    ctx.set_engine("stream")  # the whole-row engines (the automatic policy may slice from S = 128)
     for (g, p, S, K, seed), r in zip(big + small, served):
         alone = ctx.poll(ctx.solve(g, p, S, K, seed))
         assert np.array_equal(r["obj"], alone["obj"]), (g["n"], p, S, K)
@@ -140,11 +142,13 @@ def test_shedding_refuses_by_projected_completion_and_admitted_equal_alone():
     assert shed > 0 and admitted
     assert st["submitted"] == 20 and st["admitted"] == len(admitted) and st["shed"] == shed
     assert st["completed"] == len(admitted) and st["rate_updates_per_s"] > 0
+    ctx.set_engine("stream")  # the whole-row engines (the automatic policy may slice from S = 128)
     for r, sd in res[:3]:
         alone = ctx.poll(ctx.solve(g, "mis", 128, 500, sd))
         assert np.array_equal(r["obj"], alone["obj"]) and np.array_equal(r["best_x"], alone["best_x"])
         assert 0 <= r["queue_ms"] <= r["first_update_ms"] <= r["latency_ms"]
     # without a deadline nothing is shed
+    ctx.set_engine("auto")
     ctx.serve_start(64)
     ids = [ctx.serve_submit(g, "mis", 128, 50, 300 + k) for k in range(6)]
     for i in ids:

@@ -237,10 +237,15 @@ def test_context_sliced_policy():
         assert a["engine"] == "sliced" and a["kernel_us"] > 0
         assert np.array_equal(a["obj"], b["obj"]) and np.array_equal(a["best_x"], b["best_x"])
         assert a["best_objective"] == objective_of(g, a["best_x"], problem)
-    # automatic policy: slices of whole 128-byte lines whose share of P fits an XCD's L2
+    # automatic policy: slices of whole 128-byte lines whose share of P fits an XCD's L2;
+    # with the state slice-major (equal slices, no split rows) P up to 64 MiB, and four
+    # slices from S = 128 with P up to 32 MiB
     ctx.set_engine("auto")
-    for g, S, engine in [(qi.erdos_renyi(2000, 8.0, 1), 256, "sliced"), (qi.erdos_renyi(2000, 8.0, 1), 128, "stream"),
-                         (qi.erdos_renyi(1000, 8.0, 1), 1000, "sliced"), (qi.erdos_renyi(30000, 4.0, 1), 256, "stream")]:
+    hubs = qi.barabasi_albert(5000, 4, 1)  # rows above the split threshold
+    for g, S, engine in [(qi.erdos_renyi(2000, 8.0, 1), 256, "sliced"), (qi.erdos_renyi(2000, 8.0, 1), 128, "sliced"),
+                         (qi.erdos_renyi(2000, 8.0, 1), 64, "stream"), (hubs, 128, "stream"), (hubs, 256, "sliced"),
+                         (qi.erdos_renyi(1000, 8.0, 1), 1000, "sliced"), (qi.erdos_renyi(30000, 4.0, 1), 256, "sliced"),
+                         (qi.erdos_renyi(80000, 4.0, 1), 256, "stream"), (qi.erdos_renyi(40000, 4.0, 1), 200, "stream")]:
         gid = ctx.upload(g, "mis")
         assert ctx.poll(ctx.solve_resident(gid, g["n"], "mis", S, 50, 1))["engine"] == engine, (g["n"], S)
         ctx.release(gid)
