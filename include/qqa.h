@@ -270,9 +270,8 @@ int qqa_autotune(qqa_ctx *c, qqa_graph_id g, qqa_problem problem, int32_t S, int
  * into chunks, P fits in one workgroup's LDS), else COMPACT for S = 1 (sparse MIS or
  * max-cut), else SLICED when the graph is sparse, S >= 256 and P (n x stride floats) is at
  * most 24 MiB, or when the solve can keep its state slice-major (S a multiple of the slice
- * count times the slice's lanes, no rows split into chunks, not max clique) and S >= 256
- * with P at most 64 MiB, or S >= 128 with P at most 32 MiB; else STREAM.  (The per-stage
- * qqa_dev_run keeps the row-major rule alone);
+ * count times the slice's lanes, not max clique), S >= 128 and P at most 64 MiB; else
+ * STREAM.  (The per-stage qqa_dev_run keeps the row-major rule alone);
  * QQA_ENGINE_PERSISTENT runs the register-resident engine when the instance fits on chip
  * (else STREAM); QQA_ENGINE_LDS_BLOCK / QQA_ENGINE_SLICED / QQA_ENGINE_COMPACT /
  * QQA_ENGINE_STREAM force those engines where possible.  QQA_E_ARG for BATCH or an unknown

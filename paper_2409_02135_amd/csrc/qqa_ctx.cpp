@@ -320,7 +320,7 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
     shape.S = S;
     shape.stride = r->shape.stride;
     shape.problem = problem;
-    const bool sm = slice_major_ok(shape, g.nchunks > 0);
+    const bool sm = slice_major_ok(shape);
     if (r->engine == kEngineStream && !g.dense && slice_shape(S).sq > 0 &&
         (c->engine_policy == QQA_ENGINE_SLICED || (c->engine_policy < 0 && slice_by_default(g.n, S, sm)))) {
       r->engine = kEngineSliced;
@@ -383,7 +383,7 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
     // the sliced engine keeps the state slice-major where it can (each XCD's slice of P, m and
     // v contiguous): P starts in P[1] and the loop's ping-pong begins there; m and v start at
     // zero, and only P is converted back, for the evaluation
-    const bool sm = sliced && slice_major_ok(p, g.nchunks > 0);
+    const bool sm = sliced && slice_major_ok(p);
     float* Ps[2] = {r->P[0], r->P[1]};
     if (sm) {
       std::swap(Ps[0], Ps[1]);
@@ -410,10 +410,12 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
         if (e == hipSuccess) e = launch_dense_parts(g.dense, p.P_in, r->coupling, g.n, p.stride, problem, c->stream);
         if (probe && e == hipSuccess) e = hipEventRecord(r->probe[pi + 1], c->stream);
       }
-      if (g.nchunks && e == hipSuccess) e = launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
+      if (g.nchunks && e == hipSuccess)
+        e = sm ? launch_slice_hub_partials(p, g.chunks, g.nchunks, c->stream)
+               : launch_hub_partials(p, g.chunks, g.nchunks, c->stream);
       if (!g.dense && probe && e == hipSuccess) e = hipEventRecord(r->probe[pi], c->stream);
       if (sliced) {
-        if (e == hipSuccess) e = launch_slice_step(p, part[t & 1], part[(t + 1) & 1], c->stream, sm);
+        if (e == hipSuccess) e = launch_slice_step(p, part[t & 1], part[(t + 1) & 1], c->stream, sm, g.nchunks);
       } else if (e == hipSuccess) {
         e = launch_step(p, c->stream);
       }

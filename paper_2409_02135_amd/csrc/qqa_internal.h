@@ -255,19 +255,20 @@ constexpr int kReplicaSlices = 8;
 // one 128-byte line of a row (S >= 256) and one XCD's slice of P fits in its 4 MiB L2 with
 // room to spare (P at most 24 MiB).  Narrower slices waste fetched lines; larger P leaves
 // the gathers missing L2 anyway.  Where the state can be kept slice-major (a context's
-// solve with equal slices and no split rows, not max clique), each XCD streams its slice
-// as one region and the sliced engine wins further: S >= 256 with P up to 64 MiB, and four
-// slices of a line each (S from 128) with P up to 32 MiB.  (Measured, 500 updates, ER mean
-// degree 5, stream against slice-major sliced, us per update: n = 50,000, S = 256: 80.4 /
-// 73.8; n = 100,000, S = 256: 159.4 / 161.6; n = 20,000 and 50,000, S = 128: 19.7 / 18.4
-// and 41.8 / 39.4.)
+// solve with equal slices, not max clique), each XCD streams its slice as one region and the
+// sliced engine wins further: from S = 128 (four slices of a line each below 256) with P up
+// to 64 MiB.  (Measured, 500 updates, stream against slice-major sliced, us per update: ER
+// mean degree 5, S = 256, n = 50,000 / 60,000 / 100,000: 80.4 / 73.8, 96.4 / 89.9,
+// 159.4 / 161.6; S = 128, n = 20,000 / 50,000 / 100,000 / 130,000: 19.7 / 18.4,
+// 41.8 / 39.4, 80.7 / 79.3, 101.8 / 104.7; BA m = 4 with split hub rows, S = 128,
+// n = 50,000 / 100,000: 50.9 / 45.8, 99.4 / 94.7; S = 256, n = 50,000: 99.0 / 83.2.)
 constexpr int kSliceAutoMinReplicas = 256;
 constexpr size_t kSliceAutoMaxBytes = (size_t)24 << 20;
+constexpr size_t kSliceMajorAutoMaxBytes = (size_t)64 << 20;
 inline bool slice_by_default(int n, int S, bool slice_major) {
   const size_t stride = 4 * (size_t)((S + 3) / 4);
   const size_t bytes = (size_t)n * stride * sizeof(float);
-  if (slice_major)
-    return (S >= kSliceAutoMinReplicas && bytes <= ((size_t)64 << 20)) || (S >= 128 && bytes <= ((size_t)32 << 20));
+  if (slice_major && S >= 128 && bytes <= kSliceMajorAutoMaxBytes) return true;
   return S >= kSliceAutoMinReplicas && bytes <= kSliceAutoMaxBytes;
 }
 struct SliceShape {
@@ -276,10 +277,12 @@ struct SliceShape {
 };
 SliceShape slice_shape(int S);
 // slice_major: P (both buffers), m and v hold the state slice-major, [slice][row][slice
-// width] (equal slices, stride == S, no split rows, no max clique or dense product:
+// width], and the split rows' chunk partials [slice][chunk][slice width], written by
+// launch_slice_hub_partials (equal slices, stride == S, no max clique or dense product:
 // slice_major_ok); launch_slice_permute converts between that and the row-major n x stride.
 hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st, bool slice_major = false);
-bool slice_major_ok(const StepParams& p, bool split_rows);
+bool slice_major_ok(const StepParams& p);
+hipError_t launch_slice_hub_partials(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st);
 hipError_t launch_slice_permute(const float* src, float* dst, int n, int S, bool to_slice_major, hipStream_t st);
 
 // Compact engine (S = 1, sparse MIS or max-cut): P, m, v as n floats each.  pack takes
@@ -290,7 +293,7 @@ hipError_t launch_compact_step(const StepParams& p, const float* Pc_in, float* P
 hipError_t launch_compact_pack(const float* src, int stride, int n, float* dst, hipStream_t st);
 hipError_t launch_compact_unpack(const float* src, int n, int stride, float* dst, hipStream_t st);
 hipError_t launch_slice_step(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st,
-                             bool slice_major = false);
+                             bool slice_major = false, int nchunks = 0);
 
 // Partial coupling sums of every chunk into p.hub_partial (reads P_in, row_ptr, col, w).
 hipError_t launch_hub_partials(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st);

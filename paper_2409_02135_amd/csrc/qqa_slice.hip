@@ -27,11 +27,13 @@ namespace qqa {
 // The slice of `row` served by this workgroup, as a row of its own: pointers at the slice's
 // first replica, S = its valid replicas.  Slice s of NSL holds quads [s nq / NSL,
 // (s + 1) nq / NSL) of the row's nq quads.
-// SM (slice-major state, equal slices, no split rows, sums or dense product): P, m and v
-// hold slice s's rows contiguously, [slice][row][its 4 (q1 - q0) replicas], so the row of
-// the view is 4 (q1 - q0) floats apart.
+// SM (slice-major state, equal slices, no sums or dense product): P, m and v hold slice
+// s's rows contiguously, [slice][row][its 4 (q1 - q0) replicas], so the row of the view is
+// 4 (q1 - q0) floats apart; the split rows' chunk partials likewise, [slice][chunk][width]
+// (nchunks chunks).
 template <int NSL, bool SM = false>
-__device__ __forceinline__ StepParams slice_view(const StepParams& a, const int slice, int* q0_out) {
+__device__ __forceinline__ StepParams slice_view(const StepParams& a, const int slice, int* q0_out,
+                                                 const int nchunks = 0) {
   const int nq = (a.S + 3) >> 2;
   const int q0 = slice * nq / NSL, q1 = (slice + 1) * nq / NSL;
   const size_t off = 4 * (size_t)q0;
@@ -43,7 +45,8 @@ __device__ __forceinline__ StepParams slice_view(const StepParams& a, const int 
   b.m = a.m ? a.m + soff : nullptr;
   b.v = a.v ? a.v + soff : nullptr;
   b.coupling = a.coupling ? a.coupling + off : nullptr;
-  b.hub_partial = a.hub_partial ? a.hub_partial + off : nullptr;
+  const size_t hoff = SM ? (size_t)slice * nchunks * 4 * (size_t)(q1 - q0) : off;
+  b.hub_partial = a.hub_partial ? a.hub_partial + hoff : nullptr;
   b.colsum = a.colsum ? a.colsum + off : nullptr;
   b.S = min(a.S, 4 * q1) - 4 * q0;
   *q0_out = q0;
@@ -175,14 +178,14 @@ __global__ __launch_bounds__(kBlock) void slice_stats_kernel(StepParams a, float
 // 30.4 at S = 512.  Two quads per lane would spill under that budget and keep theirs.
 template <int LS, int QS, bool FULL, bool SUMS, int NSL, bool SM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QS == 1 ? 8 : 1, 8))) void slice_step_kernel(StepParams a, const float2* __restrict__ part_in,
-                                                            float2* __restrict__ part_out) {
+                                                            float2* __restrict__ part_out, int nchunks) {
   int slice, rb;
   slice_of_block<NSL>((int)blockIdx.x, &slice, &rb);
   const int row = rb * (kBlock / LS) + (int)(threadIdx.x / LS);
   if (row >= a.n) return;  // whole lane groups leave together
   const int gl = threadIdx.x & (LS - 1);
   int q0;
-  const StepParams b = slice_view<NSL, SM>(a, slice, &q0);
+  const StepParams b = slice_view<NSL, SM>(a, slice, &q0, nchunks);
   float4 p[QS], mm[QS], vv[QS], acc[QS], po[QS], mo[QS], vo[QS];
   const RowMeta rm = row_meta(b, row);
   float mu, cg;
@@ -198,6 +201,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QS == 1 
   store_row<LS, QS, FULL>(b, b.P_out, row, gl, po, mo, vo, true);
   const float2 pt = slice_partial<LS, QS, FULL>(b, gl, po);
   if (gl == 0) part_out[(size_t)slice * a.n + row] = pt;
+}
+
+// Split rows with slice-major state: the partial coupling sum of one chunk over one slice
+// of the replicas, in the chunk's edge order (the same sums, bit for bit, as the whole-row
+// chunk kernel's), written [slice][chunk][width].  Workgroup b serves slice b mod 8 (XCD
+// pairs with four slices), as the update does.
+template <int LS, int QS, int NSL>
+__global__ __launch_bounds__(kBlock) void slice_hub_partial_kernel(StepParams a, const HubChunk* __restrict__ chunks,
+                                                                   int nchunks) {
+  int slice, rb;
+  slice_of_block<NSL>((int)blockIdx.x, &slice, &rb);
+  const int c = rb * (kBlock / LS) + (int)(threadIdx.x / LS);
+  if (c >= nchunks) return;  // whole lane groups leave together
+  const int gl = threadIdx.x & (LS - 1);
+  int q0;
+  const StepParams b = slice_view<NSL, true>(a, slice, &q0, nchunks);
+  const HubChunk ch = chunks[c];
+  const int e_end = min(ch.e0 + kHubChunk, a.row_ptr[ch.row + 1]);
+  float4 acc[QS];
+#pragma unroll
+  for (int k = 0; k < QS; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  gather_coupling<LS, QS, true, false, false>(b, ch.e0, e_end, gl, LS * QS, a.problem == kMAXCUT, acc);
+  float* out = const_cast<float*>(b.hub_partial) + (size_t)c * b.stride;
+#pragma unroll
+  for (int k = 0; k < QS; ++k) *reinterpret_cast<float4*>(out + 4 * (gl + LS * k)) = acc[k];
 }
 
 static unsigned blocks_of(long long threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
@@ -245,12 +273,13 @@ static void launch_slice_stats_t(const StepParams& p, float2* part, bool sm, hip
 }
 
 template <int LS, int QS, int NSL>
-static void launch_slice_t(const StepParams& p, const float2* part_in, float2* part_out, bool sm, hipStream_t st) {
+static void launch_slice_t(const StepParams& p, const float2* part_in, float2* part_out, bool sm, int nchunks,
+                           hipStream_t st) {
   const dim3 grid = slice_grid(p.n, LS, NSL), block(kBlock);
   const bool full = p.S == 4 * NSL * LS * QS;  // equal slices, every lane's quads valid
   const bool sums = p.problem == kMAXCLIQUE;
 #define L(FU, SU, M) \
-  hipLaunchKernelGGL((slice_step_kernel<LS, QS, FU, SU, NSL, M>), grid, block, 0, st, p, part_in, part_out)
+  hipLaunchKernelGGL((slice_step_kernel<LS, QS, FU, SU, NSL, M>), grid, block, 0, st, p, part_in, part_out, nchunks)
   if (sm) L(true, false, true);
   else if (sums) {
     if (full) L(true, true, false);
@@ -262,10 +291,16 @@ static void launch_slice_t(const StepParams& p, const float2* part_in, float2* p
 #undef L
 }
 
-bool slice_major_ok(const StepParams& p, bool split_rows) {
+bool slice_major_ok(const StepParams& p) {
   const SliceShape s = slice_shape(p.S);
-  return s.sq != 0 && p.S == 4 * s.nsl * s.ls * s.qs && p.stride == p.S && !split_rows && !p.colsum &&
-         !p.coupling && p.problem != kMAXCLIQUE;
+  return s.sq != 0 && p.S == 4 * s.nsl * s.ls * s.qs && p.stride == p.S && !p.colsum && !p.coupling &&
+         p.problem != kMAXCLIQUE;
+}
+
+template <int LS, int QS, int NSL>
+static void launch_slice_hub_t(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st) {
+  hipLaunchKernelGGL((slice_hub_partial_kernel<LS, QS, NSL>), slice_grid(nchunks, LS, NSL), dim3(kBlock), 0, st, p,
+                     chunks, nchunks);
 }
 
 __global__ void slice_permute_kernel(const float4* __restrict__ src, float4* __restrict__ dst, int n, int nsl,
@@ -299,7 +334,7 @@ hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st,
   if (p.n == 0) return hipSuccess;
   const SliceShape s = slice_shape(p.S);
   if (s.sq == 0) return hipErrorInvalidValue;
-  if (slice_major && !slice_major_ok(p, false)) return hipErrorInvalidValue;
+  if (slice_major && !slice_major_ok(p)) return hipErrorInvalidValue;
 #define X(L, Q, N)                                     \
   if (s.ls == L && s.qs == Q && s.nsl == N) {          \
     launch_slice_stats_t<L, Q, N>(p, part, slice_major, st); \
@@ -311,14 +346,28 @@ hipError_t launch_slice_stats(const StepParams& p, float2* part, hipStream_t st,
 }
 
 hipError_t launch_slice_step(const StepParams& p, const float2* part_in, float2* part_out, hipStream_t st,
-                             bool slice_major) {
+                             bool slice_major, int nchunks) {
   if (p.n == 0) return hipSuccess;
   const SliceShape s = slice_shape(p.S);
   if (s.sq == 0) return hipErrorInvalidValue;
-  if (slice_major && !slice_major_ok(p, false)) return hipErrorInvalidValue;
+  if (slice_major && !slice_major_ok(p)) return hipErrorInvalidValue;
 #define X(L, Q, N)                                       \
   if (s.ls == L && s.qs == Q && s.nsl == N) {            \
-    launch_slice_t<L, Q, N>(p, part_in, part_out, slice_major, st); \
+    launch_slice_t<L, Q, N>(p, part_in, part_out, slice_major, nchunks, st); \
+    return hipGetLastError();                            \
+  }
+  QQA_FOR_EACH_SLICE_LAYOUT(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_slice_hub_partials(const StepParams& p, const HubChunk* chunks, int nchunks, hipStream_t st) {
+  if (nchunks == 0) return hipSuccess;
+  if (!slice_major_ok(p)) return hipErrorInvalidValue;
+  const SliceShape s = slice_shape(p.S);
+#define X(L, Q, N)                                       \
+  if (s.ls == L && s.qs == Q && s.nsl == N) {            \
+    launch_slice_hub_t<L, Q, N>(p, chunks, nchunks, st); \
     return hipGetLastError();                            \
   }
   QQA_FOR_EACH_SLICE_LAYOUT(X)

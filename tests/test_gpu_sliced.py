@@ -190,16 +190,18 @@ def test_sliced_rejects_narrow_replica_counts():
     assert e.value.code == q.QQA_E_ARG
 
 
-@pytest.mark.parametrize("n,S,problem", [(4000, 256, "mis"), (3000, 512, "maxcut"), (2500, 128, "mis"),
-                                         (3000, 200, "mis")])
-def test_context_slice_major_state_equals_row_major(n, S, problem):
+@pytest.mark.parametrize("n,S,problem,family", [(4000, 256, "mis", "er"), (3000, 512, "maxcut", "er"),
+                                                (2500, 128, "mis", "er"), (3000, 200, "mis", "er"),
+                                                (5000, 128, "maxcut", "ba"), (4000, 256, "mis", "ba")])
+def test_context_slice_major_state_equals_row_major(n, S, problem, family):
     """A context's sliced solve keeps its state slice-major where the slices are equal (each
-    XCD's slice of P, m, v contiguous) and converts P back for the evaluation; the per-stage
-    path runs the same engine on row-major buffers.  Same seed, schedule and updates: every
-    replica's exact objective, the best replica and its solution agree bit for bit (S = 200
-    has unequal slices and stays row-major in both)."""
+    XCD's slice of P, m, v contiguous, and the split rows' chunk partials per slice) and
+    converts P back for the evaluation; the per-stage path runs the same engine on row-major
+    buffers.  Same seed, schedule and updates: every replica's exact objective, the best
+    replica and its solution agree bit for bit (S = 200 has unequal slices and stays
+    row-major in both; the BA graphs have split hub rows)."""
     q = qqa()
-    g = qi.erdos_renyi(n, 6.0, 40 + S)
+    g = qi.erdos_renyi(n, 6.0, 40 + S) if family == "er" else qi.barabasi_albert(n, 4, 40 + S)
     if problem == "maxcut":
         g = qi.pm1_weights(g, 3)
     K, seed = 120, 17
@@ -243,7 +245,7 @@ def test_context_sliced_policy():
     ctx.set_engine("auto")
     hubs = qi.barabasi_albert(5000, 4, 1)  # rows above the split threshold
     for g, S, engine in [(qi.erdos_renyi(2000, 8.0, 1), 256, "sliced"), (qi.erdos_renyi(2000, 8.0, 1), 128, "sliced"),
-                         (qi.erdos_renyi(2000, 8.0, 1), 64, "stream"), (hubs, 128, "stream"), (hubs, 256, "sliced"),
+                         (qi.erdos_renyi(2000, 8.0, 1), 64, "stream"), (hubs, 128, "sliced"), (hubs, 256, "sliced"),
                          (qi.erdos_renyi(1000, 8.0, 1), 1000, "sliced"), (qi.erdos_renyi(30000, 4.0, 1), 256, "sliced"),
                          (qi.erdos_renyi(80000, 4.0, 1), 256, "stream"), (qi.erdos_renyi(40000, 4.0, 1), 200, "stream")]:
         gid = ctx.upload(g, "mis")
