@@ -12,7 +12,8 @@
 // while a job runs, and an instance's P ping-pong (256 B per row at 32 replicas) stays in
 // L2.
 //
-// The host splits the jobs over the XCDs (longest processing time first).  On each XCD,
+// The host splits the jobs over the XCDs (longest processing time first) and orders each
+// XCD's jobs in rounds whose teams fill its workgroups (first-fit decreasing).  On each XCD,
 // workgroups claim team places in job order from a counter and read which XCD they run on
 // from the hardware, so a team forms from whichever workgroups of that XCD free up first.
 // Every job's team fits the XCD's resident workgroups, so the lowest job with unclaimed
