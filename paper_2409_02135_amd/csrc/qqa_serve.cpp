@@ -217,21 +217,27 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
   std::vector<int32_t> xcd_jobs(kResidentXcds + 1, 0), xcd_places(kResidentXcds, 0);
   double longest_xcd_updates = 0.0;
   if (resident) {
-    // longest processing time first: each instance, largest team x updates first, goes to
-    // the XCD with the least work so far; an XCD claims its jobs in that order
+    // longest processing time first: each instance, largest cost first, goes to the XCD with
+    // the least cost so far
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     auto team_of = [&](int i) { return (inst[i].g->n + rows_per_wg - 1) / rows_per_wg; };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-      return (int64_t)team_of(a) * inst[a].K > (int64_t)team_of(b) * inst[b].K;
-    });
+    // cost of a job: its team x updates x (8 + mean degree), the row work of an update
+    // growing with the gathers (measured on the 512-instance batch: 268-270 against 279 us per
+    // update with team x updates alone; 8 was the best of 0.5, 3, 8 and 16, the others no
+    // better than team x updates)
+    auto cost_of = [&](int i) {
+      const double deg = inst[i].g->n ? (double)inst[i].g->nnz / inst[i].g->n : 0.0;
+      return (double)team_of(i) * inst[i].K * (8.0 + deg);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost_of(a) > cost_of(b); });
     std::vector<std::vector<int>> per(kResidentXcds);
-    std::vector<int64_t> load(kResidentXcds, 0);
+    std::vector<double> load(kResidentXcds, 0);
     std::vector<double> updates(kResidentXcds, 0.0);
     for (int i : order) {
       const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
       per[x].push_back(i);
-      load[x] += (int64_t)team_of(i) * inst[i].K;
+      load[x] += cost_of(i);
       updates[x] += inst[i].K;
     }
     // within an XCD: first-fit decreasing into rounds whose teams fill the XCD's workgroups,
