@@ -205,6 +205,8 @@ void release_request_buffers(qqa_ctx* c, Request* r) {
   c->hpool.put(r->table_host, r->table_bytes);
   r->table_dev = nullptr;
   r->table_host = nullptr;
+  c->dpool.put(r->noise_dev, r->noise_bytes);
+  r->noise_dev = nullptr;
   r->P[0] = r->P[1] = r->m = r->v = nullptr;
   r->acc = nullptr;
   r->out_dev = r->out_host = nullptr;
@@ -330,6 +332,14 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
       r->table_bytes = (size_t)steps * sizeof(float4);
       r->footprint += r->table_bytes;
     }
+    // one workgroup cannot hide the generator's dependent chain behind other rows: its
+    // normals are formed beforehand by the whole GPU, a bounded chunk of updates at a time
+    if (r->engine == kEngineLdsBlock && steps > 0) {
+      const size_t per_update = (size_t)g.n * (r->shape.stride / 4) * sizeof(float4);
+      r->noise_chunk = (int)std::min<size_t>((size_t)steps, std::max<size_t>(1, kNoiseTableMaxBytes / per_update));
+      r->noise_bytes = per_update * (size_t)r->noise_chunk;
+      r->footprint += r->noise_bytes;
+    }
   }
   if (!budget_fits(c, r->footprint))
     return set_err(c, QQA_E_NOMEM, "HBM budget held by earlier requests; poll them first");
@@ -339,6 +349,7 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
   if (r->table_bytes) {
     e = c->dpool.get(r->table_bytes, (void**)&r->table_dev);
     if (e == hipSuccess) e = c->hpool.get(r->table_bytes, (void**)&r->table_host);
+    if (e == hipSuccess && r->noise_bytes) e = c->dpool.get(r->noise_bytes, (void**)&r->noise_dev);
     if (e != hipSuccess) {
       release_request_buffers(c, r.get());
       return set_err(c, QQA_E_NOMEM, std::string("request buffers: ") + hipGetErrorString(e));
@@ -436,7 +447,20 @@ static int submit_plain(qqa_ctx* c, int64_t gid, bool temp, qqa_problem problem,
     pp.t0 = 0;
     pp.t1 = steps;
     pp.bar = bar;
-    if (e == hipSuccess) e = launch_persistent(pp, r->engine, r->rows_per_group, r->grid, c->stream);
+    if (r->engine == kEngineLdsBlock) {
+      // LDS block: each chunk's normals, then the chunk's updates (P and the moments pass
+      // through global memory between chunks)
+      pp.noise = r->noise_dev;
+      pp.nnz = g.nnz <= INT32_MAX ? (int32_t)g.nnz : 0;
+      for (int t0 = 0; t0 < steps && e == hipSuccess; t0 += r->noise_chunk) {
+        pp.t0 = t0;
+        pp.t1 = std::min(steps, t0 + r->noise_chunk);
+        e = launch_noise_table(p, pp.t0, pp.t1, r->noise_dev, c->stream);
+        if (e == hipSuccess) e = launch_persistent(pp, r->engine, r->rows_per_group, r->grid, c->stream);
+      }
+    } else if (e == hipSuccess) {
+      e = launch_persistent(pp, r->engine, r->rows_per_group, r->grid, c->stream);
+    }
   }
   if (e == hipSuccess) e = hipEventRecord(r->ev[2], c->stream);
   if (e == hipSuccess) e = enqueue_finish(c, r.get(), g, r->P[steps & 1]);

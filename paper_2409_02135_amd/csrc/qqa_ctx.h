@@ -54,6 +54,9 @@ struct Request {
   float4* table_dev = nullptr;  // per-update scalars (persistent engines)
   float4* table_host = nullptr;
   size_t table_bytes = 0;
+  float4* noise_dev = nullptr;  // LDS-block engine: the normals of a chunk of updates
+  size_t noise_bytes = 0;
+  int noise_chunk = 0;          // updates per noise table
   size_t footprint = 0;
   float* P[2] = {nullptr, nullptr};
   float* m = nullptr;

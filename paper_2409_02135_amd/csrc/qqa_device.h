@@ -288,13 +288,14 @@ __device__ __forceinline__ void row_stats(const StepParams& a, const int gl, con
 // replicas 0).  Quad indices are local to `a` (whose pointers and S may describe a slice of
 // the row); q_off is the slice's first quad in the row, for the noise counter.  SUMS: the
 // kernel may run max clique (per-replica sums in a.colsum); kernels that never do leave it
-// out and keep their registers.
-template <int LPR, int QPL, bool FULL, bool SUMS = true>
+// out and keep their registers.  NOISE_IN: the quads' normals come in xi_in (formed
+// beforehand with the same generator and counters), not from the generator here.
+template <int LPR, int QPL, bool FULL, bool SUMS = true, bool NOISE_IN = false>
 __device__ __forceinline__ void finish_elems(const StepParams& a, const int row, const int gl, const int q_off,
                                              const float mu, const float cg, const float4 (&p)[QPL],
                                              const float4 (&mm)[QPL], const float4 (&vv)[QPL],
                                              const float4 (&acc)[QPL], float4 (&po)[QPL], float4 (&mo)[QPL],
-                                             float4 (&vo)[QPL]) {
+                                             float4 (&vo)[QPL], const float4* xi_in = nullptr) {
   const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
   const bool maxcut = a.problem == kMAXCUT;
   const bool clique = SUMS && a.problem == kMAXCLIQUE;
@@ -304,8 +305,9 @@ __device__ __forceinline__ void finish_elems(const StepParams& a, const int row,
     const int q = gl + LPR * k;
     po[k] = mo[k] = vo[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (!FULL && q >= nq) continue;
-    const float4 xi =
-        normals4(philox4x32_10((uint32_t)row, (uint32_t)(q_off + q), a.k, kStreamNoise, a.key0, a.key1));
+    const float4 xi = NOISE_IN ? xi_in[k]
+                               : normals4(philox4x32_10((uint32_t)row, (uint32_t)(q_off + q), a.k, kStreamNoise,
+                                                        a.key0, a.key1));
     float4 T = make_float4(0.f, 0.f, 0.f, 0.f);  // max clique: 1^T p of the quad's replicas
     if (clique) {
 #pragma unroll

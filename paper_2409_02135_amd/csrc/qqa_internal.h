@@ -143,7 +143,16 @@ struct PersistParams {
   const float4* table;          // per update t: {ce, inv_bc1, inv_bc2, 0}
   int32_t t0, t1;
   unsigned* bar;                // [0] arrivals (zero before the launch), [1] abort flag
+  // LDS engine (required there): the normals of update t, row i, quad q at
+  // noise[((t - t0) n + i) nq + q] (nq = stride / 4), formed by launch_noise_table
+  const float4* noise;
+  int32_t nnz;                  // LDS engine: the graph's edges (CSR entries); 0 keeps them in global memory
 };
+// The normals of updates [t0, t1) of every row and replica quad of `a`, as the update
+// kernels generate them (the same counters and keys), into xi ((t1 - t0) n nq quads).
+hipError_t launch_noise_table(const StepParams& a, int t0, int t1, float4* xi, hipStream_t st);
+// the largest noise table an LDS-block solve holds (longer solves run in chunks of updates)
+constexpr size_t kNoiseTableMaxBytes = (size_t)64 << 20;
 enum PersistEngine {
   kEngineStream = 0, kEnginePersistent = 1, kEngineLdsBlock = 2, kEngineBatch = 3, kEngineSliced = 4, kEngineCompact = 5,
   kEngineResident = 6

@@ -104,34 +104,113 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistParams pp) {
 }
 
 // Single workgroup: P ping-pongs between two LDS buffers, updates are separated by
-// workgroup barriers only.
-template <int LPR, int RPG>
+// workgroup barriers only.  The update loop reads no global memory but the per-update
+// scalars and the normals, which the whole GPU forms beforehand (pp.noise): one workgroup
+// cannot hide the generator's dependent chain behind other rows.  Both are loaded one
+// update ahead (the loop is unrolled by two, so the loaded registers are never copied, which
+// would wait for the loads), and the rows' CSR ranges stay in registers.  CSR: where the
+// column indices (1), and the weights (2), sit: 0 global memory, else copied into LDS after
+// the two P buffers, so that the gathers wait on LDS alone.
+template <int LPR, int RPG, int CSR>
+__device__ __forceinline__ void lds_update(const StepParams& a0, float4* lds, const int* lcol,
+                                           const float* lw, const int in_q, const int out_q, const int t,
+                                           const float4 tb, const int row0, const int gl, const int (&e0)[RPG],
+                                           const int (&e1)[RPG], float4 (&p)[RPG][1], float4 (&mm)[RPG][1],
+                                           float4 (&vv)[RPG][1], const float4 (&xi)[RPG]) {
+  StepParams a = a0;
+  a.ce = tb.x;
+  a.inv_bc1 = tb.y;
+  a.inv_bc2 = tb.z;
+  a.k = (uint32_t)t + 1u;
+  const bool maxcut = a.problem == kMAXCUT;
+  // a lane group past the last row updates that row too (its registers hold it) and stores
+  // nothing: no branch around the update, across which the loads in flight would be waited for
+#pragma unroll
+  for (int r = 0; r < RPG; ++r) {
+    const int row = min(row0 + r, a.n - 1);
+    // the coupling sum in CSR order, as gather_coupling forms it
+    float4 acc[1] = {make_float4(0.f, 0.f, 0.f, 0.f)};
+    for (int e = e0[r]; e < e1[r]; ++e) {
+      const int j = CSR ? lcol[e] : a.col[e];
+      const float w = CSR == 2 ? lw[e] : (CSR == 0 && a.w ? a.w[e] : 1.f);
+      const float4 x = lds[in_q + j * LPR + gl];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float xc = comp(x, c);
+        const float f = maxcut ? 2.f * xc - 1.f : xc;
+        set_comp(acc[0], c, fmaf(w, f, comp(acc[0], c)));
+      }
+    }
+    float mu, cg;
+    row_stats<LPR, 1, true>(a, gl, p[r], mu, cg);
+    float4 po[1], mo[1], vo[1];
+    const float4 x[1] = {xi[r]};
+    finish_elems<LPR, 1, true, false, true>(a, row, gl, 0, mu, cg, p[r], mm[r], vv[r], acc, po, mo, vo, x);
+    if (row0 + r < a.n) lds[out_q + row * LPR + gl] = po[0];
+    p[r][0] = po[0];
+    mm[r][0] = mo[0];
+    vv[r][0] = vo[0];
+  }
+}
+
+template <int LPR, int RPG, int CSR>
 __global__ __launch_bounds__(kLdsBlock) void lds_block_kernel(PersistParams pp) {
   extern __shared__ float4 lds[];
-  StepParams a = pp.a;
-  const size_t words = (size_t)a.n * a.stride;
-  float* sP[2] = {reinterpret_cast<float*>(lds), reinterpret_cast<float*>(lds) + words};
-  const float4* src = reinterpret_cast<const float4*>(pp.P[pp.t0 & 1]);
-  float4* dst0 = reinterpret_cast<float4*>(sP[pp.t0 & 1]);
-  for (size_t i = threadIdx.x; i < words / 4; i += kLdsBlock) dst0[i] = src[i];
-  __syncthreads();
+  const StepParams a = pp.a;
+  const int n = a.n;
+  const int quads = n * LPR;  // float4 per P buffer (S = 4 LPR, so the stride is 4 LPR)
+  const int t0 = pp.t0, t1 = pp.t1;
+  {
+    const float4* src = reinterpret_cast<const float4*>(pp.P[t0 & 1]);
+    const int b = (t0 & 1) * quads;
+    for (int i = threadIdx.x; i < quads; i += kLdsBlock) lds[b + i] = src[i];
+  }
+  int* lcol = reinterpret_cast<int*>(lds + 2 * quads);
+  float* lw = reinterpret_cast<float*>(lcol + pp.nnz);
+  if (CSR)
+    for (int i = threadIdx.x; i < pp.nnz; i += kLdsBlock) {
+      lcol[i] = a.col[i];
+      if (CSR == 2) lw[i] = a.w[i];
+    }
   const int group = (int)threadIdx.x / LPR;
   const int gl = threadIdx.x & (LPR - 1);
   const int row0 = group * RPG;
   float4 p[RPG][1], mm[RPG][1], vv[RPG][1];
+  int e0[RPG], e1[RPG];
 #pragma unroll
-  for (int r = 0; r < RPG; ++r)
-    if (row0 + r < a.n) load_row<LPR, 1, true>(a, sP[pp.t0 & 1], row0 + r, gl, p[r], mm[r], vv[r]);
-  for (int t = pp.t0; t < pp.t1; ++t) {
-    a.P_in = sP[t & 1];
-    a.P_out = sP[(t + 1) & 1];
-    per_update(pp, t, &a);
-    run_rows<LPR, RPG, false>(a, row0, gl, p, mm, vv);
-    __syncthreads();
+  for (int r = 0; r < RPG; ++r) {
+    const int row = min(row0 + r, n - 1);
+    load_row<LPR, 1, true>(a, pp.P[t0 & 1], row, gl, p[r], mm[r], vv[r]);
+    e0[r] = a.row_ptr[row];
+    e1[r] = a.row_ptr[row + 1];
   }
-  const float4* fin = reinterpret_cast<const float4*>(sP[pp.t1 & 1]);
-  float4* out = reinterpret_cast<float4*>(pp.P[pp.t1 & 1]);
-  for (size_t i = threadIdx.x; i < words / 4; i += kLdsBlock) out[i] = fin[i];
+  __syncthreads();
+  // normals of update t, row i, lane quad gl at noise[((t - t0) n + i) LPR + gl]
+  const size_t per_update = (size_t)n * LPR;
+  float4 xa[RPG], xb[RPG], ta, tb;
+  auto fetch = [&](int t, float4(&x)[RPG], float4& tv) {
+    t = min(t, t1 - 1);
+    tv = pp.table[t];
+#pragma unroll
+    for (int r = 0; r < RPG; ++r)
+      x[r] = pp.noise[(size_t)(t - t0) * per_update + (size_t)min(row0 + r, n - 1) * LPR + gl];
+  };
+  if (t0 < t1) fetch(t0, xa, ta);
+  for (int t = t0; t < t1;) {
+    fetch(t + 1, xb, tb);
+    lds_update<LPR, RPG, CSR>(a, lds, lcol, lw, (t & 1) * quads, ((t + 1) & 1) * quads, t, ta, row0, gl, e0,
+                              e1, p, mm, vv, xa);
+    __syncthreads();
+    if (++t >= t1) break;
+    fetch(t + 1, xa, ta);
+    lds_update<LPR, RPG, CSR>(a, lds, lcol, lw, (t & 1) * quads, ((t + 1) & 1) * quads, t, tb, row0, gl, e0,
+                              e1, p, mm, vv, xb);
+    __syncthreads();
+    ++t;
+  }
+  float4* out = reinterpret_cast<float4*>(pp.P[t1 & 1]);
+  const int b = (t1 & 1) * quads;
+  for (int i = threadIdx.x; i < quads; i += kLdsBlock) out[i] = lds[b + i];
   store_moments<LPR, RPG>(a, row0, gl, mm, vv);
 }
 
@@ -205,19 +284,32 @@ static hipError_t launch_coop(const PersistParams& pp, int grid, hipStream_t st)
 hipError_t launch_persistent(const PersistParams& pp, int engine, int rpg, int grid, hipStream_t st) {
   const ReplicaShape r = replica_shape(pp.a.S, pp.a.lanes_per_row);
   if (engine == kEngineLdsBlock) {
-    const size_t lds = 2 * (size_t)pp.a.n * pp.a.stride * sizeof(float);
-#define X(L)                                                                                                \
-  if (r.lpr == L) {                                                                                         \
-    switch (rpg) {                                                                                          \
-      case 1: hipLaunchKernelGGL((lds_block_kernel<L, 1>), dim3(1), dim3(kLdsBlock), lds, st, pp); break; \
-      case 2: hipLaunchKernelGGL((lds_block_kernel<L, 2>), dim3(1), dim3(kLdsBlock), lds, st, pp); break; \
-      case 4: hipLaunchKernelGGL((lds_block_kernel<L, 4>), dim3(1), dim3(kLdsBlock), lds, st, pp); break; \
-      default: return hipErrorInvalidValue;                                                                 \
-    }                                                                                                       \
-    return hipGetLastError();                                                                               \
+    if (!pp.noise || pp.t0 > pp.t1) return hipErrorInvalidValue;
+    if (pp.t0 == pp.t1) return hipSuccess;
+    // the CSR arrays join P in LDS when they fit
+    const size_t lds_p = 2 * (size_t)pp.a.n * pp.a.stride * sizeof(float);
+    const size_t lds_csr = (size_t)pp.nnz * sizeof(int32_t) * (pp.a.w ? 2 : 1);
+    const int csr = pp.nnz > 0 && lds_p + lds_csr <= lds_limit() ? (pp.a.w ? 2 : 1) : 0;
+    const size_t lds = lds_p + (csr ? lds_csr : 0);
+#define K(L, R, C) hipLaunchKernelGGL((lds_block_kernel<L, R, C>), dim3(1), dim3(kLdsBlock), lds, st, pp)
+#define RPG_CASE(L, N)              \
+  case N:                           \
+    if (csr == 2) K(L, N, 2);       \
+    else if (csr == 1) K(L, N, 1);  \
+    else K(L, N, 0);                \
+    break;
+#define X(L)                                  \
+  if (r.lpr == L) {                           \
+    switch (rpg) {                            \
+      RPG_CASE(L, 1) RPG_CASE(L, 2) RPG_CASE(L, 4) \
+      default: return hipErrorInvalidValue;   \
+    }                                         \
+    return hipGetLastError();                 \
   }
     QQA_LDS_LAYOUTS(X)
 #undef X
+#undef RPG_CASE
+#undef K
     return hipErrorInvalidValue;
   }
   if (engine == kEnginePersistent) {
@@ -227,6 +319,28 @@ hipError_t launch_persistent(const PersistParams& pp, int engine, int rpg, int g
 #undef X
   }
   return hipErrorInvalidValue;
+}
+
+// The noise table of an LDS-block solve: thread i forms the normals of quad q of row `row`
+// at update t, exactly as finish_elems does in the update kernels.
+__global__ __launch_bounds__(kBlock) void noise_table_kernel(StepParams a, int t0, int t1, int nq,
+                                                             float4* __restrict__ xi) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long per = (long long)a.n * nq;
+  if (i >= per * (t1 - t0)) return;
+  const int dt = (int)(i / per);
+  const long long rq = i - (long long)dt * per;
+  const int row = (int)(rq / nq), q = (int)(rq - (long long)row * nq);
+  xi[i] = normals4(philox4x32_10((uint32_t)row, (uint32_t)q, (uint32_t)(t0 + dt) + 1u, kStreamNoise, a.key0, a.key1));
+}
+
+hipError_t launch_noise_table(const StepParams& a, int t0, int t1, float4* xi, hipStream_t st) {
+  if (a.n <= 0 || t1 <= t0) return hipSuccess;
+  const int nq = a.stride / 4;
+  const long long total = (long long)a.n * nq * (t1 - t0);
+  hipLaunchKernelGGL(noise_table_kernel, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a, t0,
+                     t1, nq, xi);
+  return hipGetLastError();
 }
 
 }  // namespace qqa

@@ -598,12 +598,30 @@ int qqa_dev_run(const qqa_dev_graph* g, qqa_problem problem, const qqa_schedule*
   pp.t0 = t0;
   pp.t1 = t1;
   pp.bar = d_bar;
-  hipError_t e = launch_persistent(pp, use, rpg, grid, st);
+  hipError_t e = hipSuccess;
+  float4* d_noise = nullptr;
+  if (use == kEngineLdsBlock && t1 > t0) {
+    // the normals of a bounded chunk of updates at a time, then the chunk's updates
+    const size_t per_update = (size_t)g->n * (p.stride / 4) * sizeof(float4);
+    const int chunk = (int)std::min<size_t>((size_t)(t1 - t0), std::max<size_t>(1, kNoiseTableMaxBytes / per_update));
+    pp.nnz = g->nnz;
+    e = hipMallocAsync((void**)&d_noise, per_update * (size_t)chunk, st);
+    pp.noise = d_noise;
+    for (int c0 = t0; c0 < t1 && e == hipSuccess; c0 += chunk) {
+      pp.t0 = c0;
+      pp.t1 = std::min(t1, c0 + chunk);
+      e = launch_noise_table(p, pp.t0, pp.t1, d_noise, st);
+      if (e == hipSuccess) e = launch_persistent(pp, use, rpg, grid, st);
+    }
+  } else if (use != kEngineLdsBlock) {
+    e = launch_persistent(pp, use, rpg, grid, st);
+  }
   unsigned bar[2] = {0, 0};
   hipError_t e2 = hipMemcpyAsync(bar, d_bar, sizeof(bar), hipMemcpyDeviceToHost, st);
   hipError_t e3 = hipStreamSynchronize(st);
   (void)hipFreeAsync(d_table, st);
   (void)hipFreeAsync(d_bar, st);
+  if (d_noise) (void)hipFreeAsync(d_noise, st);
   DEV_CHECK(e);
   DEV_CHECK(e2);
   DEV_CHECK(e3);

@@ -120,3 +120,24 @@ def test_context_engine_policy_same_results():
         if engine != "sliced":
             assert np.array_equal(a["obj"], b["obj"]) and np.array_equal(a["best_x"], b["best_x"])
     ctx.close()
+
+
+def test_context_lds_block_noise_chunks_same_results():
+    # A context solve on the LDS engine forms its normals ahead of the updates, a bounded
+    # table of updates at a time: 1,024 rows at S = 8 (64 KiB of P in LDS) hold 2,048
+    # updates per table, so 4,500 updates run in three chunks (P and the moments pass
+    # through global memory between them).  The results equal those of the streaming
+    # engine, which draws the same normals.  At S = 64 P exceeds the LDS: streaming.
+    q = qqa()
+    ctx = q.Context(0)
+    g = qi.erdos_renyi(1024, 4.0, 7)
+    gid = ctx.upload(g, "mis")
+    for S, K in [(8, 4500), (64, 40)]:
+        ctx.set_engine("auto")
+        a = ctx.poll(ctx.solve_resident(gid, g["n"], "mis", S, K, 11))
+        ctx.set_engine("stream")
+        b = ctx.poll(ctx.solve_resident(gid, g["n"], "mis", S, K, 11))
+        assert a["engine"] == ("lds_block" if S == 8 else "stream") and b["engine"] == "stream"
+        assert np.array_equal(a["obj"], b["obj"]) and np.array_equal(a["best_x"], b["best_x"])
+    ctx.release(gid)
+    ctx.close()
