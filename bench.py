@@ -26,6 +26,8 @@ import numpy as np  # noqa: E402
 METRIC = "replica-var updates/s (N·S·steps/s); p50/p99 solve latency, batched vs plain"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 compute units at 2.4 GHz
+COMPUTE_UNITS = 256
 
 WORKLOADS = {
     # name: (family, n, degree parameter, problem, S, updates)
@@ -79,6 +81,17 @@ def algorithmic_bytes_per_update_launch(n, nnz, S, stride, weighted):
     state = 24 * n * S
     csr = 4 * (n + 1) + 4 * nnz + (4 * nnz if weighted else 0)
     return state + csr
+
+
+def update_flops(n, nnz, S, maxcut, alpha_e):
+    """Arithmetic of one update (AdamW): per replica-variable the statistics (4 flops), the
+    penalty, entropy and communication gradient (11 + the alpha_e - 2 multiplies of the
+    entropy power; 2 fewer for max-cut, whose gradient is the coupling itself), the moments
+    and step (16), noise and clamp (4); per CSR entry and replica a multiply-add (2 more
+    for max-cut's 2 p - 1)."""
+    per_elem = 31 + (alpha_e - 2) + (0 if maxcut else 2)
+    per_edge = 4 if maxcut else 2
+    return n * S * per_elem + nnz * S * per_edge
 
 
 def dense_coupling_us(q, W, n, S, problem, launches=20):
@@ -445,11 +458,19 @@ def measure(q, workload, steps, warmup, lanes_arg=-1, engine="auto", updates=0):
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                     "avg_launch_us": step_us, "algorithmic_bytes_per_launch": abytes,
                     "sampled_kernel_us": float(np.mean([r["kernel_us"] for r in results]))}
+    elif engine_ran == "lds_block":
+        # one workgroup on one compute unit runs the whole solve: bound by that unit's vector
+        # ALUs (the instance is far too small for memory bandwidth to matter)
+        flops = update_flops(n, nnz, S, problem == "maxcut", q.qqa_schedule_default(problem, n).entropy_alpha)
+        peak = FP32_VECTOR_PEAK_TFLOPS * 1e3 / COMPUTE_UNITS
+        achieved = flops / (step_us * 1e-6) / 1e9
+        roofline = {"bound": "alu", "kernel": "lds_block_kernel", "scope": "one compute unit",
+                    "achieved": achieved, "peak": peak, "unit": "GFLOP/s", "frac": achieved / peak,
+                    "traffic": None, "avg_update_us": step_us, "algorithmic_flops_per_update": flops}
     else:
         abytes = algorithmic_bytes_per_update_launch(n, nnz, S, stride, problem == "maxcut")
         achieved = abytes / (step_us * 1e-6) / 1e9
-        kernel = {"sliced": "slice_step_kernel", "compact": "compact_step_kernel", "lds_block": "lds_block_kernel",
-                  "persistent": "persistent_kernel"}.get(engine_ran, "step_kernel")
+        kernel = {"sliced": "slice_step_kernel", "compact": "compact_step_kernel", "persistent": "persistent_kernel"}.get(engine_ran, "step_kernel")
         record = {"slice_step_kernel": ("slice_step_traffic.json", SLICE_SOURCES),
                   "compact_step_kernel": ("compact_step_traffic.json", COMPACT_SOURCES),
                   "step_kernel": ("step_kernel_traffic.json", DEVICE_SOURCES)}.get(kernel)
