@@ -40,6 +40,9 @@ def run(q, g, problem, S, t0, t1, K, seed, engine, state=None):
 CASES = [
     ("rrg256_S16_mis", lambda: qi.random_regular(256, 3, 0), "mis", 16, "lds_block"),
     ("er300_S32_maxcut", lambda: qi.pm1_weights(qi.erdos_renyi(300, 6.0, 1), 2), "maxcut", 32, "lds_block"),
+    # 30,946 column indices (121 KB) do not fit in LDS beside P (128 KB): the gathers read them
+    # from global memory (degrees at most 49: no split rows)
+    ("er1024_d30_S16_mis", lambda: qi.erdos_renyi(1024, 30.0, 4), "mis", 16, "lds_block"),
     ("er3000_S64_mis", lambda: qi.erdos_renyi(3000, 5.0, 2), "mis", 64, "persistent"),
     ("er6000_S128_maxcut", lambda: qi.pm1_weights(qi.erdos_renyi(6000, 5.0, 3), 4), "maxcut", 128, "persistent"),
     ("er20000_S256_mis", lambda: qi.erdos_renyi(20000, 5.0, 0), "mis", 256, "persistent"),
