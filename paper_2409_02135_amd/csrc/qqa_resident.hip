@@ -22,6 +22,8 @@
 //
 // Rows go through the same device functions as the streaming kernels (qqa_device.h), with
 // edges summed in CSR order, so every instance ends with the bits of the same solve alone.
+// The work of an update that needs no neighbour row (the normals, mu and sigma) is done
+// while the team barrier waits, for the next update.
 #include "qqa_device.h"
 
 namespace qqa {
@@ -41,14 +43,19 @@ __device__ __forceinline__ int xcd_id() {
 // the other members poll.  No counter is shared, so the arrivals do not serialise on one
 // address, and a poll reads one line except at the first member.  (Measured on the
 // 512-instance batch: 8% less time per update than every member polling every flag.)
-__device__ __forceinline__ bool team_sync(const ResidentParams& rp, unsigned* flags, const int member, const int team,
-                                          const unsigned epoch) {
-  __shared__ int ok;
+// Split in two: team_arrive publishes this member's arrival, team_wait waits for the release;
+// between them the member's waves do the work of the next update that needs no other row.
+__device__ __forceinline__ void team_arrive(unsigned* flags, const int member, const unsigned epoch) {
   __builtin_amdgcn_s_waitcnt(0);  // this wave's row stores have reached L2
   __syncthreads();
+  if (threadIdx.x == 0 && member != 0)
+    __hip_atomic_store(flags + (size_t)member * kFlagWords, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool team_wait(const ResidentParams& rp, unsigned* flags, const int member, const int team,
+                                          const unsigned epoch) {
+  __shared__ int ok;
   if (threadIdx.x < 64) {
-    if (threadIdx.x == 0 && member != 0)
-      __hip_atomic_store(flags + (size_t)member * kFlagWords, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const long long t0 = wall_clock64();
     int good = 1;
     for (;;) {
@@ -143,6 +150,25 @@ __device__ __forceinline__ bool run_job(const ResidentParams& rp, const int job,
       p[r][0] = load_shared(sd.P[0] + (size_t)(row0 + r * kGroups) * a.stride + 4 * gl);  // as the gathers read it
     }
   unsigned* flags = rp.flags + (size_t)jb.flag_base * kFlagWords;
+  // The parts of the coming update that need only the lane's own rows: each row quad's
+  // normals (the generator and counters of finish_elems) and each row's mu and sigma term
+  // (row_stats of the new p), formed while the member waits for its team.  They wait in LDS,
+  // each thread's own slots: in registers they would spill (measured on the 512-instance
+  // batch, us per update: 270 as part of the update, 263 with the normals in registers and
+  // 4 registers spilled, 346 with the statistics too and 16 spilled, 255-258 in LDS).
+  __shared__ float4 xi_lds[RPG][kBlock];
+  __shared__ float2 st_lds[RPG][kBlock];
+  auto normals = [&](const uint32_t k) {
+#pragma unroll
+    for (int r = 0; r < RPG; ++r) {
+      xi_lds[r][threadIdx.x] =
+          normals4(philox4x32_10((uint32_t)(row0 + r * kGroups), (uint32_t)gl, k, kStreamNoise, a.key0, a.key1));
+      float mu, cg;
+      row_stats<LPR, 1, true>(a, gl, p[r], mu, cg);
+      st_lds[r][threadIdx.x] = make_float2(mu, cg);
+    }
+  };
+  normals(1u);
   for (int t = 0; t < sd.K; ++t) {
     a.P_in = sd.P[t & 1];
     a.P_out = sd.P[(t + 1) & 1];
@@ -157,13 +183,17 @@ __device__ __forceinline__ bool run_job(const ResidentParams& rp, const int job,
       if (row >= a.n) continue;  // whole lane groups
       float4 acc[1], po[1], mo[1], vo[1];
       acc[0] = res_coupling<LPR, QUADS>(a, row, gl);
-      finish_row<LPR, 1, true, false>(a, row, gl, p[r], mm[r], vv[r], acc, po, mo, vo);  // never max clique
+      const float2 st = st_lds[r][threadIdx.x];
+      const float4 x[1] = {xi_lds[r][threadIdx.x]};
+      finish_elems<LPR, 1, true, false, true>(a, row, gl, 0, st.x, st.y, p[r], mm[r], vv[r], acc, po, mo, vo, x);
       store_row<LPR, 1, true, false>(a, a.P_out, row, gl, po, mo, vo, false);
       p[r][0] = po[0];
       mm[r][0] = mo[0];
       vv[r][0] = vo[0];
     }
-    if (!team_sync(rp, flags, member, jb.team, (unsigned)t + 1u)) return false;
+    team_arrive(flags, member, (unsigned)t + 1u);
+    if (t + 1 < sd.K) normals((uint32_t)t + 2u);
+    if (!team_wait(rp, flags, member, jb.team, (unsigned)t + 1u)) return false;
   }
   if (member == 0 && threadIdx.x == 0) atomicAdd(rp.done, 1u);
   return true;
