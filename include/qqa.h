@@ -151,7 +151,9 @@ typedef struct {
 /* How the update loop runs.  STREAM: one launch per update, state streamed through
  * memory.  PERSISTENT: one cooperative launch for all updates; every lane group keeps
  * its rows' p, m, v in registers and only the new p goes to memory, updates separated by
- * a grid barrier.  LDS_BLOCK: one workgroup with P in LDS (small instances).  BATCH: a
+ * a grid barrier.  LDS_BLOCK: one workgroup with P (and the CSR when it fits) in LDS
+ * (small instances); its normals are formed by the whole GPU before each chunk of updates,
+ * into a device table of at most 64 MiB that the request's footprint includes.  BATCH: a
  * ragged multi-instance launch (qqa_solve_batch, the server).  SLICED: streaming, with
  * the replica axis cut into 8 slices, slice s of every row updated on XCD s so that the
  * neighbour gathers of an XCD stay within 1/8 of P (its L2); one launch per update, which
