@@ -67,6 +67,15 @@ __device__ __forceinline__ void set_comp(float4& v, int c, float x) {
   if (c == 0) v.x = x; else if (c == 1) v.y = x; else if (c == 2) v.z = x; else v.w = x;
 }
 
+// z^E for a compile-time E: the multiplications of ipow_odd(z, E), in its order
+template <int E>
+__device__ __forceinline__ float ipow_fixed(float z) {
+  float r = z;
+#pragma unroll
+  for (int i = 1; i < E; ++i) r *= z;
+  return r;
+}
+
 __device__ __forceinline__ float ipow_odd(float z, int e) {
   float r = z;
   for (int i = 1; i < e; ++i) r *= z;
@@ -207,7 +216,7 @@ __device__ __forceinline__ RowMeta row_meta(const StepParams& a, const int row) 
 // a.coupling instead (a compile-time choice: a runtime branch around that load would join
 // the sparse path and make it wait for every load in flight).
 template <int LPR, int QPL, bool FULL, bool COHERENT = false, bool SPLIT = true, bool DENSE = false,
-          int QUADS = kGatherQuads>
+          int QUADS = kGatherQuads, int SPEC = 0>
 __device__ __forceinline__ void row_coupling(const StepParams& a, const int row, const RowMeta& rm, const int gl,
                                              float4 (&acc)[QPL]) {
   const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
@@ -247,7 +256,8 @@ __device__ __forceinline__ void row_coupling(const StepParams& a, const int row,
       }
     }
   } else {
-    gather_coupling<LPR, QPL, FULL, COHERENT, SPLIT, QUADS>(a, rm.e0, rm.e1, gl, nq, a.problem == kMAXCUT, acc);
+    const bool maxcut = SPEC ? spec_problem(SPEC) == kMAXCUT : a.problem == kMAXCUT;
+    gather_coupling<LPR, QPL, FULL, COHERENT, SPLIT, QUADS>(a, rm.e0, rm.e1, gl, nq, maxcut, acc);
   }
 }
 
@@ -290,16 +300,16 @@ __device__ __forceinline__ void row_stats(const StepParams& a, const int gl, con
 // kernel may run max clique (per-replica sums in a.colsum); kernels that never do leave it
 // out and keep their registers.  NOISE_IN: the quads' normals come in xi_in (formed
 // beforehand with the same generator and counters), not from the generator here.
-template <int LPR, int QPL, bool FULL, bool SUMS = true, bool NOISE_IN = false>
+template <int LPR, int QPL, bool FULL, bool SUMS = true, bool NOISE_IN = false, int SPEC = 0>
 __device__ __forceinline__ void finish_elems(const StepParams& a, const int row, const int gl, const int q_off,
                                              const float mu, const float cg, const float4 (&p)[QPL],
                                              const float4 (&mm)[QPL], const float4 (&vv)[QPL],
                                              const float4 (&acc)[QPL], float4 (&po)[QPL], float4 (&mo)[QPL],
                                              float4 (&vo)[QPL], const float4* xi_in = nullptr) {
   const int nq = FULL ? LPR * QPL : (a.S + 3) >> 2;
-  const bool maxcut = a.problem == kMAXCUT;
-  const bool clique = SUMS && a.problem == kMAXCLIQUE;
-  const bool adam = a.rule == kADAMW;
+  const bool maxcut = SPEC ? spec_problem(SPEC) == kMAXCUT : a.problem == kMAXCUT;
+  const bool clique = SUMS && (SPEC ? spec_problem(SPEC) == kMAXCLIQUE : a.problem == kMAXCLIQUE);
+  const bool adam = SPEC ? spec_rule(SPEC) == kADAMW : a.rule == kADAMW;
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int q = gl + LPR * k;
@@ -320,7 +330,7 @@ __device__ __forceinline__ void finish_elems(const StepParams& a, const int row,
       // MIS: -1 + lambda C;  max-cut: C;  max clique: -1 + lambda (1^T p - 1/2 - C)
       const float gf = maxcut ? C : fmaf(a.lambda, clique ? (comp(T, c) - 0.5f) - C : C, -1.f);
       const float z = 2.f * pc - 1.f;
-      const float ge = a.ce * ipow_odd(z, a.alpha_e - 1);
+      const float ge = a.ce * (SPEC ? ipow_fixed<spec_alpha(SPEC) - 1>(z) : ipow_odd(z, a.alpha_e - 1));
       const float gc = cg * (pc - mu);
       const float g = gf + ge + gc;
       float pn, mn = 0.f, vn = 0.f;

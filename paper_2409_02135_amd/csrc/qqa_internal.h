@@ -11,6 +11,19 @@ namespace qqa {
 
 enum : int32_t { kMIS = 0, kMAXCUT = 1, kMAXCLIQUE = 2, kCOLORING = 3 };
 enum : int32_t { kADAMW = 0, kLANGEVIN = 1 };
+
+// Facts about a solve that a kernel may fix at compile time, so that the uniform branches and
+// selects on them leave its instruction stream: 0 (none: every fact read from the
+// parameters) or spec_of(problem, step rule, entropy alpha).  A fixed fact changes no
+// arithmetic: the same operations run in the same order.
+constexpr int spec_of(int problem, int rule, int alpha_e) { return 1 + problem + 4 * rule + 8 * alpha_e; }
+constexpr int spec_problem(int s) { return (s - 1) % 4; }
+constexpr int spec_rule(int s) { return ((s - 1) / 4) % 2; }
+constexpr int spec_alpha(int s) { return (s - 1) / 8; }
+// the fixed facts of a default schedule (AdamW, entropy alpha 4) of MIS or max-cut, else 0
+constexpr int default_spec(int problem, int rule, int alpha_e) {
+  return rule == kADAMW && alpha_e == 4 && (problem == kMIS || problem == kMAXCUT) ? spec_of(problem, rule, alpha_e) : 0;
+}
 enum : uint32_t { kStreamInit = 0, kStreamNoise = 1 };
 
 constexpr int kMaxReplicas = 4096;
@@ -191,13 +204,14 @@ struct ResidentParams {
   unsigned* done;             // [1] jobs completed (zero before the launch)
   long long timeout_ticks;    // longest wait at one barrier, in wall-clock ticks
 };
-// Co-resident workgroups of the kernel for a (lanes per row, rows per lane group) shape,
+// Co-resident workgroups of the kernel for a (lanes per row, rows per lane group) shape and
+// the batch's fixed facts (spec: default_spec of its instances' common schedule, else 0),
 // 0 if the shape is not built.
-int resident_workgroups(int lanes_per_row, int rows_per_group);
+int resident_workgroups(int lanes_per_row, int rows_per_group, int spec);
 // The launch, then a kernel that writes each slot's outcome into its result record's
 // barrier word [1] (0: every job ran to completion).
-hipError_t launch_resident(const ResidentParams& rp, int lanes_per_row, int rows_per_group, int grid, int nslots,
-                           int njobs, hipStream_t st);
+hipError_t launch_resident(const ResidentParams& rp, int lanes_per_row, int rows_per_group, int spec, int grid,
+                           int nslots, int njobs, hipStream_t st);
 
 // Dense coupling product C = W f(P) on the matrix cores (W symmetric n x n, P and C
 // n x stride; f(p) = 2p - 1 for max-cut, p for MIS).

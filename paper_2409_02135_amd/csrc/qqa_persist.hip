@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(PersistParams pp) {
 // would wait for the loads), and the rows' CSR ranges stay in registers.  CSR: where the
 // column indices (1), and the weights (2), sit: 0 global memory, else copied into LDS after
 // the two P buffers, so that the gathers wait on LDS alone.
-template <int LPR, int RPG, int CSR>
+template <int LPR, int RPG, int CSR, int SPEC>
 __device__ __forceinline__ void lds_update(const StepParams& a0, float4* lds, const int* lcol,
                                            const float* lw, const int in_q, const int out_q, const int t,
                                            const float4 tb, const int row0, const int gl, const int (&e0)[RPG],
@@ -122,7 +122,7 @@ __device__ __forceinline__ void lds_update(const StepParams& a0, float4* lds, co
   a.inv_bc1 = tb.y;
   a.inv_bc2 = tb.z;
   a.k = (uint32_t)t + 1u;
-  const bool maxcut = a.problem == kMAXCUT;
+  const bool maxcut = SPEC ? spec_problem(SPEC) == kMAXCUT : a.problem == kMAXCUT;
   // a lane group past the last row updates that row too (its registers hold it) and stores
   // nothing: no branch around the update, across which the loads in flight would be waited for
 #pragma unroll
@@ -145,7 +145,7 @@ __device__ __forceinline__ void lds_update(const StepParams& a0, float4* lds, co
     row_stats<LPR, 1, true>(a, gl, p[r], mu, cg);
     float4 po[1], mo[1], vo[1];
     const float4 x[1] = {xi[r]};
-    finish_elems<LPR, 1, true, false, true>(a, row, gl, 0, mu, cg, p[r], mm[r], vv[r], acc, po, mo, vo, x);
+    finish_elems<LPR, 1, true, false, true, SPEC>(a, row, gl, 0, mu, cg, p[r], mm[r], vv[r], acc, po, mo, vo, x);
     if (row0 + r < a.n) lds[out_q + row * LPR + gl] = po[0];
     p[r][0] = po[0];
     mm[r][0] = mo[0];
@@ -153,7 +153,7 @@ __device__ __forceinline__ void lds_update(const StepParams& a0, float4* lds, co
   }
 }
 
-template <int LPR, int RPG, int CSR>
+template <int LPR, int RPG, int CSR, int SPEC>
 __global__ __launch_bounds__(kLdsBlock) void lds_block_kernel(PersistParams pp) {
   extern __shared__ float4 lds[];
   const StepParams a = pp.a;
@@ -198,12 +198,12 @@ __global__ __launch_bounds__(kLdsBlock) void lds_block_kernel(PersistParams pp) 
   if (t0 < t1) fetch(t0, xa, ta);
   for (int t = t0; t < t1;) {
     fetch(t + 1, xb, tb);
-    lds_update<LPR, RPG, CSR>(a, lds, lcol, lw, (t & 1) * quads, ((t + 1) & 1) * quads, t, ta, row0, gl, e0,
+    lds_update<LPR, RPG, CSR, SPEC>(a, lds, lcol, lw, (t & 1) * quads, ((t + 1) & 1) * quads, t, ta, row0, gl, e0,
                               e1, p, mm, vv, xa);
     __syncthreads();
     if (++t >= t1) break;
     fetch(t + 1, xa, ta);
-    lds_update<LPR, RPG, CSR>(a, lds, lcol, lw, (t & 1) * quads, ((t + 1) & 1) * quads, t, tb, row0, gl, e0,
+    lds_update<LPR, RPG, CSR, SPEC>(a, lds, lcol, lw, (t & 1) * quads, ((t + 1) & 1) * quads, t, tb, row0, gl, e0,
                               e1, p, mm, vv, xb);
     __syncthreads();
     ++t;
@@ -291,12 +291,18 @@ hipError_t launch_persistent(const PersistParams& pp, int engine, int rpg, int g
     const size_t lds_csr = (size_t)pp.nnz * sizeof(int32_t) * (pp.a.w ? 2 : 1);
     const int csr = pp.nnz > 0 && lds_p + lds_csr <= lds_limit() ? (pp.a.w ? 2 : 1) : 0;
     const size_t lds = lds_p + (csr ? lds_csr : 0);
-#define K(L, R, C) hipLaunchKernelGGL((lds_block_kernel<L, R, C>), dim3(1), dim3(kLdsBlock), lds, st, pp)
-#define RPG_CASE(L, N)              \
-  case N:                           \
-    if (csr == 2) K(L, N, 2);       \
-    else if (csr == 1) K(L, N, 1);  \
-    else K(L, N, 0);                \
+    // the default schedule (AdamW, entropy alpha 4) of unweighted MIS and weighted max-cut with
+    // the CSR in LDS runs with those facts fixed at compile time
+    const bool dflt = pp.a.rule == kADAMW && pp.a.alpha_e == 4;
+    const bool mis1 = dflt && csr == 1 && pp.a.problem == kMIS, cut2 = dflt && csr == 2 && pp.a.problem == kMAXCUT;
+#define K(L, R, C, SP) hipLaunchKernelGGL((lds_block_kernel<L, R, C, SP>), dim3(1), dim3(kLdsBlock), lds, st, pp)
+#define RPG_CASE(L, N)                                          \
+  case N:                                                       \
+    if (cut2) K(L, N, 2, spec_of(kMAXCUT, kADAMW, 4));          \
+    else if (mis1) K(L, N, 1, spec_of(kMIS, kADAMW, 4));        \
+    else if (csr == 2) K(L, N, 2, 0);                           \
+    else if (csr == 1) K(L, N, 1, 0);                           \
+    else K(L, N, 0, 0);                                         \
     break;
 #define X(L)                                  \
   if (r.lpr == L) {                           \

@@ -97,11 +97,11 @@ __device__ __forceinline__ float4 load_shared(const float* p) {
 
 // The coupling sum of one row for lane gl's quad (one quad per lane, every quad valid), U
 // edges per batch: the same operations in the same edge order as the streaming kernels'.
-template <int LPR, int U>
+template <int LPR, int U, int SPEC>
 __device__ __forceinline__ float4 res_coupling(const StepParams& a, const int row, const int gl) {
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   const int e_begin = a.row_ptr[row], e_end = a.row_ptr[row + 1];
-  const bool maxcut = a.problem == kMAXCUT;
+  const bool maxcut = SPEC ? spec_problem(SPEC) == kMAXCUT : a.problem == kMAXCUT;
   for (int e0 = e_begin; e0 < e_end; e0 += U) {
     const float* src[U];
     float w[U];
@@ -130,7 +130,7 @@ __device__ __forceinline__ float4 res_coupling(const StepParams& a, const int ro
   return acc;
 }
 
-template <int LPR, int RPG, int QUADS>
+template <int LPR, int RPG, int QUADS, int SPEC>
 __device__ __forceinline__ bool run_job(const ResidentParams& rp, const int job, const int member) {
   constexpr int kGroups = kBlock / LPR;
   const ResidentJob jb = rp.jobs[job];
@@ -182,10 +182,11 @@ __device__ __forceinline__ bool run_job(const ResidentParams& rp, const int job,
       const int row = row0 + r * kGroups;
       if (row >= a.n) continue;  // whole lane groups
       float4 acc[1], po[1], mo[1], vo[1];
-      acc[0] = res_coupling<LPR, QUADS>(a, row, gl);
+      acc[0] = res_coupling<LPR, QUADS, SPEC>(a, row, gl);
       const float2 st = st_lds[r][threadIdx.x];
       const float4 x[1] = {xi_lds[r][threadIdx.x]};
-      finish_elems<LPR, 1, true, false, true>(a, row, gl, 0, st.x, st.y, p[r], mm[r], vv[r], acc, po, mo, vo, x);
+      finish_elems<LPR, 1, true, false, true, SPEC>(a, row, gl, 0, st.x, st.y, p[r], mm[r], vv[r], acc, po, mo, vo,
+                                                    x);
       store_row<LPR, 1, true, false>(a, a.P_out, row, gl, po, mo, vo, false);
       p[r][0] = po[0];
       mm[r][0] = mo[0];
@@ -201,7 +202,7 @@ __device__ __forceinline__ bool run_job(const ResidentParams& rp, const int job,
 
 }  // namespace
 
-template <int LPR, int RPG, int QUADS>
+template <int LPR, int RPG, int QUADS, int SPEC>
 // Held to four waves per SIMD (at most 128 registers, none spilled at three rows per lane
 // group).  Measured on the 512-instance batch, µs per update: three rows at four waves 298-305,
 // four rows at three waves 333-335, two rows at five waves (spilling) 326, five rows at three
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     const int job = __builtin_amdgcn_readfirstlane(sh_job), member = __builtin_amdgcn_readfirstlane(sh_member);
     __syncthreads();  // every wave has read the claim before thread 0 makes the next
     if (job < 0) return;
-    if (!run_job<LPR, RPG, QUADS>(rp, job, member)) return;
+    if (!run_job<LPR, RPG, QUADS, SPEC>(rp, job, member)) return;
   }
 }
 
@@ -255,33 +256,42 @@ __global__ void resident_flags_kernel(ResidentParams rp, int nslots, int njobs) 
   X(4, 3) X(8, 3) X(16, 3) X(32, 3) X(64, 3)
 constexpr int kResidentQuads = 4;
 
-int resident_workgroups(int lanes_per_row, int rows_per_group) {
+// SPEC: a batch whose instances all run the default schedule of one problem (AdamW, entropy
+// alpha 4, MIS or max-cut) runs the kernel with those facts fixed (default_spec), else 0
+#define QQA_RESIDENT_SPEC(L, R, F)                                    \
+  F(L, R, 0) F(L, R, spec_of(kMIS, kADAMW, 4)) F(L, R, spec_of(kMAXCUT, kADAMW, 4))
+
+int resident_workgroups(int lanes_per_row, int rows_per_group, int spec) {
   int dev = 0, per_cu = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-#define X(L, R)                                                                                              \
-  if (lanes_per_row == L && rows_per_group == R) {                                                           \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_kernel<L, R, kResidentQuads>, kBlock,    \
-                                                     0) != hipSuccess)                                          \
-      return 0;                                                                                              \
-    return per_cu * prop.multiProcessorCount;                                                                \
+#define F(L, R, SP)                                                                                             \
+  if (lanes_per_row == L && rows_per_group == R && spec == SP) {                                                \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_kernel<L, R, kResidentQuads, SP>, kBlock, \
+                                                     0) != hipSuccess)                                             \
+      return 0;                                                                                                 \
+    return per_cu * prop.multiProcessorCount;                                                                   \
   }
+#define X(L, R) QQA_RESIDENT_SPEC(L, R, F)
   QQA_RESIDENT_SHAPES(X)
 #undef X
+#undef F
   return 0;
 }
 
-hipError_t launch_resident(const ResidentParams& rp, int lanes_per_row, int rows_per_group, int grid, int nslots,
-                           int njobs, hipStream_t st) {
+hipError_t launch_resident(const ResidentParams& rp, int lanes_per_row, int rows_per_group, int spec, int grid,
+                           int nslots, int njobs, hipStream_t st) {
   ResidentParams arg = rp;
   void* args[] = {&arg};
   hipError_t e = hipErrorInvalidValue;
-#define X(L, R)                                                                                                 \
-  if (lanes_per_row == L && rows_per_group == R)                                                                \
-    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(resident_kernel<L, R, kResidentQuads>), dim3(grid), \
-                                   dim3(kBlock), args, 0, st);
+#define F(L, R, SP)                                                                                              \
+  if (lanes_per_row == L && rows_per_group == R && spec == SP)                                                   \
+    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(resident_kernel<L, R, kResidentQuads, SP>),       \
+                                   dim3(grid), dim3(kBlock), args, 0, st);
+#define X(L, R) QQA_RESIDENT_SPEC(L, R, F)
   QQA_RESIDENT_SHAPES(X)
 #undef X
+#undef F
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(resident_flags_kernel, dim3((nslots + kBlock - 1) / kBlock), dim3(kBlock), 0, st, rp, nslots,
                      njobs);

@@ -199,6 +199,10 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     resident = pref == c->batch_resident.end() || pref->second != 0;
   }
   int res_lanes = 0, res_grid = 0, rows_per_wg = 0;
+  // the facts every instance shares (the default schedule of one problem), fixed in the kernel
+  int res_spec = default_spec(inst[0].problem, inst[0].s.rule, inst[0].s.entropy_alpha);
+  for (int i = 1; i < count && res_spec; ++i)
+    if (default_spec(inst[i].problem, inst[i].s.rule, inst[i].s.entropy_alpha) != res_spec) res_spec = 0;
   if (resident) {
     const LayoutClass& lc = classes.begin()->second;
     const ReplicaShape sh = replica_shape(lc.S, lc.lanes);
@@ -206,7 +210,7 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     resident = sh.qpl == 1 && lc.S == 4 * sh.lpr;
     for (int i = 0; i < count && resident; ++i) resident = inst[i].g->nchunks == 0;
     if (resident) {
-      res_grid = resident_workgroups(res_lanes, kResidentRowsPerGroup);
+      res_grid = resident_workgroups(res_lanes, kResidentRowsPerGroup, res_spec);
       rows_per_wg = (kBlock / res_lanes) * kResidentRowsPerGroup;
       int max_team = 0;
       for (int i = 0; i < count; ++i) max_team = std::max(max_team, (inst[i].g->n + rows_per_wg - 1) / rows_per_wg);
@@ -387,7 +391,7 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     // 100 us for every update those jobs run
     rp.timeout_ticks = (long long)((10.0 + 1e-4 * longest_xcd_updates) * 1e3 * khz);
     e = hipEventRecord(run->ev[1], st);
-    if (e == hipSuccess) e = launch_resident(rp, res_lanes, kResidentRowsPerGroup, res_grid, count, count, st);
+    if (e == hipSuccess) e = launch_resident(rp, res_lanes, kResidentRowsPerGroup, res_spec, res_grid, count, count, st);
   } else if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (!resident && e == hipSuccess) {
     hipError_t ce = hipSuccess;

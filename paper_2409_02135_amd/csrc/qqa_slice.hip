@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void slice_stats_kernel(StepParams a, float
 // One quad per lane: eight waves per SIMD, the register budget held to 64 (at most 62 used, no
 // spills; 80 unbounded, six waves).  Measured: 30.3 against 30.7 us at S = 256, 29.2 against
 // 30.4 at S = 512.  Two quads per lane would spill under that budget and keep theirs.
-template <int LS, int QS, bool FULL, bool SUMS, int NSL, bool SM>
+template <int LS, int QS, bool FULL, bool SUMS, int NSL, bool SM, int SPEC = 0>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QS == 1 ? 8 : 1, 8))) void slice_step_kernel(StepParams a, const float2* __restrict__ part_in,
                                                             float2* __restrict__ part_out, int nchunks) {
   int slice, rb;
@@ -196,8 +196,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QS == 1 
   // ER n = 20,000, mean degree 5).  Wider slices keep 4-quad batches, which measured best there.
   // The batch size changes no result: the edge order of the sums is the same.
   constexpr int kSliceGatherQuads = LS <= 8 ? 6 : 4;
-  row_coupling<LS, QS, FULL, false, false, false, kSliceGatherQuads>(b, row, rm, gl, acc);
-  finish_elems<LS, QS, FULL, SUMS>(b, row, gl, q0, mu, cg, p, mm, vv, acc, po, mo, vo);
+  row_coupling<LS, QS, FULL, false, false, false, kSliceGatherQuads, SPEC>(b, row, rm, gl, acc);
+  finish_elems<LS, QS, FULL, SUMS, false, SPEC>(b, row, gl, q0, mu, cg, p, mm, vv, acc, po, mo, vo);
   store_row<LS, QS, FULL>(b, b.P_out, row, gl, po, mo, vo, true);
   const float2 pt = slice_partial<LS, QS, FULL>(b, gl, po);
   if (gl == 0) part_out[(size_t)slice * a.n + row] = pt;
@@ -280,7 +280,15 @@ static void launch_slice_t(const StepParams& p, const float2* part_in, float2* p
   const bool sums = p.problem == kMAXCLIQUE;
 #define L(FU, SU, M) \
   hipLaunchKernelGGL((slice_step_kernel<LS, QS, FU, SU, NSL, M>), grid, block, 0, st, p, part_in, part_out, nchunks)
-  if (sm) L(true, false, true);
+#define LSPEC(PROBLEM)                                                                                       \
+  hipLaunchKernelGGL((slice_step_kernel<LS, QS, true, false, NSL, true, spec_of(PROBLEM, kADAMW, 4)>), grid, block, 0, \
+                     st, p, part_in, part_out, nchunks)
+  // the default schedules (AdamW, entropy alpha 4) of MIS and max-cut with slice-major state
+  // run with those facts fixed at compile time
+  const bool spec = p.rule == kADAMW && p.alpha_e == 4;
+  if (sm && spec && p.problem == kMIS) LSPEC(kMIS);
+  else if (sm && spec && p.problem == kMAXCUT) LSPEC(kMAXCUT);
+  else if (sm) L(true, false, true);
   else if (sums) {
     if (full) L(true, true, false);
     else L(false, true, false);
@@ -288,6 +296,7 @@ static void launch_slice_t(const StepParams& p, const float2* part_in, float2* p
     if (full) L(true, false, false);
     else L(false, false, false);
   }
+#undef LSPEC
 #undef L
 }
 
