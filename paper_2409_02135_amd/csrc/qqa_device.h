@@ -353,14 +353,14 @@ __device__ __forceinline__ void finish_elems(const StepParams& a, const int row,
 }
 
 // Statistics, then the element update, of one whole row.
-template <int LPR, int QPL, bool FULL, bool SUMS = true>
+template <int LPR, int QPL, bool FULL, bool SUMS = true, int SPEC = 0>
 __device__ __forceinline__ void finish_row(const StepParams& a, const int row, const int gl, const float4 (&p)[QPL],
                                            const float4 (&mm)[QPL], const float4 (&vv)[QPL],
                                            const float4 (&acc)[QPL], float4 (&po)[QPL], float4 (&mo)[QPL],
                                            float4 (&vo)[QPL]) {
   float mu, cg;
   row_stats<LPR, QPL, FULL>(a, gl, p, mu, cg);
-  finish_elems<LPR, QPL, FULL, SUMS>(a, row, gl, 0, mu, cg, p, mm, vv, acc, po, mo, vo);
+  finish_elems<LPR, QPL, FULL, SUMS, false, SPEC>(a, row, gl, 0, mu, cg, p, mm, vv, acc, po, mo, vo);
 }
 
 template <int LPR, int QPL, bool FULL, bool COHERENT = false>
@@ -384,13 +384,13 @@ __device__ __forceinline__ void store_row(const StepParams& a, float* P, const i
 
 // One update of one row, state streamed from and to memory.  DENSE: the coupling product
 // was computed beforehand into a.coupling.
-template <int LPR, int QPL, bool FULL, bool SUMS = true, bool DENSE = false>
+template <int LPR, int QPL, bool FULL, bool SUMS = true, bool DENSE = false, int SPEC = 0>
 __device__ __forceinline__ void update_row(const StepParams& a, const int row, const int gl) {
   float4 p[QPL], mm[QPL], vv[QPL], acc[QPL], po[QPL], mo[QPL], vo[QPL];
   const RowMeta rm = DENSE ? RowMeta{0, 0, -1} : row_meta(a, row);
   load_row<LPR, QPL, FULL>(a, a.P_in, row, gl, p, mm, vv);  // issued before the gathers
-  row_coupling<LPR, QPL, FULL, false, true, DENSE>(a, row, rm, gl, acc);
-  finish_row<LPR, QPL, FULL, SUMS>(a, row, gl, p, mm, vv, acc, po, mo, vo);
+  row_coupling<LPR, QPL, FULL, false, true, DENSE, kGatherQuads, SPEC>(a, row, rm, gl, acc);
+  finish_row<LPR, QPL, FULL, SUMS, SPEC>(a, row, gl, p, mm, vv, acc, po, mo, vo);
   store_row<LPR, QPL, FULL>(a, a.P_out, row, gl, po, mo, vo, true);
 }
 

@@ -132,10 +132,11 @@ struct HubItem {
   int32_t chunk;
 };
 
-// Launches over a work list of one replica layout.  `clock` is a device int.
+// Launches over a work list of one replica layout.  `clock` is a device int.  spec: the
+// default_spec every slot of the step's list shares, else 0.
 hipError_t launch_slot_init(const SlotDesc* slots, const WorkItem* items, int nitems, int lanes_per_row, hipStream_t st);
 hipError_t launch_slot_step(const SlotDesc* slots, const WorkItem* items, int nitems, int S, int lanes_per_row,
-                            const int32_t* clock, int t_arg, hipStream_t st);
+                            int spec, const int32_t* clock, int t_arg, hipStream_t st);
 hipError_t launch_slot_hubs(const SlotDesc* slots, const HubItem* items, int nitems, int S, int lanes_per_row,
                             const int32_t* clock, int t_arg, hipStream_t st);
 hipError_t launch_clock_advance(int32_t* clock, int by, hipStream_t st);

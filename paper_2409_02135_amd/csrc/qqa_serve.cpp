@@ -116,6 +116,7 @@ namespace {
 // One replica layout class of a batch: its slots' row blocks and split-row chunks.
 struct LayoutClass {
   int S = 0, lanes = 0;
+  int spec = -1;  // the default_spec its instances share (0: none), -1 before the first
   std::vector<WorkItem> items;
   std::vector<HubItem> hubs;
   std::vector<int32_t> ids;
@@ -187,6 +188,8 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
     LayoutClass& lc = classes[{inst[i].S, inst[i].lanes}];
     lc.S = inst[i].S;
     lc.lanes = inst[i].lanes;
+    const int sp = default_spec(inst[i].problem, inst[i].s.rule, inst[i].s.entropy_alpha);
+    lc.spec = lc.spec < 0 || lc.spec == sp ? sp : 0;
     append_items(i, *inst[i].g, inst[i].lanes, &lc.items, &lc.hubs);
     lc.ids.push_back(i);
   }
@@ -403,7 +406,7 @@ int qqa_solve_batch(qqa_ctx* c, int32_t count, const qqa_graph_id* graphs, const
                                 lc.lanes, d_clock, r, st);
         if (ce == hipSuccess)
           ce = launch_slot_step(d_slots, reinterpret_cast<const WorkItem*>(A + lc.off_items), (int)lc.items.size(),
-                                lc.S, lc.lanes, d_clock, r, st);
+                                lc.S, lc.lanes, std::max(lc.spec, 0), d_clock, r, st);
       }
     if (ce == hipSuccess) ce = launch_clock_advance(d_clock, R, st);
     e = hipStreamEndCapture(st, &run->graph);

@@ -340,6 +340,9 @@ void Server::run() {
     // work lists of the active slots, by replica layout class; slots finishing this round
     std::map<std::pair<int, int>, std::pair<size_t, size_t>> item_range, hub_range, eval_range, init_range;
     std::map<std::pair<int, int>, std::pair<size_t, size_t>> id_range;
+    // the schedule facts every running slot of a class shares (default_spec), else 0; a class
+    // is not split by them (more, smaller launches per update measured slower)
+    std::map<std::pair<int, int>, int> class_spec;
     items.clear();
     hubs.clear();
     eval_items.clear();
@@ -368,6 +371,9 @@ void Server::run() {
       if (running < kRunElements) {
         running += (int64_t)r->n * qqa_replica_stride(r->S);
         cls_slots[{r->S, r->lanes}].push_back(kv.second);
+        const int sp = default_spec(r->problem, r->sched.rule, r->sched.entropy_alpha);
+        auto cs = class_spec.emplace(std::make_pair(r->S, r->lanes), sp).first;
+        if (cs->second != sp) cs->second = 0;
         running_slots.push_back(kv.second);
       } else {  // waits this round: its next update index is unchanged at the next boundary
         r->start += kRound;
@@ -470,7 +476,7 @@ void Server::run() {
                                clock + r, st);
         if (e == hipSuccess)
           e = launch_slot_step(d_slots, L_items + kv.second.first, (int)kv.second.second, kv.first.first,
-                               kv.first.second, d_zero, clock + r, st);
+                               kv.first.second, class_spec[kv.first], d_zero, clock + r, st);
       }
     clock += kRound;
     // evaluate and copy back the slots that finished

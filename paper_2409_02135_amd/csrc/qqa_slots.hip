@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void slot_init_kernel(const SlotDesc* slots
   }
 }
 
-template <int LPR, int QPL, bool FULL>
+template <int LPR, int QPL, bool FULL, int SPEC>
 __global__ __launch_bounds__(kBlock) void slot_step_kernel(const SlotDesc* slots, const WorkItem* items, int nitems,
                                                            const int32_t* clock, int t_arg) {
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void slot_step_kernel(const SlotDesc* slots
     int row = w.row0 + (int)threadIdx.x / LPR;
     if (LPR == 64) row = __builtin_amdgcn_readfirstlane(row);
     if (row >= a.n) continue;  // whole lane groups
-    update_row<LPR, QPL, FULL, false>(a, row, threadIdx.x & (LPR - 1));  // batches never run max clique
+    update_row<LPR, QPL, FULL, false, false, SPEC>(a, row, threadIdx.x & (LPR - 1));  // never max clique
   }
 }
 
@@ -246,22 +246,24 @@ hipError_t launch_slot_init(const SlotDesc* slots, const WorkItem* items, int ni
 }
 
 hipError_t launch_slot_step(const SlotDesc* slots, const WorkItem* items, int nitems, int S, int lanes_per_row,
-                            const int32_t* clock, int t_arg, hipStream_t st) {
+                            int spec, const int32_t* clock, int t_arg, hipStream_t st) {
   if (nitems == 0) return hipSuccess;
   const ReplicaShape r = replica_shape(S, lanes_per_row);
   const bool full = S == 4 * r.lpr * r.qpl;
-#define X(LL, QQ)                                                                                              \
-  if (r.lpr == LL && r.qpl == QQ) {                                                                            \
-    if (full)                                                                                                  \
-      hipLaunchKernelGGL((slot_step_kernel<LL, QQ, true>), dim3(slot_grid(nitems)), dim3(kBlock), 0, st, slots, \
-                         items, nitems, clock, t_arg);                                                         \
-    else                                                                                                       \
-      hipLaunchKernelGGL((slot_step_kernel<LL, QQ, false>), dim3(slot_grid(nitems)), dim3(kBlock), 0, st,      \
-                         slots, items, nitems, clock, t_arg);                                                  \
-    return hipGetLastError();                                                                                  \
+#define K(LL, QQ, FU, SP) \
+  hipLaunchKernelGGL((slot_step_kernel<LL, QQ, FU, SP>), dim3(slot_grid(nitems)), dim3(kBlock), 0, st, slots, items, \
+                     nitems, clock, t_arg)
+#define X(LL, QQ)                                                             \
+  if (r.lpr == LL && r.qpl == QQ) {                                           \
+    if (full && spec == spec_of(kMIS, kADAMW, 4)) K(LL, QQ, true, spec_of(kMIS, kADAMW, 4));          \
+    else if (full && spec == spec_of(kMAXCUT, kADAMW, 4)) K(LL, QQ, true, spec_of(kMAXCUT, kADAMW, 4)); \
+    else if (full) K(LL, QQ, true, 0);                                        \
+    else K(LL, QQ, false, 0);                                                 \
+    return hipGetLastError();                                                 \
   }
   QQA_SLOT_LAYOUTS(X)
 #undef X
+#undef K
   return hipErrorInvalidValue;
 }
 
