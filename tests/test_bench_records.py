@@ -46,3 +46,14 @@ def test_algorithmic_bytes():
     n, nnz, S = 20000, 100560, 256
     assert bench.algorithmic_bytes_per_update_launch(n, nnz, S, S, False) == 24 * n * S + 4 * (n + 1) + 4 * nnz
     assert bench.algorithmic_bytes_per_update_launch(n, nnz, S, S, True) == 24 * n * S + 4 * (n + 1) + 8 * nnz
+
+
+def test_default_line_records_are_current():
+    # the counter records the default bench line reports were taken with the kernel sources
+    # in the tree (a kernel change leaves its traffic unmeasured until the counters are retaken)
+    for name, sources, workload in [
+            ("slice_step_traffic.json", bench.SLICE_SOURCES, "mis_er_n20000_d5_S256_K3000"),
+            ("slice_step_traffic.json", bench.SLICE_SOURCES, "maxcut_ba_n100000_m4_pm1_S128_K3000"),
+            ("dense_tile128_kernel_traffic.json", bench.DENSE_SOURCES, "maxcut_dense_n4096_gauss_S256_K3000"),
+            ("resident_traffic.json", bench.RESIDENT_SOURCES, bench.BATCH_WORKLOAD)]:
+        assert bench.traffic_from_profiles(name, sources, workload) is not None, (name, workload)
