@@ -400,7 +400,9 @@ int qqa_dev_step(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule
  * as a context would) on caller buffers: P0 and P1 ping-pong (P[t0 & 1] holds the state
  * before update t0, P[t1 & 1] the state after), m and v updated in place.  Returns
  * QQA_E_ARG if the engine cannot run this instance, QQA_E_DEVICE if a persistent
- * launch's barrier timed out.  Synchronous for the persistent engines' abort check. */
+ * launch's barrier timed out.  Synchronous for the persistent engines' abort check.  The
+ * LDS_BLOCK engine allocates (stream-ordered) a table of the normals of at most 64 MiB for
+ * the call and frees it before returning. */
 int qqa_dev_run(const qqa_dev_graph *g, qqa_problem problem, const qqa_schedule *sched, int32_t S,
                 int32_t t0, int32_t t1, int32_t K, uint64_t seed, float *P0, float *P1, float *m, float *v,
                 int32_t engine, int32_t lanes_per_row, void *stream);
