@@ -144,3 +144,17 @@ def test_context_lds_block_noise_chunks_same_results():
         assert np.array_equal(a["obj"], b["obj"]) and np.array_equal(a["best_x"], b["best_x"])
     ctx.release(gid)
     ctx.close()
+
+
+def test_dev_run_lds_block_noise_chunks_from_mid_schedule():
+    # the per-stage entry point on the LDS engine: updates 100 .. 4,599 of a 5,000-update
+    # schedule run as two noise chunks (4,096 updates of 256 rows x 4 quads fit one 64 MiB
+    # table), starting mid-schedule: the same bits as the streaming engine
+    q = qqa()
+    g = qi.random_regular(256, 3, 0)
+    S, K, seed = 16, 5000, 8
+    a = run(q, g, "mis", S, 0, 100, K, seed, "stream")
+    b = run(q, g, "mis", S, 100, 4600, K, seed, "lds_block", state=a)
+    c = run(q, g, "mis", S, 100, 4600, K, seed, "stream", state=a)
+    for x, y in zip([b[0][0], b[1], b[2]], [c[0][0], c[1], c[2]]):
+        assert torch.equal(x, y)
